@@ -1,0 +1,274 @@
+/* glam: MI355X (gfx950) kernels for the differentiable render of anchor-decoded
+ * 3-D Gaussians, the per-iteration hot path of a Gaussian mapping backend
+ * (GLAM-SLAM, Sec. III-A and III-D of the paper).
+ *
+ * One mapping iteration renders keyframe views and differentiates a photometric loss:
+ *   glam_decode      anchor features -> Gaussians, view-conditioned MLPs (Eq. 2) with
+ *                    one MLP set per spatial partition (Eq. 6)
+ *   glam_project     3-D Gaussians -> projected 2-D Gaussians + footprint boxes
+ *   glam_bin_sort    (tile, depth) pairs, device radix sort, per-tile ranges
+ *   glam_render_fwd  front-to-back alpha compositing per 16x16 tile (Eq. 1)
+ *   glam_loss        L1 + SSIM objective (Eq. 3) and its image gradient
+ *   glam_render_bwd  reverse compositing, projection adjoint, decode adjoint
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers owned by the caller; the library never
+ *    allocates, frees or keeps them.  Scratch memory comes from a caller workspace
+ *    whose size glam_*_workspace_bytes() reports.
+ *  - "[3][n]" is structure-of-arrays: three contiguous rows of n values.  Pointers
+ *    must be 16-byte aligned.
+ *  - Calls are asynchronous on the given stream and never synchronise, so a sequence
+ *    of calls can be captured into a HIP graph.  They are reentrant; the library has no
+ *    global mutable state.
+ *  - Arguments are validated on the host before anything is launched; a rejected call
+ *    returns GLAM_ERR_INVALID_ARG (or GLAM_ERR_WORKSPACE) and launches nothing.
+ *  - Data-dependent overflow (more (tile, Gaussian) pairs than the caller's capacity)
+ *    is detected on the device: the call sets the sticky word status[0] to
+ *    GLAM_ERR_CAPACITY and writes the required pair count to status[2..3]; outputs of
+ *    that call and of later calls reading them are then undefined (no memory outside
+ *    the given buffers is touched).
+ *  - No exception crosses the ABI and nothing is printed.
+ *
+ * View table.  Several keyframe views (possibly of different partitions and
+ * resolutions) are processed by one call.  glam_views_build() derives, on the host,
+ * one glam_view_info per view (offsets of its Gaussians, pixels and tiles in the
+ * batched buffers); the caller copies that array verbatim to device memory and passes
+ * both copies in a glam_views.  Offsets are view-major:
+ *   view-Gaussians  [g_begin, g_begin + g_count) of every per-Gaussian array
+ *   pixels          [pix_begin, pix_begin + W*H) of per-pixel arrays; images are
+ *                   [3][H][W] planes starting at 3*pix_begin
+ *   tiles           [tile_begin, tile_begin + tiles_x*tiles_y), row-major per view
+ */
+#ifndef GLAM_H
+#define GLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GLAM_OK = 0,
+  GLAM_ERR_INVALID_ARG = 1,
+  GLAM_ERR_WORKSPACE = 2,
+  GLAM_ERR_CAPACITY = 3,
+  GLAM_ERR_HIP = 4,
+  GLAM_ERR_UNSUPPORTED = 5
+} glam_status;
+
+/* Human-readable name of a status (static storage). */
+const char* glam_status_string(int32_t status);
+
+/* Flags (bitwise or). */
+enum {
+  /* Gaussians are given directly (mean, log-scale, raw quaternion, opacity logit,
+     colour) instead of being decoded from anchors; every view sees the same set. */
+  GLAM_PLAIN = 1u << 0,
+  /* Opacity activation sigmoid instead of the default tanh with non-positive values
+     dropped (anchor mode); plain mode always uses sigmoid of the logit. */
+  GLAM_OPACITY_SIGMOID = 1u << 1
+};
+
+/* Pinhole camera: world->camera rotation R (row-major) and translation t, OpenCV
+   axes (x right, y down, z forward), focal lengths and principal point in pixels,
+   image size, and the spatial partition (index of the MLP set, Eq. 6) whose anchors
+   this view renders. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t partition;
+  int32_t reserved;
+} glam_camera;
+
+/* Per-view offsets into the batched buffers (filled by glam_views_build). */
+typedef struct {
+  glam_camera cam;
+  int64_t g_begin, g_count;     /* view-Gaussians                                   */
+  int64_t pix_begin;            /* pixels                                           */
+  int32_t tile_begin;           /* tiles                                            */
+  int32_t tiles_x, tiles_y;
+  int32_t anchor_begin;         /* first anchor of the view's partition (anchor mode) */
+  int32_t anchor_count;
+  int32_t reserved;
+} glam_view_info;
+
+typedef struct {
+  const glam_view_info* host;   /* [n] host memory                                 */
+  const glam_view_info* dev;    /* [n] device copy of the same bytes               */
+  int32_t n;
+  int32_t tile_w, tile_h;       /* 16 x 16 (the only size built)                   */
+  int32_t reserved;
+  int64_t n_gauss;              /* total view-Gaussians                            */
+  int64_t n_pix;                /* total pixels                                    */
+  int64_t n_tiles;              /* total tiles                                     */
+} glam_views;
+
+/* Fills info[n_views] and the totals of *views (everything except the host/dev
+   pointers).  Anchor mode: part_begin[n_parts+1] (host) delimits each partition's
+   anchors, each view gets anchor_count*K Gaussians.  Plain mode (part_begin NULL):
+   every view gets plain_G Gaussians.  Pure host function. */
+glam_status glam_views_build(const glam_camera* cams, int32_t n_views,
+                             const int32_t* part_begin, int32_t n_parts, int32_t K,
+                             int64_t plain_G, int32_t tile_w, int32_t tile_h,
+                             glam_view_info* info, glam_views* views);
+
+/* Anchors (Sec. III-A, Scaffold-GS structure): position x_a, feature f_a (F values),
+   one log-scale s_a and K offsets o_aj; the K Gaussians of anchor a sit at
+   x_a + exp(s_a) o_aj.  Anchors are grouped contiguously by partition. */
+typedef struct {
+  const float* pos;        /* [3][A]                                                */
+  const float* feat;       /* [A][F] row-major                                      */
+  const float* log_scale;  /* [A]                                                   */
+  const float* offs;       /* [3][A*K], Gaussian j of anchor a at a*K + j           */
+  int32_t A, F, K;         /* F == 32, K <= 16 are built                            */
+  int32_t hidden;          /* MLP hidden width, 32                                  */
+} glam_anchors;
+
+/* MLP sets, one per partition (Eq. 6): mlp[m][P] with P = glam_mlp_param_count(F, K,
+   hidden), three two-layer ReLU MLPs in the order opacity (K outputs), colour (3K),
+   covariance (7K: 3 scales then 4 quaternion values per Gaussian), each packed as
+   W1[hidden][F+4], b1[hidden], W2[out][hidden], b2[out].  The MLP input is
+   z = [f_a, d_ac, delta_ac] (Eq. 2): feature, unit view direction, distance. */
+int32_t glam_mlp_param_count(int32_t F, int32_t K, int32_t hidden);
+
+/* Gaussians, structure-of-arrays with row stride n.
+   Anchor mode (decoded, per view-Gaussian): mean, scale, unit quaternion (w,x,y,z),
+   opacity, colour.  Plain mode (shared by all views, n = G): mean, log-scale, raw
+   quaternion, opacity logit, colour. */
+typedef struct {
+  float* mean;     /* [3][n] */
+  float* scale;    /* [3][n] */
+  float* quat;     /* [4][n] */
+  float* opacity;  /* [n]    */
+  float* rgb;      /* [3][n] */
+  int64_t n;
+} glam_gaussians;
+
+/* Projected 2-D Gaussians, one per view-Gaussian (row stride views.n_gauss). */
+typedef struct {
+  float* uv;        /* [2][n] pixel-space centre                                    */
+  float* conic;     /* [3][n] (A, B, C) of the inverse 2-D covariance               */
+  float* depth;     /* [n]    camera-space z                                        */
+  float* ext;       /* [2][n] footprint half extents, -1 when culled                */
+  int32_t* ntiles;  /* [n]    tiles touched, 0 when culled                          */
+  float* splat;     /* [n][12] packed render record (u, v, A, B, C, opacity, r, g, b,
+                       pixel box x0|x1<<16 and y0|y1<<16 as bits, depth)            */
+} glam_projected;
+
+/* Sorted (tile, Gaussian) pairs and per-tile ranges. */
+typedef struct {
+  uint64_t* keys;   /* [capacity] sorted keys: tile << depth_bits | depth key        */
+  uint32_t* vals;   /* [capacity] sorted view-Gaussian indices                       */
+  uint32_t* ranges; /* [n_tiles][2] [start, end) into keys/vals                      */
+  int64_t capacity;
+  int32_t* status;  /* [8] device: [0] sticky status, [1] pair count (low word),
+                       [2..3] required capacity (int64), [4] depth key bits,
+                       [5] tile key bits, [6] radix passes; caller zeroes [0] once   */
+} glam_bins;
+
+/* Workspace bytes glam_bin_sort needs for this view table and pair capacity. */
+size_t glam_bin_sort_workspace_bytes(const glam_views* views, int64_t capacity);
+
+/* --- forward -------------------------------------------------------------------- */
+
+/* Eq. 2 + Eq. 6: for every view v, decode the anchors of partition cam.partition with
+   MLP set mlp[partition] (mlp holds n_parts sets; a view whose partition is outside
+   [0, n_parts) is rejected) into out (row stride views.n_gauss): mean = x_a + e^{s_a} o,
+   scale = e^{s_a} sigmoid(y), quaternion y/|y|, opacity tanh(y) (or sigmoid), colour
+   sigmoid(y).  FP32 MFMA for the MLPs. */
+glam_status glam_decode(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
+                        const glam_views* views, uint32_t flags, glam_gaussians* out,
+                        hipStream_t stream);
+
+/* Projection and footprint of every view-Gaussian.  Culls depth <= 0.2 and opacity
+   <= 1/255; Jacobian x/z, y/z clamped to 1.15x the image (beyond a 0.15-image border);
+   2-D covariance dilated by 0.3 px^2; footprint box: |x + 0.5 - u| <= ext_x with
+   ext = sqrt(2 ln(255 opacity) Sigma2D_xx) (likewise y), outside of which the
+   Gaussian's alpha is below 1/255. */
+glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, uint32_t flags,
+                         glam_projected* out, hipStream_t stream);
+
+/* Tile binning and device LSD radix sort by (global tile, depth): pairs emitted per
+   view-Gaussian in index order (row-major over its tiles), stable sort, so equal
+   depths keep index order.  ranges of empty tiles are [0, 0). */
+glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, glam_bins* bins,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Eq. 1 per pixel centre (x+0.5, y+0.5), front to back over its tile's range:
+   alpha = min(0.99, opacity exp(power)), skipped when alpha < 1/255, the walk stops
+   before an entry that would take T below 1e-4.  Writes image [3][H][W] per view,
+   final transmittance T_final and n_contrib (1 + range position of the last
+   composited entry) per pixel.  bg: [3] device (background colour, may be NULL). */
+glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins,
+                            const glam_views* views, const float* bg, float* image,
+                            float* T_final, int32_t* n_contrib, hipStream_t stream);
+
+/* Eq. 3 per view: L_v = mean |C - target| + w_ssim (1 - mean SSIM), SSIM over an 11x11
+   box window with zero padding, C1 = 0.01^2, C2 = 0.03^2.  Writes dL/dimage (same
+   layout as image) and loss[n_views] (device).  workspace: glam_loss_workspace_bytes. */
+size_t glam_loss_workspace_bytes(const glam_views* views);
+glam_status glam_loss(const glam_views* views, const float* image, const float* target,
+                      float w_ssim, float* dimage, float* loss, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
+/* --- backward ------------------------------------------------------------------- */
+
+/* Gradients.  Intermediate buffers are required (the library allocates nothing):
+   g2d [n_gauss][9] = d(u, v, A, B, C, opacity, r, g, b) of each projected Gaussian
+   (nine consecutive floats per view-Gaussian, so one wave adds all nine at once),
+   dgauss: d(mean, scale, quat, opacity, rgb) per view-Gaussian (anchor mode) or of
+   the plain parameters (plain mode: d(mean, log-scale, raw quat, logit, rgb), n = G).
+   Anchor mode outputs dfeat [A][F], doffs [3][A*K], dlog_scale [A], dmlp [M][P]. */
+typedef struct {
+  float* g2d;
+  glam_gaussians dgauss;
+  float* dfeat;
+  float* doffs;
+  float* dlog_scale;
+  float* dmlp;
+} glam_grads;
+
+/* Reverse compositing from (T_final, n_contrib): T_i recovered by division by
+   (1 - alpha_i), per-Gaussian gradients reduced across each wavefront before FP32
+   atomics.  Overwrites g2d [n_gauss][9] (zeroes it first). */
+glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins,
+                               const glam_views* views, const float* bg, const float* T_final,
+                               const int32_t* n_contrib, const float* dimage, float* g2d,
+                               hipStream_t stream);
+
+/* Projection adjoint: g2d -> dgauss (anchor mode: per view-Gaussian; plain mode:
+   summed over views into the plain parameter gradients).  Overwrites dgauss. */
+glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* proj,
+                             const glam_views* views, uint32_t flags, const float* g2d,
+                             glam_gaussians* dgauss, hipStream_t stream);
+
+/* Decode adjoint: dgauss -> dfeat, doffs, dlog_scale, dmlp, summed over the views of
+   each partition.  Overwrites them.  workspace: glam_decode_bwd_workspace_bytes. */
+size_t glam_decode_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views,
+                                       int32_t n_parts);
+glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
+                            const glam_views* views, uint32_t flags,
+                            const glam_gaussians* dgauss, float* dfeat, float* doffs,
+                            float* dlog_scale, float* dmlp, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* The whole backward: composite adjoint, projection adjoint, then (anchor mode) the
+   decode adjoint.  workspace: glam_decode_bwd_workspace_bytes (0 in plain mode). */
+glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins,
+                            const glam_views* views, const float* bg, const float* T_final,
+                            const int32_t* n_contrib, const float* dimage,
+                            const glam_gaussians* gauss, const glam_anchors* anchors,
+                            const float* mlp, int32_t n_parts, uint32_t flags,
+                            glam_grads* grads, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -100,12 +100,13 @@ void composite(int n, GetG getg, IsCand cand, const double* uv, const double* co
       if (e.alpha > kAlphaMin - 1e-6) r.amb |= ORC_AMB_ALPHA;
       continue;
     }
-    if (prev_depth >= 0.0 && std::fabs(depth[g] - prev_depth) < 1e-6 * depth[g])
-      r.amb |= ORC_AMB_DEPTH;
-    prev_depth = depth[g];
     if (std::fabs(e.alpha - kAlphaMin) < 1e-6) r.amb |= ORC_AMB_ALPHA;
     if (std::fabs(e.raw - kAlphaMax) < 1e-6) r.amb |= ORC_AMB_CLAMP;
     if (e.alpha < kAlphaMin) continue;
+    // an order flip between two entries that both take part changes the pixel
+    if (prev_depth >= 0.0 && std::fabs(depth[g] - prev_depth) < 1e-6 * depth[g])
+      r.amb |= ORC_AMB_DEPTH;
+    prev_depth = depth[g];
     const double Tn = r.T * (1.0 - e.alpha);
     if (std::fabs(Tn - kTMin) < 1e-8) r.amb |= ORC_AMB_T;
     if (Tn < kTMin) { r.n_eval = i + 1; break; }

@@ -1,0 +1,276 @@
+// C ABI of the glam library: host-side validation, view table construction, and the
+// launch sequence of every entry point.  Nothing here allocates device memory or
+// synchronises; every launch goes to the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "glam.h"
+#include "kernels.hpp"
+
+namespace glam {
+bool decode_supported(int F, int K);
+}
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+bool ok_ptr(const void* p) { return p != nullptr && aligned16(p); }
+
+bool views_ok(const glam_views* v) {
+  if (!v || !v->host || !v->dev || v->n <= 0) return false;
+  if (v->tile_w != glam::kTileEdge() || v->tile_h != glam::kTileEdge()) return false;
+  if (v->n_gauss < 0 || v->n_pix <= 0 || v->n_tiles <= 0) return false;
+  // totals must agree with the host table
+  long long g = 0, p = 0, t = 0;
+  for (int i = 0; i < v->n; ++i) {
+    const glam_view_info& vi = v->host[i];
+    if (vi.g_begin != g || vi.pix_begin != p || vi.tile_begin != t) return false;
+    if (vi.cam.width <= 0 || vi.cam.height <= 0 || vi.cam.width > 32767 || vi.cam.height > 32767) return false;
+    g += vi.g_count;
+    p += (long long)vi.cam.width * vi.cam.height;
+    t += (long long)vi.tiles_x * vi.tiles_y;
+  }
+  return g == v->n_gauss && p == v->n_pix && t == v->n_tiles && t < (1ll << 31) && g < (1ll << 32);
+}
+
+bool gauss_ok(const glam_gaussians* g, bool need) {
+  if (!g) return false;
+  if (!need) return true;
+  return ok_ptr(g->mean) && ok_ptr(g->scale) && ok_ptr(g->quat) && ok_ptr(g->opacity) && ok_ptr(g->rgb) && g->n > 0;
+}
+
+bool anchors_ok(const glam_anchors* a) {
+  return a && ok_ptr(a->pos) && ok_ptr(a->feat) && ok_ptr(a->log_scale) && ok_ptr(a->offs) && a->A > 0 &&
+         a->hidden == 32 && a->K > 0 && a->K <= 16 && (a->F == 8 || a->F == 16 || a->F == 32 || a->F == 64);
+}
+
+bool anchor_views_ok(const glam_anchors* a, const glam_views* v) {
+  // every view's partition range lies inside the anchors and carries anchor_count*K
+  // Gaussians; a partition's views form one contiguous run
+  for (int i = 0; i < v->n; ++i) {
+    const glam_view_info& vi = v->host[i];
+    if (vi.anchor_begin < 0 || vi.anchor_count < 0 || (long long)vi.anchor_begin + vi.anchor_count > a->A) return false;
+    if (vi.g_count != (long long)vi.anchor_count * a->K) return false;
+    if (vi.cam.partition < 0) return false;
+    for (int j = 0; j < i; ++j)
+      if (v->host[j].cam.partition == vi.cam.partition && v->host[i - 1].cam.partition != vi.cam.partition)
+        return false;
+  }
+  return true;
+}
+
+bool proj_ok(const glam_projected* p) {
+  return p && ok_ptr(p->uv) && ok_ptr(p->conic) && ok_ptr(p->depth) && ok_ptr(p->ext) && ok_ptr(p->ntiles) &&
+         ok_ptr(p->splat);
+}
+
+bool bins_ok(const glam_bins* b) {
+  return b && ok_ptr(b->keys) && ok_ptr(b->vals) && ok_ptr(b->ranges) && ok_ptr(b->status) && b->capacity > 0 &&
+         b->capacity < (1ll << 32);
+}
+
+int max_partition(const glam_views* v) {
+  int m = -1;
+  for (int i = 0; i < v->n; ++i) m = v->host[i].cam.partition > m ? v->host[i].cam.partition : m;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* glam_status_string(int32_t s) {
+  switch (s) {
+    case GLAM_OK: return "ok";
+    case GLAM_ERR_INVALID_ARG: return "invalid argument";
+    case GLAM_ERR_WORKSPACE: return "workspace too small";
+    case GLAM_ERR_CAPACITY: return "pair capacity exceeded";
+    case GLAM_ERR_HIP: return "HIP launch error";
+    case GLAM_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int32_t glam_mlp_param_count(int32_t F, int32_t K, int32_t hidden) {
+  if (F <= 0 || K <= 0 || hidden <= 0) return -1;
+  const int n_in = F + 4;
+  return 3 * (hidden * n_in + hidden) + (K + 3 * K + 7 * K) * (hidden + 1);
+}
+
+glam_status glam_views_build(const glam_camera* cams, int32_t n_views, const int32_t* part_begin, int32_t n_parts,
+                             int32_t K, int64_t plain_G, int32_t tile_w, int32_t tile_h, glam_view_info* info,
+                             glam_views* views) {
+  if (!cams || !info || !views || n_views <= 0) return GLAM_ERR_INVALID_ARG;
+  if (tile_w != glam::kTileEdge() || tile_h != glam::kTileEdge()) return GLAM_ERR_UNSUPPORTED;
+  if (part_begin && (n_parts <= 0 || K <= 0)) return GLAM_ERR_INVALID_ARG;
+  if (!part_begin && plain_G <= 0) return GLAM_ERR_INVALID_ARG;
+  long long g = 0, p = 0, t = 0;
+  for (int i = 0; i < n_views; ++i) {
+    const glam_camera& c = cams[i];
+    if (c.width <= 0 || c.height <= 0 || c.width > 32767 || c.height > 32767) return GLAM_ERR_INVALID_ARG;
+    if (!(c.fx > 0.f) || !(c.fy > 0.f)) return GLAM_ERR_INVALID_ARG;
+    glam_view_info& vi = info[i];
+    std::memset(&vi, 0, sizeof(vi));
+    vi.cam = c;
+    vi.tiles_x = (c.width + tile_w - 1) / tile_w;
+    vi.tiles_y = (c.height + tile_h - 1) / tile_h;
+    vi.g_begin = g;
+    vi.pix_begin = p;
+    vi.tile_begin = (int32_t)t;
+    if (part_begin) {
+      if (c.partition < 0 || c.partition >= n_parts) return GLAM_ERR_INVALID_ARG;
+      vi.anchor_begin = part_begin[c.partition];
+      vi.anchor_count = part_begin[c.partition + 1] - part_begin[c.partition];
+      if (vi.anchor_count < 0) return GLAM_ERR_INVALID_ARG;
+      vi.g_count = (long long)vi.anchor_count * K;
+    } else {
+      vi.g_count = plain_G;
+    }
+    g += vi.g_count;
+    p += (long long)c.width * c.height;
+    t += (long long)vi.tiles_x * vi.tiles_y;
+  }
+  if (t >= (1ll << 31) || g >= (1ll << 32)) return GLAM_ERR_UNSUPPORTED;
+  views->n = n_views;
+  views->tile_w = tile_w;
+  views->tile_h = tile_h;
+  views->n_gauss = g;
+  views->n_pix = p;
+  views->n_tiles = t;
+  return GLAM_OK;
+}
+
+size_t glam_bin_sort_workspace_bytes(const glam_views* views, int64_t capacity) {
+  if (!views || capacity <= 0) return 0;
+  return glam::bin_sort_workspace(*views, capacity);
+}
+
+glam_status glam_decode(const glam_anchors* anchors, const float* mlp, int32_t n_parts, const glam_views* views,
+                        uint32_t flags, glam_gaussians* out, hipStream_t stream) {
+  if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(out, true) || n_parts <= 0)
+    return GLAM_ERR_INVALID_ARG;
+  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if (!anchor_views_ok(anchors, views) || out->n != views->n_gauss || max_partition(views) >= n_parts)
+    return GLAM_ERR_INVALID_ARG;
+  if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
+  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, stream);
+}
+
+glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, uint32_t flags, glam_projected* out,
+                         hipStream_t stream) {
+  if (!views_ok(views) || !gauss_ok(gauss, true) || !proj_ok(out)) return GLAM_ERR_INVALID_ARG;
+  const bool plain = (flags & GLAM_PLAIN) != 0;
+  if (plain) {
+    for (int i = 0; i < views->n; ++i)
+      if (views->host[i].g_count != gauss->n) return GLAM_ERR_INVALID_ARG;
+  } else if (gauss->n != views->n_gauss) {
+    return GLAM_ERR_INVALID_ARG;
+  }
+  return glam::launch_project(*gauss, *views, plain, *out, stream);
+}
+
+glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, glam_bins* bins, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  if (!proj_ok(proj) || !views_ok(views) || !bins_ok(bins) || !ok_ptr(workspace)) return GLAM_ERR_INVALID_ARG;
+  if (workspace_bytes < glam::bin_sort_workspace(*views, bins->capacity)) return GLAM_ERR_WORKSPACE;
+  return glam::launch_bin_sort(*proj, *views, *bins, workspace, workspace_bytes, stream);
+}
+
+glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
+                            const float* bg, float* image, float* T_final, int32_t* n_contrib, hipStream_t stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(image) || !ok_ptr(T_final) ||
+      !ok_ptr(n_contrib) || (bg && !aligned16(bg)))
+    return GLAM_ERR_INVALID_ARG;
+  return glam::launch_render_fwd(*proj, *bins, *views, bg, image, T_final, n_contrib, stream);
+}
+
+size_t glam_loss_workspace_bytes(const glam_views* views) {
+  if (!views) return 0;
+  return glam::loss_workspace(*views);
+}
+
+glam_status glam_loss(const glam_views* views, const float* image, const float* target, float w_ssim, float* dimage,
+                      float* loss, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!views_ok(views) || !ok_ptr(image) || !ok_ptr(target) || !ok_ptr(dimage) || !ok_ptr(loss) ||
+      !ok_ptr(workspace) || !(w_ssim >= 0.f))
+    return GLAM_ERR_INVALID_ARG;
+  if (workspace_bytes < glam::loss_workspace(*views)) return GLAM_ERR_WORKSPACE;
+  return glam::launch_loss(*views, image, target, w_ssim, dimage, loss, workspace, stream);
+}
+
+glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
+                               const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
+                               float* g2d, hipStream_t stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(T_final) || !ok_ptr(n_contrib) ||
+      !ok_ptr(dimage) || !ok_ptr(g2d) || (bg && !aligned16(bg)))
+    return GLAM_ERR_INVALID_ARG;
+  return glam::launch_composite_bwd(*proj, *bins, *views, bg, T_final, n_contrib, dimage, g2d, stream);
+}
+
+glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* proj, const glam_views* views,
+                             uint32_t flags, const float* g2d, glam_gaussians* dgauss, hipStream_t stream) {
+  if (!gauss_ok(gauss, true) || !proj_ok(proj) || !views_ok(views) || !ok_ptr(g2d) || !gauss_ok(dgauss, true))
+    return GLAM_ERR_INVALID_ARG;
+  const bool plain = (flags & GLAM_PLAIN) != 0;
+  if (plain) {
+    if (dgauss->n != gauss->n) return GLAM_ERR_INVALID_ARG;
+    for (int i = 0; i < views->n; ++i)
+      if (views->host[i].g_count != gauss->n) return GLAM_ERR_INVALID_ARG;
+  } else if (gauss->n != views->n_gauss || dgauss->n != views->n_gauss) {
+    return GLAM_ERR_INVALID_ARG;
+  }
+  return glam::launch_project_bwd(*gauss, *proj, *views, plain, g2d, *dgauss, stream);
+}
+
+size_t glam_decode_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views, int32_t n_parts) {
+  if (!anchors || !views || n_parts <= 0) return 0;
+  return glam::decode_bwd_workspace(*anchors, *views, n_parts);
+}
+
+glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32_t n_parts, const glam_views* views,
+                            uint32_t flags, const glam_gaussians* dgauss, float* dfeat, float* doffs,
+                            float* dlog_scale, float* dmlp, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+  if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(dgauss, true) || !ok_ptr(dfeat) ||
+      !ok_ptr(doffs) || !ok_ptr(dlog_scale) || !ok_ptr(dmlp) || !ok_ptr(workspace) || n_parts <= 0)
+    return GLAM_ERR_INVALID_ARG;
+  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if (!anchor_views_ok(anchors, views) || dgauss->n != views->n_gauss || max_partition(views) >= n_parts)
+    return GLAM_ERR_INVALID_ARG;
+  if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
+  if (workspace_bytes < glam::decode_bwd_workspace(*anchors, *views, n_parts)) return GLAM_ERR_WORKSPACE;
+  return glam::launch_decode_bwd(*anchors, mlp, n_parts, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *dgauss, dfeat,
+                                 doffs, dlog_scale, dmlp, workspace, stream);
+}
+
+glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
+                            const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
+                            const glam_gaussians* gauss, const glam_anchors* anchors, const float* mlp,
+                            int32_t n_parts, uint32_t flags, glam_grads* grads, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+  if (!grads) return GLAM_ERR_INVALID_ARG;
+  const bool plain = (flags & GLAM_PLAIN) != 0;
+  // validate everything before the first launch
+  if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(T_final) || !ok_ptr(n_contrib) ||
+      !ok_ptr(dimage) || !ok_ptr(grads->g2d) || !gauss_ok(gauss, true) || !gauss_ok(&grads->dgauss, true))
+    return GLAM_ERR_INVALID_ARG;
+  if (!plain) {
+    if (!anchors_ok(anchors) || !ok_ptr(mlp) || !ok_ptr(grads->dfeat) || !ok_ptr(grads->doffs) ||
+        !ok_ptr(grads->dlog_scale) || !ok_ptr(grads->dmlp) || !ok_ptr(workspace) || n_parts <= 0)
+      return GLAM_ERR_INVALID_ARG;
+    if (!anchor_views_ok(anchors, views) || max_partition(views) >= n_parts) return GLAM_ERR_INVALID_ARG;
+    if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
+    if (workspace_bytes < glam::decode_bwd_workspace(*anchors, *views, n_parts)) return GLAM_ERR_WORKSPACE;
+  }
+  glam_status s = glam_composite_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, grads->g2d, stream);
+  if (s != GLAM_OK) return s;
+  s = glam_project_bwd(gauss, proj, views, flags, grads->g2d, &grads->dgauss, stream);
+  if (s != GLAM_OK || plain) return s;
+  return glam_decode_bwd(anchors, mlp, n_parts, views, flags, &grads->dgauss, grads->dfeat, grads->doffs,
+                         grads->dlog_scale, grads->dmlp, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// Tile binning and depth sort.
+//
+//  1. scan_reduce      per 2048 view-Gaussians: sum of tile counts, max depth bits
+//  2. scan_plan        one block: exclusive scan of the block sums, pair count P,
+//                      capacity check, lossless key width (tile bits + depth bits) and
+//                      the number of 8-bit radix passes
+//  3. duplicate        per view-Gaussian: its pairs, key = tile << dbits | depth key,
+//                      value = view-Gaussian index, in index order (row-major tiles)
+//  4. radix passes     LSD, reduce-then-scan (no inter-block waiting): upsweep digit
+//                      histogram per block, per-digit scan across blocks, downsweep
+//                      scatter with a stable in-block rank from wave ballots
+//  5. ranges           [start, end) of every tile
+//
+// Every kernel reads P and the key layout from the device-side plan, so the whole
+// sequence runs without a host round trip (and can be captured in a graph).  Passes
+// beyond the plan's count exit at once.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace glam {
+
+namespace {
+
+constexpr int kScanThreads = 256, kScanItems = 8, kScanBlock = kScanThreads * kScanItems;
+constexpr int kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
+constexpr int kMaxSortBlocks = 1024;
+constexpr uint32_t kDepthBase = 0x3E4CCCCDu;  // bit pattern of 0.2f: every visible depth is above it
+
+struct Plan {
+  uint32_t P;          // pair count (clamped to capacity)
+  uint32_t dbits;      // depth key bits
+  uint32_t npasses;    // radix passes
+  uint32_t tbits;      // tile key bits
+  uint32_t tiles_per_block;
+  uint32_t n_sort_tiles;
+  uint32_t pad[10];
+};
+
+struct Layout {
+  size_t partial_sum, partial_max, plan, keys_alt, vals_alt, hist, digit_total, total;
+  int n_scan_blocks, n_sort_blocks;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout(long long n_gauss, long long capacity) {
+  Layout L;
+  L.n_scan_blocks = (int)((n_gauss + kScanBlock - 1) / kScanBlock);
+  if (L.n_scan_blocks < 1) L.n_scan_blocks = 1;
+  long long tiles = (capacity + kSortTile - 1) / kSortTile;
+  L.n_sort_blocks = (int)(tiles < 1 ? 1 : (tiles > kMaxSortBlocks ? kMaxSortBlocks : tiles));
+  size_t o = 0;
+  L.partial_sum = o; o = align256(o + 4ull * L.n_scan_blocks);
+  L.partial_max = o; o = align256(o + 4ull * L.n_scan_blocks);
+  L.plan = o; o = align256(o + sizeof(Plan));
+  L.keys_alt = o; o = align256(o + 8ull * (size_t)capacity);
+  L.vals_alt = o; o = align256(o + 4ull * (size_t)capacity);
+  L.hist = o; o = align256(o + 4ull * kRadix * L.n_sort_blocks);
+  L.digit_total = o; o = align256(o + 4ull * kRadix);
+  L.total = o;
+  return L;
+}
+
+int bit_length(uint64_t x) {
+  int b = 0;
+  while (x) { ++b; x >>= 1; }
+  return b;
+}
+
+__device__ __forceinline__ int dbit_length(uint32_t x) { return x ? 32 - __clz(x) : 0; }
+
+__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t* ntiles, const float* depth,
+                                                                   long long n, uint32_t* psum, uint32_t* pmax) {
+  __shared__ uint32_t s_sum, s_max;
+  if (threadIdx.x == 0) { s_sum = 0; s_max = 0; }
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kScanBlock;
+  uint32_t sum = 0, mx = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    const long long g = base + (long long)i * kScanThreads + threadIdx.x;
+    if (g < n) {
+      const int32_t nt = ntiles[g];
+      sum += (uint32_t)nt;
+      if (nt > 0) mx = max(mx, __float_as_uint(depth[g]));
+    }
+  }
+  atomicAdd(&s_sum, sum);
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  if (threadIdx.x == 0) { psum[blockIdx.x] = s_sum; pmax[blockIdx.x] = s_max; }
+}
+
+// One block of 1024 threads: exclusive scan of the block sums in place, and the plan.
+__global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const uint32_t* pmax, int nb,
+                                                         long long capacity, long long n_tiles, int n_sort_blocks,
+                                                         Plan* plan, int32_t* status) {
+  __shared__ unsigned long long s_part[1024];
+  __shared__ uint32_t s_max[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int lo = min(nb, t * per), hi = min(nb, lo + per);
+  unsigned long long local = 0;
+  uint32_t mx = 0;
+  for (int i = lo; i < hi; ++i) { local += psum[i]; mx = max(mx, pmax[i]); }
+  s_part[t] = local;
+  s_max[t] = mx;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned long long v = t >= off ? s_part[t - off] : 0ull;
+    uint32_t m = t >= off ? s_max[t - off] : 0u;
+    __syncthreads();
+    s_part[t] += v;
+    s_max[t] = max(s_max[t], m);
+    __syncthreads();
+  }
+  unsigned long long run = s_part[t] - local;  // exclusive prefix of this thread's segment
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = psum[i];
+    psum[i] = (uint32_t)run;
+    run += v;
+  }
+  if (t == 1023) {
+    const unsigned long long P = s_part[1023];
+    const uint32_t maxbits = s_max[1023];
+    Plan pl;
+    for (int k = 0; k < 10; ++k) pl.pad[k] = 0;
+    long long Pc = (long long)P;
+    if (Pc > capacity) {
+      status[0] = GLAM_ERR_CAPACITY;
+      Pc = capacity;
+    }
+    status[1] = (int32_t)(uint32_t)Pc;
+    status[2] = (int32_t)(uint32_t)(P & 0xffffffffull);
+    status[3] = (int32_t)(uint32_t)(P >> 32);
+    pl.P = (uint32_t)Pc;
+    pl.dbits = (P > 0 && maxbits > kDepthBase) ? (uint32_t)dbit_length(maxbits - kDepthBase) : 1u;
+    pl.tbits = n_tiles > 1 ? (uint32_t)(64 - __clzll((unsigned long long)(n_tiles - 1))) : 0u;
+    pl.npasses = Pc > 0 ? (pl.dbits + pl.tbits + kRadixBits - 1) / kRadixBits : 0u;
+    pl.n_sort_tiles = (uint32_t)((Pc + kSortTile - 1) / kSortTile);
+    pl.tiles_per_block = (pl.n_sort_tiles + n_sort_blocks - 1) / n_sort_blocks;
+    status[4] = (int32_t)pl.dbits;
+    status[5] = (int32_t)pl.tbits;
+    status[6] = (int32_t)pl.npasses;
+    *plan = pl;
+  }
+}
+
+// Pairs of every view-Gaussian; the first 2048-block scan is redone here in LDS.
+__global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* ntiles, const float* splat,
+                                                                 long long n, const glam_view_info* views,
+                                                                 int n_views, const uint32_t* psum,
+                                                                 const Plan* plan, uint64_t* keys_out,
+                                                                 uint32_t* vals_out, uint64_t* keys_alt,
+                                                                 uint32_t* vals_alt) {
+  __shared__ uint32_t s_nt[kScanBlock];
+  __shared__ uint32_t s_scan[kScanThreads];
+  const Plan pl = *plan;
+  const long long base = (long long)blockIdx.x * kScanBlock;
+  for (int i = 0; i < kScanItems; ++i) {
+    const int j = i * kScanThreads + threadIdx.x;
+    const long long g = base + j;
+    s_nt[j] = g < n ? (uint32_t)ntiles[g] : 0u;
+  }
+  __syncthreads();
+  // thread t owns entries [t*8, t*8+8)
+  uint32_t local[kScanItems];
+  uint32_t sum = 0;
+  for (int i = 0; i < kScanItems; ++i) { local[i] = sum; sum += s_nt[threadIdx.x * kScanItems + i]; }
+  s_scan[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const uint32_t before = s_scan[threadIdx.x] - sum + psum[blockIdx.x];
+  uint64_t* kout = (pl.npasses & 1u) ? keys_alt : keys_out;
+  uint32_t* vout = (pl.npasses & 1u) ? vals_alt : vals_out;
+  for (int i = 0; i < kScanItems; ++i) {
+    const long long g = base + threadIdx.x * kScanItems + i;
+    if (g >= n) break;
+    const uint32_t cnt = s_nt[threadIdx.x * kScanItems + i];
+    if (cnt == 0) continue;
+    uint32_t off = before + local[i];
+    const int vi = find_view(views, n_views, g, [](const glam_view_info& v) { return v.g_begin; });
+    const glam_view_info& vw = views[vi];
+    const float* rec = splat + g * kSplatWords;
+    const uint32_t bx = __float_as_uint(rec[9]), by = __float_as_uint(rec[10]);
+    const uint32_t dkey = __float_as_uint(rec[11]) - kDepthBase;
+    const int tx0 = (int)(bx & 0xffffu) / kTile, tx1 = (int)(bx >> 16) / kTile;
+    const int ty0 = (int)(by & 0xffffu) / kTile, ty1 = (int)(by >> 16) / kTile;
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        if (off < pl.P) {
+          const uint64_t tile = (uint64_t)(vw.tile_begin + ty * vw.tiles_x + tx);
+          kout[off] = (tile << pl.dbits) | (uint64_t)dkey;
+          vout[off] = (uint32_t)g;
+        }
+        ++off;
+      }
+  }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Lanes of this wave holding the same digit (among `valid` lanes).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan* plan, int pass, int n_blocks,
+                                                                     const uint64_t* keys_out,
+                                                                     const uint64_t* keys_alt, uint32_t* hist) {
+  const Plan pl = *plan;
+  if ((uint32_t)pass >= pl.npasses) return;
+  __shared__ uint32_t s_cnt[kRadix];
+  s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t* src = ((pass & 1) == 0) == ((pl.npasses & 1u) == 0) ? keys_out : keys_alt;
+  const int shift = pass * kRadixBits;
+  const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
+  const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    const uint32_t start = tile * kSortTile;
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+      const bool valid = idx < pl.P;
+      const uint32_t d = valid ? (uint32_t)(src[idx] >> shift) & (kRadix - 1) : 0u;
+      const uint64_t peers = match_digit(d, valid);
+      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  hist[threadIdx.x * n_blocks + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's counts across blocks.
+__global__ void __launch_bounds__(256) radix_scan_kernel(const Plan* plan, int pass, int n_blocks, uint32_t* hist,
+                                                         uint32_t* digit_total) {
+  const Plan pl = *plan;
+  if ((uint32_t)pass >= pl.npasses) return;
+  __shared__ uint32_t s[256];
+  uint32_t* row = hist + blockIdx.x * n_blocks;
+  const int per = (n_blocks + 255) / 256;
+  const int lo = min(n_blocks, (int)threadIdx.x * per), hi = min(n_blocks, lo + per);
+  uint32_t local = 0;
+  for (int i = lo; i < hi; ++i) local += row[i];
+  s[threadIdx.x] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - local;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = row[i];
+    row[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == 255) digit_total[blockIdx.x] = s[255];
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Plan* plan, int pass, int n_blocks,
+                                                                       const uint32_t* hist,
+                                                                       const uint32_t* digit_total,
+                                                                       uint64_t* keys_out, uint32_t* vals_out,
+                                                                       uint64_t* keys_alt, uint32_t* vals_alt) {
+  const Plan pl = *plan;
+  if ((uint32_t)pass >= pl.npasses) return;
+  __shared__ uint32_t s_cnt[kSortItems][kSortThreads / 64][kRadix];
+  __shared__ uint32_t s_run[kRadix];
+  __shared__ uint32_t s_scan[kRadix];
+  const bool src_is_out = ((pass & 1) == 0) == ((pl.npasses & 1u) == 0);
+  const uint64_t* ksrc = src_is_out ? keys_out : keys_alt;
+  const uint32_t* vsrc = src_is_out ? vals_out : vals_alt;
+  uint64_t* kdst = src_is_out ? keys_alt : keys_out;
+  uint32_t* vdst = src_is_out ? vals_alt : vals_out;
+  const int shift = pass * kRadixBits;
+  const int t = threadIdx.x, w = t >> 6;
+  // global base of each digit = exclusive scan of the digit totals
+  const uint32_t tot = digit_total[t];
+  s_scan[t] = tot;
+  __syncthreads();
+  for (int off = 1; off < kRadix; off <<= 1) {
+    const uint32_t v = t >= off ? s_scan[t - off] : 0u;
+    __syncthreads();
+    s_scan[t] += v;
+    __syncthreads();
+  }
+  s_run[t] = s_scan[t] - tot + hist[t * n_blocks + blockIdx.x];
+  __syncthreads();
+  const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
+  const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
+  uint32_t* cnt = &s_cnt[0][0][0];
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    for (int k = t; k < kSortItems * (kSortThreads / 64) * kRadix; k += kSortThreads) cnt[k] = 0;
+    __syncthreads();
+    const uint32_t start = tile * kSortTile;
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+    bool valid[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint32_t idx = start + i * kSortThreads + t;
+      valid[i] = idx < pl.P;
+      key[i] = valid[i] ? ksrc[idx] : 0ull;
+      val[i] = valid[i] ? vsrc[idx] : 0u;
+      dig[i] = (uint32_t)(key[i] >> shift) & (kRadix - 1);
+      const uint64_t peers = match_digit(dig[i], valid[i]);
+      rank[i] = (uint32_t)__popcll(peers & lanemask_lt());
+      if (valid[i] && rank[i] == 0) s_cnt[i][w][dig[i]] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit (thread t = digit t): exclusive prefix over (item round, wave)
+    uint32_t run = 0;
+    for (int i = 0; i < kSortItems; ++i)
+      for (int ww = 0; ww < kSortThreads / 64; ++ww) {
+        const uint32_t c = s_cnt[i][ww][t];
+        s_cnt[i][ww][t] = run;
+        run += c;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      if (!valid[i]) continue;
+      const uint32_t pos = s_run[dig[i]] + s_cnt[i][w][dig[i]] + rank[i];
+      if (pos < pl.P) {  // always true for consistent counts; keeps any fault impossible
+        kdst[pos] = key[i];
+        vdst[pos] = val[i];
+      }
+    }
+    __syncthreads();
+    s_run[t] += run;
+    __syncthreads();
+  }
+}
+
+__global__ void ranges_clear_kernel(uint32_t* ranges, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ranges[i] = 0u;
+}
+
+__global__ void ranges_mark_kernel(const Plan* plan, const uint64_t* keys, uint32_t* ranges, long long n_tiles) {
+  const Plan pl = *plan;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pl.P) return;
+  const uint64_t tile = keys[i] >> pl.dbits;
+  if (tile >= (uint64_t)n_tiles) return;
+  if (i == 0 || (keys[i - 1] >> pl.dbits) != tile) ranges[2 * tile] = i;
+  if (i + 1 == pl.P || (keys[i + 1] >> pl.dbits) != tile) ranges[2 * tile + 1] = i + 1;
+}
+
+}  // namespace
+
+size_t bin_sort_workspace(const glam_views& v, long long capacity) {
+  return layout(v.n_gauss, capacity).total;
+}
+
+glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, const glam_bins& bins, void* ws,
+                            size_t ws_bytes, hipStream_t s) {
+  const Layout L = layout(v.n_gauss, bins.capacity);
+  if (ws_bytes < L.total) return GLAM_ERR_WORKSPACE;
+  char* w = static_cast<char*>(ws);
+  uint32_t* psum = reinterpret_cast<uint32_t*>(w + L.partial_sum);
+  uint32_t* pmax = reinterpret_cast<uint32_t*>(w + L.partial_max);
+  Plan* plan = reinterpret_cast<Plan*>(w + L.plan);
+  uint64_t* keys_alt = reinterpret_cast<uint64_t*>(w + L.keys_alt);
+  uint32_t* vals_alt = reinterpret_cast<uint32_t*>(w + L.vals_alt);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(w + L.digit_total);
+  const long long n = v.n_gauss;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.depth,
+                     n, psum, pmax);
+  hipLaunchKernelGGL(scan_plan_kernel, dim3(1), dim3(1024), 0, s, psum, pmax, L.n_scan_blocks,
+                     (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status);
+  hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
+                     n, v.dev, v.n, psum, plan, bins.keys, bins.vals, keys_alt, vals_alt);
+  // host bound on the passes: tile bits are known, depth keys take at most 31 bits
+  const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
+  const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;
+  for (int p = 0; p < max_passes; ++p) {
+    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                       L.n_sort_blocks, bins.keys, keys_alt, hist);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, plan, p, L.n_sort_blocks, hist, dtot);
+    hipLaunchKernelGGL(radix_downsweep_kernel, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                       L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
+  }
+  const long long nr = 2 * v.n_tiles;
+  hipLaunchKernelGGL(ranges_clear_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, bins.ranges, nr);
+  if (bins.capacity > 0)
+    hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,
+                       bins.keys, bins.ranges, (long long)v.n_tiles);
+  return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
+}
+
+}  // namespace glam

@@ -1,0 +1,56 @@
+// Shared device helpers of the glam HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glam.h"
+
+namespace glam {
+
+constexpr int kTile = 16;             // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;
+constexpr float kZNear = 0.2f;        // cull depth
+constexpr float kDilation = 0.3f;     // px^2 added to the 2-D covariance diagonal
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr int kSplatWords = 12;       // packed render record
+
+// Index of the view whose [begin, next begin) holds `i`; views sorted by the field.
+template <class Get>
+__device__ __forceinline__ int find_view(const glam_view_info* v, int n, long long i, Get get) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (get(v[mid]) <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum across a wave64; every lane gets the total.  Rows of 16 lanes are reduced with
+// DPP (quad permutes, then row rotates), the four row sums with lane reads.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (a + b) + (c + d);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float sigmoid(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+}  // namespace glam

@@ -1,0 +1,39 @@
+// Host-side launchers of the glam kernels (each in its own .hip file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "glam.h"
+
+namespace glam {
+
+constexpr int kTileEdge() { return 16; }
+
+glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain,
+                           const glam_projected& out, hipStream_t s);
+glam_status launch_project_bwd(const glam_gaussians& g, const glam_projected& proj, const glam_views& v,
+                               bool plain, const float* g2d, const glam_gaussians& dg, hipStream_t s);
+
+size_t bin_sort_workspace(const glam_views& v, long long capacity);
+glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, const glam_bins& bins,
+                            void* ws, size_t ws_bytes, hipStream_t s);
+
+glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
+                              const float* bg, float* image, float* T_final, int32_t* n_contrib,
+                              hipStream_t s);
+glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
+                                 const float* bg, const float* T_final, const int32_t* n_contrib,
+                                 const float* dimage, float* g2d, hipStream_t s);
+
+size_t loss_workspace(const glam_views& v);
+glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
+                        float* dimage, float* loss, void* ws, hipStream_t s);
+
+glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sigmoid_opacity,
+                          const glam_gaussians& out, hipStream_t s);
+size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts);
+glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v,
+                              bool sigmoid_opacity, const glam_gaussians& dg, float* dfeat, float* doffs,
+                              float* dlog_scale, float* dmlp, void* ws, hipStream_t s);
+
+}  // namespace glam

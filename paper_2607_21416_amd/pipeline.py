@@ -1,0 +1,276 @@
+"""One mapping step on the GPU: decode -> project -> bin/sort -> composite -> loss ->
+backward, through the C ABI.  PyTorch only provides device memory and the stream.
+
+`Pipeline` owns every device buffer of a scene (inputs, intermediates, outputs,
+workspaces), so a step allocates nothing and its launch sequence can be replayed or
+captured in a HIP graph.  `GlamRender` / `GlamLoss` expose the same calls as
+torch.autograd.Functions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+TILE = 16
+
+
+def camera_array(cams) -> "C.Array":
+    arr = (B.Camera * len(cams))()
+    for i, c in enumerate(cams):
+        R = np.asarray(c["R"], np.float32).ravel()
+        t = np.asarray(c["t"], np.float32).ravel()
+        for k in range(9):
+            arr[i].R[k] = float(R[k])
+        for k in range(3):
+            arr[i].t[k] = float(t[k])
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = (float(c[k]) for k in ("fx", "fy", "cx", "cy"))
+        arr[i].width, arr[i].height = int(c["W"]), int(c["H"])
+        arr[i].partition = int(c.get("partition", 0))
+    return arr
+
+
+def _f32(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+
+
+class ViewTable:
+    """Host and device copies of the per-view offsets (glam_views_build)."""
+
+    def __init__(self, cams, device, part_begin=None, K=0, plain_G=0):
+        self.cams = camera_array(cams)
+        n = len(cams)
+        self.info = (B.ViewInfo * n)()
+        self.views = B.Views()
+        if part_begin is not None:
+            pb = np.ascontiguousarray(part_begin, np.int32)
+            self._pb = pb
+            B.glam_views_build(self.cams, n, pb, len(pb) - 1, K, 0, TILE, TILE, self.info, self.views)
+        else:
+            B.glam_views_build(self.cams, n, None, 0, 0, plain_G, TILE, TILE, self.info, self.views)
+        raw = np.frombuffer(bytes(self.info), dtype=np.uint8).copy()
+        self.dev_bytes = torch.from_numpy(raw).to(device)
+        self.views.host = C.cast(self.info, C.c_void_p)
+        self.views.dev = self.dev_bytes.data_ptr()
+        self.n = n
+
+    @property
+    def n_gauss(self):
+        return self.views.n_gauss
+
+    @property
+    def n_pix(self):
+        return self.views.n_pix
+
+    @property
+    def n_tiles(self):
+        return self.views.n_tiles
+
+    def pix_slices(self):
+        return [(int(self.info[i].pix_begin), int(self.info[i].cam.width), int(self.info[i].cam.height))
+                for i in range(self.n)]
+
+
+class Pipeline:
+    """Device buffers and launch sequence of one scene (see the synth module for the
+    scene dictionaries)."""
+
+    def __init__(self, scene: dict, device="cuda", capacity: int | None = None, bg=(0.0, 0.0, 0.0)):
+        self.device = torch.device(device)
+        dev = self.device
+        self.scene = scene
+        self.plain = scene["kind"] == "plain"
+        self.flags = B.GLAM_PLAIN if self.plain else 0
+        if not self.plain and scene.get("opacity_mode", "tanh") == "sigmoid":
+            self.flags |= B.GLAM_OPACITY_SIGMOID
+        self.ssim_weight = float(scene.get("ssim_weight", 0.0))
+        cams = scene["cams"]
+        if self.plain:
+            G = scene["mean"].shape[1]
+            self.vt = ViewTable(cams, dev, plain_G=G)
+            self.params = {k: _f32(scene[k], dev) for k in ("mean", "log_scale", "quat", "logit", "rgb")}
+            self.gauss = B.Gaussians(self.params["mean"].data_ptr(), self.params["log_scale"].data_ptr(),
+                                     self.params["quat"].data_ptr(), self.params["logit"].data_ptr(),
+                                     self.params["rgb"].data_ptr(), G)
+            self.n_parts = 0
+        else:
+            F, K = scene["F"], scene["K"]
+            self.vt = ViewTable(cams, dev, part_begin=scene["part_begin"], K=K)
+            self.params = {k: _f32(scene[k], dev) for k in ("pos", "feat", "log_scale", "offs", "mlp")}
+            A = scene["feat"].shape[0]
+            self.anchors = B.Anchors(self.params["pos"].data_ptr(), self.params["feat"].data_ptr(),
+                                     self.params["log_scale"].data_ptr(), self.params["offs"].data_ptr(), A, F, K,
+                                     scene["hidden"])
+            self.n_parts = scene["mlp"].shape[0]
+            n = self.vt.n_gauss
+            self.dec = {k: torch.empty((r, n) if r > 1 else (n,), device=dev, dtype=torch.float32)
+                        for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
+            self.gauss = B.Gaussians(*(self.dec[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "rgb")),
+                                     n)
+        n = self.vt.n_gauss
+        self.proj_t = dict(uv=torch.empty((2, n), device=dev), conic=torch.empty((3, n), device=dev),
+                           depth=torch.empty(n, device=dev), ext=torch.empty((2, n), device=dev),
+                           ntiles=torch.empty(n, device=dev, dtype=torch.int32),
+                           splat=torch.empty((n, 12), device=dev))
+        self.proj = B.Projected(*(self.proj_t[k].data_ptr() for k in ("uv", "conic", "depth", "ext", "ntiles",
+                                                                     "splat")))
+        npix = self.vt.n_pix
+        self.image = torch.empty(3 * npix, device=dev)
+        self.T_final = torch.empty(npix, device=dev)
+        self.n_contrib = torch.empty(npix, device=dev, dtype=torch.int32)
+        self.target = torch.cat([_f32(t, dev).reshape(-1) for t in scene["targets"]])
+        self.dimage = torch.empty(3 * npix, device=dev)
+        self.loss = torch.empty(self.vt.n, device=dev)
+        self.bg = torch.zeros(4, device=dev)
+        self.bg[:3] = torch.tensor(bg, dtype=torch.float32)
+        self.ws_loss = torch.empty(B.glam_loss_workspace_bytes(self.vt.views), device=dev, dtype=torch.uint8)
+        self.status = torch.zeros(8, device=dev, dtype=torch.int32)
+        self._alloc_bins(capacity if capacity else max(1024, 4 * n))
+        # gradients
+        self.g2d = torch.empty((n, 9), device=dev)
+        if self.plain:
+            G = self.gauss.n
+            self.dg = {k: torch.empty((r, G) if r > 1 else (G,), device=dev)
+                       for k, r in (("mean", 3), ("log_scale", 3), ("quat", 4), ("logit", 1), ("rgb", 3))}
+            dgs = B.Gaussians(*(self.dg[k].data_ptr() for k in ("mean", "log_scale", "quat", "logit", "rgb")), G)
+            self.grads = B.Grads(self.g2d.data_ptr(), dgs, None, None, None, None)
+            self.ws_dec = torch.empty(16, device=dev, dtype=torch.uint8)
+        else:
+            self.dg = {k: torch.empty((r, n) if r > 1 else (n,), device=dev)
+                       for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
+            dgs = B.Gaussians(*(self.dg[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "rgb")), n)
+            p = self.params
+            self.pgrad = {k: torch.empty_like(p[k]) for k in ("feat", "offs", "log_scale", "mlp")}
+            self.grads = B.Grads(self.g2d.data_ptr(), dgs, self.pgrad["feat"].data_ptr(),
+                                 self.pgrad["offs"].data_ptr(), self.pgrad["log_scale"].data_ptr(),
+                                 self.pgrad["mlp"].data_ptr())
+            nb = B.glam_decode_bwd_workspace_bytes(self.anchors, self.vt.views, self.n_parts)
+            self.ws_dec = torch.empty(max(16, nb), device=dev, dtype=torch.uint8)
+
+    # ------------------------------------------------------------------------------
+    def _alloc_bins(self, capacity: int):
+        dev = self.device
+        self.capacity = int(capacity)
+        self.keys = torch.empty(self.capacity, device=dev, dtype=torch.int64)
+        self.vals = torch.empty(self.capacity, device=dev, dtype=torch.int32)
+        self.ranges = torch.empty(2 * self.vt.n_tiles, device=dev, dtype=torch.int32)
+        self.bins = B.Bins(self.keys.data_ptr(), self.vals.data_ptr(), self.ranges.data_ptr(), self.capacity,
+                           self.status.data_ptr())
+        nb = B.glam_bin_sort_workspace_bytes(self.vt.views, self.capacity)
+        self.ws_sort = torch.empty(nb, device=dev, dtype=torch.uint8)
+
+    def stream(self):
+        return torch.cuda.current_stream(self.device)
+
+    # ------------------------------------------------------------------------------
+    def decode(self, s=None):
+        if not self.plain:
+            B.glam_decode(self.anchors, self.params["mlp"], self.n_parts, self.vt.views, self.flags, self.gauss,
+                          s or self.stream())
+
+    def project(self, s=None):
+        B.glam_project(self.gauss, self.vt.views, self.flags, self.proj, s or self.stream())
+
+    def bin_sort(self, s=None):
+        B.glam_bin_sort(self.proj, self.vt.views, self.bins, self.ws_sort, self.ws_sort.numel(), s or self.stream())
+
+    def render(self, s=None):
+        B.glam_render_fwd(self.proj, self.bins, self.vt.views, self.bg, self.image, self.T_final, self.n_contrib,
+                          s or self.stream())
+
+    def compute_loss(self, s=None):
+        B.glam_loss(self.vt.views, self.image, self.target, self.ssim_weight, self.dimage, self.loss, self.ws_loss,
+                    self.ws_loss.numel(), s or self.stream())
+
+    def backward(self, s=None, dimage=None):
+        B.glam_render_bwd(self.proj, self.bins, self.vt.views, self.bg, self.T_final, self.n_contrib,
+                          self.dimage if dimage is None else dimage, self.gauss,
+                          None if self.plain else self.anchors, None if self.plain else self.params["mlp"],
+                          self.n_parts, self.flags, self.grads, self.ws_dec, self.ws_dec.numel(), s or self.stream())
+
+    def forward(self, s=None):
+        self.decode(s)
+        self.project(s)
+        self.bin_sort(s)
+        self.render(s)
+        self.compute_loss(s)
+
+    def step(self, s=None):
+        self.forward(s)
+        self.backward(s)
+
+    # ------------------------------------------------------------------------------
+    def pair_count(self) -> int:
+        st = self.status.cpu().numpy()
+        return int(np.uint32(st[2])) | (int(np.uint32(st[3])) << 32)
+
+    def check_status(self):
+        st = self.status.cpu().numpy()
+        if st[0] != 0:
+            raise B.GlamError("device status", int(st[0]))
+
+    def fit_capacity(self, slack: float = 1.25):
+        """Runs the forward up to the sort once and grows the pair buffers to the
+        required count times `slack` (one synchronising sizing pass)."""
+        self.decode()
+        self.project()
+        self.bin_sort()
+        torch.cuda.synchronize(self.device)
+        need = self.pair_count()
+        if need > self.capacity or self.capacity > 4 * max(need, 1024):
+            self.status.zero_()
+            self._alloc_bins(max(1024, int(need * slack)))
+        return need
+
+    def images(self):
+        out = []
+        for pb, W, H in self.vt.pix_slices():
+            out.append(self.image[3 * pb:3 * pb + 3 * W * H].view(3, H, W))
+        return out
+
+    def per_pixel(self, t):
+        return [t[pb:pb + W * H].view(H, W) for pb, W, H in self.vt.pix_slices()]
+
+
+class GlamRender(torch.autograd.Function):
+    """images = render(params); backward runs the reverse compositing, projection and
+    decode adjoints.  params: (feat, offs, log_scale, mlp) in anchor mode or (mean,
+    log_scale, quat, logit, rgb) in plain mode; they must be the tensors the Pipeline
+    holds (the kernels read them in place)."""
+
+    @staticmethod
+    def forward(ctx, pipe: Pipeline, *params):
+        pipe.decode()
+        pipe.project()
+        pipe.bin_sort()
+        pipe.render()
+        ctx.pipe = pipe
+        return pipe.image.clone()
+
+    @staticmethod
+    def backward(ctx, dimage):
+        pipe = ctx.pipe
+        pipe.backward(dimage=dimage.contiguous())
+        if pipe.plain:
+            g = tuple(pipe.dg[k].clone() for k in ("mean", "log_scale", "quat", "logit", "rgb"))
+        else:
+            g = tuple(pipe.pgrad[k].clone() for k in ("feat", "offs", "log_scale", "mlp"))
+        return (None,) + g
+
+
+class GlamLoss(torch.autograd.Function):
+    """Sum over views of L1 + w (1 - SSIM) (Eq. 3); dL/dimage comes from the loss kernel."""
+
+    @staticmethod
+    def forward(ctx, pipe: Pipeline, image):
+        pipe.image.copy_(image)
+        pipe.compute_loss()
+        ctx.pipe = pipe
+        return pipe.loss.sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, ctx.pipe.dimage * g

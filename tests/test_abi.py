@@ -1,0 +1,120 @@
+"""The C ABI library on the host: it loads, exports every function include/glam.h
+declares, builds view tables, and rejects bad arguments before any launch (no GPU is
+touched by these tests)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2607_21416_amd import binding as B
+from paper_2607_21416_amd.pipeline import camera_array
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "glam.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\*?(glam_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_param_count_matches_oracle():
+    assert B.glam_mlp_param_count(32, 10, 32) == 7182 == oracle.mlp_param_count(32, 10, 32)
+    assert B.glam_mlp_param_count(16, 4, 32) == oracle.mlp_param_count(16, 4, 32)
+
+
+def _build(cams, part_begin=None, K=0, plain_G=0):
+    arr = camera_array(cams)
+    info = (B.ViewInfo * len(cams))()
+    views = B.Views()
+    pb = None if part_begin is None else np.ascontiguousarray(part_begin, np.int32)
+    st = B.load().glam_views_build(B.ref(arr), len(cams), B.ref(pb), 0 if pb is None else len(pb) - 1, K, plain_G,
+                                   16, 16, B.ref(info), B.ref(views))
+    return st, info, views
+
+
+def test_views_build_offsets():
+    s = synth.anchor_scene(3, [100, 50, 75], 2, W=70, H=45, fx=50)
+    st, info, views = _build(s["cams"], s["part_begin"], s["K"])
+    assert st == B.GLAM_OK
+    g = p = t = 0
+    for i, cam in enumerate(s["cams"]):
+        vi = info[i]
+        m = cam["partition"]
+        assert vi.g_begin == g and vi.pix_begin == p and vi.tile_begin == t
+        assert vi.tiles_x == 5 and vi.tiles_y == 3  # ceil(70/16), ceil(45/16): ragged edges
+        assert vi.anchor_begin == s["part_begin"][m]
+        assert vi.anchor_count == s["part_begin"][m + 1] - s["part_begin"][m]
+        assert vi.g_count == vi.anchor_count * s["K"]
+        g += vi.g_count; p += 70 * 45; t += 15
+    assert (views.n, views.n_gauss, views.n_pix, views.n_tiles) == (6, g, p, t)
+    st, info, views = _build(s["cams"][:2], None, 0, 123)
+    assert st == B.GLAM_OK and views.n_gauss == 246 and info[1].g_begin == 123
+
+
+def test_views_build_rejects_bad_input():
+    cams = [synth.camera(np.eye(3), np.zeros(3), 50, 50, 10, 10, 20, 20)]
+    assert _build(cams, None, 0, 0)[0] == B.GLAM_ERR_INVALID_ARG           # no Gaussians
+    bad = dict(cams[0], W=0)
+    assert _build([bad], None, 0, 10)[0] == B.GLAM_ERR_INVALID_ARG         # empty image
+    bad = dict(cams[0], partition=3)
+    assert _build([bad], [0, 5], 10)[0] == B.GLAM_ERR_INVALID_ARG         # no such partition
+
+
+def test_calls_reject_before_launch():
+    lib = B.load()
+    s = synth.plain_scene(1, 10, 32, 32)
+    st, info, views = _build(s["cams"], None, 0, 10)
+    fake = 0x100000  # aligned, never dereferenced: validation fails first
+    views.host = C.cast(info, C.c_void_p)
+    views.dev = fake
+    g = B.Gaussians(fake, fake, fake, fake, fake, 10)
+    proj_null = B.Projected(fake, None, fake, fake, fake, fake)
+    assert lib.glam_project(B.ref(g), B.ref(views), B.GLAM_PLAIN, B.ref(proj_null), None) == B.GLAM_ERR_INVALID_ARG
+    proj = B.Projected(fake, fake, fake, fake, fake, fake + 4)  # misaligned
+    assert lib.glam_project(B.ref(g), B.ref(views), B.GLAM_PLAIN, B.ref(proj), None) == B.GLAM_ERR_INVALID_ARG
+    proj = B.Projected(fake, fake, fake, fake, fake, fake)
+    g_wrong = B.Gaussians(fake, fake, fake, fake, fake, 11)  # plain G must match the view table
+    assert lib.glam_project(B.ref(g_wrong), B.ref(views), B.GLAM_PLAIN, B.ref(proj), None) == B.GLAM_ERR_INVALID_ARG
+    bins = B.Bins(fake, fake, fake, 1000, fake)
+    need = lib.glam_bin_sort_workspace_bytes(B.ref(views), 1000)
+    assert need > 12000
+    assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins), C.c_void_p(fake), need - 1,
+                             None) == B.GLAM_ERR_WORKSPACE
+    bins0 = B.Bins(fake, fake, fake, 0, fake)
+    assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins0), C.c_void_p(fake), need,
+                             None) == B.GLAM_ERR_INVALID_ARG
+    # anchor decode: unsupported feature width / offset count
+    sa = synth.anchor_scene(2, [20], 1, W=32, H=32, fx=30, F=8, K=3)
+    st, info2, views2 = _build(sa["cams"], sa["part_begin"], 3)
+    views2.host = C.cast(info2, C.c_void_p)
+    views2.dev = fake
+    an = B.Anchors(fake, fake, fake, fake, 20, 8, 3, 32)
+    out = B.Gaussians(fake, fake, fake, fake, fake, views2.n_gauss)
+    assert lib.glam_decode(B.ref(an), C.c_void_p(fake), 1, B.ref(views2), 0, B.ref(out), None) == B.GLAM_ERR_UNSUPPORTED
+    an_bad = B.Anchors(fake, fake, fake, fake, 20, 8, 3, 16)  # hidden width other than 32
+    assert lib.glam_decode(B.ref(an_bad), C.c_void_p(fake), 1, B.ref(views2), 0, B.ref(out),
+                           None) == B.GLAM_ERR_INVALID_ARG
+    assert lib.glam_decode(B.ref(an), C.c_void_p(fake), 0, B.ref(views2), 0, B.ref(out),
+                           None) == B.GLAM_ERR_INVALID_ARG  # partition 0 needs one MLP set
+    assert B.status_string(B.GLAM_ERR_CAPACITY) == "pair capacity exceeded"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libglam.so"))
+    with pytest.raises(ImportError):
+        B.load()
