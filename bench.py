@@ -1,0 +1,250 @@
+#!/usr/bin/env python
+"""Mapping-iteration throughput of the anchor-decoded Gaussian-splatting render on one
+MI355X: anchor-MLP decode -> projection -> tile bin + depth sort -> compositing ->
+L1 + 0.2 (1 - SSIM) loss -> backward to anchor features, offsets, scales and MLP
+weights (Sec. III-A and III-D of the paper).
+
+Workload (the metric's configuration): 50k anchors x 10 offsets = 500k Gaussians on the
+synthetic street corridor, four keyframe views at 1226x370.  One step is the whole
+path for the four views in one batched launch sequence, replayed from a HIP graph; a
+mapping iteration is one keyframe view rendered forward and backward, so
+value = 4 * steps / second.
+
+Also reported: per-stage times, Gaussian-pixel evaluations/s, the roofline of the
+dominant kernel, the batched-vs-plain speedup on 16 partitions x 4 views (one batched
+graph replay against 64 sequential per-view launch sequences), and the FP64 CPU oracle
+timed on this host on the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per Gaussian-pixel evaluation (FP32 operations of the definition):
+#   forward:  offset 2, quadratic form 9, exp 2, opacity 1, clamp 1, threshold 1,
+#             transmittance 2, stop test 1, weight 1, colour 6            -> 26
+#   backward: the forward's alpha 16, T_i recovery 2, colour gradient 4, alpha gradient 9,
+#             behind-colour update 6, opacity/power 2, centre 8, conic 7 -> 54
+FLOP_FWD = 26
+FLOP_BWD = 54
+PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, scalar (non-packed) FP32
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def split_views(scene):
+    """One single-view scene per view of an anchor scene (its partition's anchors,
+    MLP set and target): the plain per-view form."""
+    import numpy as np
+    out = []
+    K = scene["K"]
+    for v, cam in enumerate(scene["cams"]):
+        m = cam["partition"]
+        a0, a1 = int(scene["part_begin"][m]), int(scene["part_begin"][m + 1])
+        sub = dict(scene)
+        sub.update(pos=np.ascontiguousarray(scene["pos"][:, a0:a1]), feat=scene["feat"][a0:a1],
+                   log_scale=scene["log_scale"][a0:a1], offs=np.ascontiguousarray(scene["offs"][:, a0 * K:a1 * K]),
+                   part_begin=np.array([0, a1 - a0], np.int32), mlp=scene["mlp"][m:m + 1],
+                   cams=[dict(cam, partition=0)], targets=[scene["targets"][v]])
+        out.append(sub)
+    return out
+
+
+def timed(torch, fn, iters, stream):
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(iters):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / iters
+
+
+def stage_times(torch, pipe, iters):
+    """Average duration of each C-ABI call of the step, HIP events on the stream the
+    kernels run on (eager launches)."""
+    s = torch.cuda.current_stream()
+    calls = [("decode", pipe.decode), ("project", pipe.project), ("bin_sort", pipe.bin_sort),
+             ("render_fwd", pipe.render), ("loss", pipe.compute_loss),
+             ("composite_bwd", pipe.composite_bwd), ("project_bwd", pipe.project_bwd),
+             ("decode_bwd", pipe.decode_bwd)]
+    ev = {k: ([torch.cuda.Event(enable_timing=True) for _ in range(iters)],
+              [torch.cuda.Event(enable_timing=True) for _ in range(iters)]) for k, _ in calls}
+    torch.cuda.synchronize()
+    for i in range(iters):
+        for k, f in calls:
+            ev[k][0][i].record(s)
+            f()
+            ev[k][1][i].record(s)
+    torch.cuda.synchronize()
+    return {k: sum(a.elapsed_time(b) for a, b in zip(*ev[k])) / iters for k, _ in calls}
+
+
+def make_step(torch, pipe, use_graph):
+    if not use_graph:
+        return pipe.step, None
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pipe.step()  # warm, outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        pipe.step()
+    torch.cuda.synchronize()
+    return g.replay, g
+
+
+def cpu_baseline(scene, views):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_num_threads(threads)
+    t0 = time.perf_counter()
+    fwd = oracle.forward(scene, views=views)
+    oracle.backward(scene, fwd)
+    dt = time.perf_counter() - t0
+    return dict(value=len(views) / dt, unit="iterations/s", cores=threads, kind="oracle",
+                sample=f"config-3 views {list(views)}: one FP64 forward + loss + backward pass each "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-graph", action="store_true", help="eager launches instead of a HIP graph replay")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched-vs-plain comparison")
+    ap.add_argument("--stage-iters", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); partitions shard across GPUs "
+              "without communication, so there is no multi-GPU run to make here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2607_21416_amd import binding
+    from paper_2607_21416_amd.pipeline import Pipeline
+
+    binding.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("bench: generating config 3 (50k anchors, 4 views 1226x370)")
+    scene = synth.config("C3")
+    pipe = Pipeline(scene, device=dev)
+    need = pipe.fit_capacity()
+    pipe.status.zero_()
+    log(f"bench: {pipe.vt.n_gauss} view-Gaussians, {need} pairs, capacity {pipe.capacity}")
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    step, graph = make_step(torch, pipe, not args.no_graph)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps ({'graph' if graph else 'eager'})")
+    t0 = time.perf_counter()
+    ms = timed(torch, step, args.steps, stream)
+    wall = time.perf_counter() - t0
+    pipe.check_status()
+    n_views = pipe.vt.n
+    value = n_views * 1000.0 / ms
+    log(f"bench: {ms:.3f} ms/step, {value:.1f} iterations/s (wall {wall:.2f} s)")
+
+    # per-stage times and evaluation counts (eager, outside the timed region)
+    st = stage_times(torch, pipe, args.stage_iters)
+    pipe.check_status()
+    pipe.count_evaluations()
+    pipe.render()
+    torch.cuda.synchronize()
+    evals_fwd = int(pipe.n_eval.to(torch.int64).sum().item())
+    evals_bwd = int(pipe.n_contrib.to(torch.int64).sum().item())
+    pipe.count_evaluations(False)
+    log("bench: stages " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    dom = max(("render_fwd", "composite_bwd"), key=lambda k: st[k])
+    flops = evals_fwd * FLOP_FWD if dom == "render_fwd" else evals_bwd * FLOP_BWD
+    achieved = flops / (st[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
+                        f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
+
+    out = {
+        "metric": "mapping iters/s fwd+bwd (500k Gaussians, 1226x370); batched vs plain speedup",
+        "value": round(value, 2), "unit": "iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config 3: 50k anchors x 10 offsets = 500k Gaussians, street corridor, "
+                               "4 keyframe views 1226x370, L1 + 0.2 (1 - SSIM), fwd + bwd to anchors and MLPs",
+                   "views_per_step": n_views, "view_gaussians": int(pipe.vt.n_gauss), "pairs": int(need),
+                   "launch": "hip graph" if graph else "eager"},
+        "stages_ms": {k: round(v, 4) for k, v in st.items()},
+        "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
+                              "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
+        "roofline": roofline,
+    }
+    del graph
+
+    if not args.no_batched:
+        log("bench: config 4 (16 partitions x 4 views), batched vs plain")
+        s4 = synth.config("C4")
+        bp = Pipeline(s4, device=dev)
+        bp.fit_capacity()
+        bp.status.zero_()
+        for _ in range(2):
+            bp.step()
+        bstep, bg = make_step(torch, bp, True)
+        tb = timed(torch, bstep, max(3, args.steps // 4), stream)
+        bp.check_status()
+        plains = []
+        for sub in split_views(s4):
+            p = Pipeline(sub, device=dev)
+            p.fit_capacity()
+            p.status.zero_()
+            plains.append(p)
+
+        def plain_all():
+            for p in plains:
+                p.step()
+
+        plain_all()
+        tp = timed(torch, plain_all, max(2, args.steps // 8), stream)
+        for p in plains:
+            p.check_status()
+        out["batched_vs_plain"] = {"workload": "config 4: 16 partitions (log-uniform 20k-400k Gaussians) x 4 views "
+                                               "1226x370, own MLPs",
+                                   "views": bp.vt.n, "view_gaussians": int(bp.vt.n_gauss),
+                                   "batched_ms": round(tb, 3), "plain_ms": round(tp, 3),
+                                   "speedup": round(tp / tb, 3),
+                                   "batched_iterations_per_s": round(bp.vt.n * 1000.0 / tb, 1),
+                                   "plain_iterations_per_s": round(bp.vt.n * 1000.0 / tp, 1)}
+        log(f"bench: batched {tb:.2f} ms, plain {tp:.2f} ms, speedup {tp / tb:.2f}")
+        del bg, bp, plains
+
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline (all 4 views of config 3)")
+        out["cpu_baseline"] = cpu_baseline(scene, list(range(n_views)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

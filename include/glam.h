@@ -204,10 +204,14 @@ glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, g
    alpha = min(0.99, opacity exp(power)), skipped when alpha < 1/255, the walk stops
    before an entry that would take T below 1e-4.  Writes image [3][H][W] per view,
    final transmittance T_final and n_contrib (1 + range position of the last
-   composited entry) per pixel.  bg: [3] device (background colour, may be NULL). */
+   composited entry) per pixel.  bg: [3] device (background colour, may be NULL).
+   n_eval (may be NULL): per pixel, the range entries visited up to and including the
+   one that stopped the walk, or the whole range length if it never stopped (the
+   Gaussian-pixel evaluation count of the definition, independent of any skipping). */
 glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins,
                             const glam_views* views, const float* bg, float* image,
-                            float* T_final, int32_t* n_contrib, hipStream_t stream);
+                            float* T_final, int32_t* n_contrib, int32_t* n_eval,
+                            hipStream_t stream);
 
 /* Eq. 3 per view: L_v = mean |C - target| + w_ssim (1 - mean SSIM), SSIM over an 11x11
    box window with zero padding, C1 = 0.01^2, C2 = 0.03^2.  Writes dL/dimage (same

@@ -96,7 +96,7 @@ def load():
         "glam_decode": (I32, [P, P, I32, P, U32, P, P]),
         "glam_project": (I32, [P, P, U32, P, P]),
         "glam_bin_sort": (I32, [P, P, P, P, SZ, P]),
-        "glam_render_fwd": (I32, [P, P, P, P, P, P, P, P]),
+        "glam_render_fwd": (I32, [P, P, P, P, P, P, P, P, P]),
         "glam_loss_workspace_bytes": (SZ, [P]),
         "glam_loss": (I32, [P, P, P, F32, P, P, P, SZ, P]),
         "glam_composite_bwd": (I32, [P, P, P, P, P, P, P, P, P]),
@@ -176,9 +176,10 @@ def glam_bin_sort(proj, views, bins, ws, ws_bytes, stream):
                                                         _stream(stream)))
 
 
-def glam_render_fwd(proj, bins, views, bg, image, T_final, n_contrib, stream):
+def glam_render_fwd(proj, bins, views, bg, image, T_final, n_contrib, n_eval, stream):
     return _check("glam_render_fwd", load().glam_render_fwd(ref(proj), ref(bins), ref(views), ref(bg), ref(image),
-                                                            ref(T_final), ref(n_contrib), _stream(stream)))
+                                                            ref(T_final), ref(n_contrib), ref(n_eval),
+                                                            _stream(stream)))
 
 
 def glam_loss_workspace_bytes(views):

@@ -180,11 +180,12 @@ glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, g
 }
 
 glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
-                            const float* bg, float* image, float* T_final, int32_t* n_contrib, hipStream_t stream) {
+                            const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
+                            hipStream_t stream) {
   if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(image) || !ok_ptr(T_final) ||
-      !ok_ptr(n_contrib) || (bg && !aligned16(bg)))
+      !ok_ptr(n_contrib) || (bg && !aligned16(bg)) || (n_eval && !aligned16(n_eval)))
     return GLAM_ERR_INVALID_ARG;
-  return glam::launch_render_fwd(*proj, *bins, *views, bg, image, T_final, n_contrib, stream);
+  return glam::launch_render_fwd(*proj, *bins, *views, bg, image, T_final, n_contrib, n_eval, stream);
 }
 
 size_t glam_loss_workspace_bytes(const glam_views* views) {

@@ -540,6 +540,15 @@ size_t bwd_smem() {
   return sizeof(float) * (C::PA + 4 * (16 * C::ZS + 16 * C::YS + 16 * C::HS + 16));
 }
 
+// Raises a kernel's dynamic LDS limit above the 64 KiB default.  Not a stream operation;
+// skipped while the stream is being captured (the first, eager call has set it).
+bool set_smem_limit(const void* fn, size_t bytes, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  if (cs != hipStreamCaptureStatusNone) return true;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
 int max_anchors(const glam_views& v) {
   int mx = 0;
   for (int i = 0; i < v.n; ++i) mx = v.host[i].anchor_count > mx ? v.host[i].anchor_count : mx;
@@ -560,9 +569,7 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
   const int mx = max_anchors(v);
   if (mx == 0 || v.n == 0) return GLAM_OK;
   const size_t sm = fwd_smem<F, K>();
-  if (hipFuncSetAttribute((const void*)decode_kernel<F, K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) !=
-      hipSuccess)
-    return GLAM_ERR_HIP;
+  if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
   hipLaunchKernelGGL((decode_kernel<F, K>), dim3((mx + 63) / 64, v.n), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0,
                      out);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
@@ -577,9 +584,7 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
   float* partial = static_cast<float*>(ws);
   if (v.n > 0 && max_anchors(v) > 0) {
     const size_t sm = bwd_smem<F, K>();
-    if (hipFuncSetAttribute((const void*)decode_bwd_kernel<F, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sm) != hipSuccess)
-      return GLAM_ERR_HIP;
+    if (!set_smem_limit((const void*)decode_bwd_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
     hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(bpp, v.n), dim3(256), sm, s, a, mlp, v.dev, v.n, sig ? 1 : 0, dg,
                        bpp, dfeat, doffs, dls, partial);
   }

@@ -20,7 +20,7 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
 
 glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                               const float* bg, float* image, float* T_final, int32_t* n_contrib,
-                              hipStream_t s);
+                              int32_t* n_eval, hipStream_t s);
 glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                                  const float* bg, const float* T_final, const int32_t* n_contrib,
                                  const float* dimage, float* g2d, hipStream_t s);

@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
                                                          const uint32_t* __restrict__ ranges,
                                                          const glam_view_info* views, int n_views,
                                                          const float* bg, float* image, float* T_final,
-                                                         int32_t* n_contrib, uint32_t capacity, uint32_t n_gauss) {
+                                                         int32_t* n_contrib, int32_t* n_eval, uint32_t capacity,
+                                                         uint32_t n_gauss) {
   __shared__ float4 s_rec[3][kBatch];
   const int tile = blockIdx.x;
   const TileGeom tg = tile_geom(views, n_views, tile);
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
   const float px = tg.x + 0.5f, py = tg.y + 0.5f;
   const bool quad_live = tg.qx0 <= tg.qx1 && tg.qy0 <= tg.qy1;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  int last = 0;
+  int last = 0, stop = (int)(e - s);
   bool done = !tg.inside;
   for (uint32_t b0 = s; b0 < e; b0 += kBatch) {
     if (__syncthreads_count(done) == kBatch) break;
@@ -118,6 +119,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
               const float Tn = T * (1.f - alpha);
               if (Tn < kTMin) {
                 done = true;
+                stop = (int)(b0 - s) + i + 1;
               } else {
                 const float wgt = alpha * T;
                 C0 = fmaf(r1.z, wgt, C0);
@@ -145,6 +147,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
     img[2 * HW + p] = fmaf(T, b2, C2);
     T_final[tg.pix] = T;
     n_contrib[tg.pix] = last;
+    if (n_eval) n_eval[tg.pix] = stop;
   }
 }
 
@@ -248,7 +251,7 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restr
 }
 
 __global__ void background_kernel(const glam_view_info* views, int n_views, long long n_pix, const float* bg,
-                                  float* image, float* T_final, int32_t* n_contrib) {
+                                  float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pix) return;
   const int vi = find_view(views, n_views, i, [](const glam_view_info& v) { return v.pix_begin; });
@@ -257,6 +260,7 @@ __global__ void background_kernel(const glam_view_info* views, int n_views, long
   for (int c = 0; c < 3; ++c) image[3 * vw.pix_begin + c * HW + p] = bg ? bg[c] : 0.f;
   T_final[i] = 1.f;
   n_contrib[i] = 0;
+  if (n_eval) n_eval[i] = 0;
 }
 
 __global__ void zero_kernel(float* p, long long n) {
@@ -265,22 +269,23 @@ __global__ void zero_kernel(float* p, long long n) {
 }
 
 glam_status launch_background(const glam_views& v, const float* bg, float* image, float* T_final,
-                              int32_t* n_contrib, hipStream_t s) {
+                              int32_t* n_contrib, int32_t* n_eval, hipStream_t s) {
   hipLaunchKernelGGL(background_kernel, dim3((unsigned)((v.n_pix + 255) / 256)), dim3(256), 0, s, v.dev, v.n,
-                     (long long)v.n_pix, bg, image, T_final, n_contrib);
+                     (long long)v.n_pix, bg, image, T_final, n_contrib, n_eval);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
 }  // namespace
 
 glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
-                              const float* bg, float* image, float* T_final, int32_t* n_contrib, hipStream_t s) {
+                              const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
+                              hipStream_t s) {
   if (v.n_tiles == 0 || v.n_gauss == 0) {
     // nothing to composite: background everywhere
-    return launch_background(v, bg, image, T_final, n_contrib, s);
+    return launch_background(v, bg, image, T_final, n_contrib, n_eval, s);
   }
   hipLaunchKernelGGL(render_fwd_kernel, dim3((unsigned)v.n_tiles), dim3(256), 0, s, proj.splat, bins.vals,
-                     bins.ranges, v.dev, v.n, bg, image, T_final, n_contrib, (uint32_t)bins.capacity,
+                     bins.ranges, v.dev, v.n, bg, image, T_final, n_contrib, n_eval, (uint32_t)bins.capacity,
                      (uint32_t)v.n_gauss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }

@@ -121,6 +121,7 @@ class Pipeline:
         self.image = torch.empty(3 * npix, device=dev)
         self.T_final = torch.empty(npix, device=dev)
         self.n_contrib = torch.empty(npix, device=dev, dtype=torch.int32)
+        self.n_eval = None
         self.target = torch.cat([_f32(t, dev).reshape(-1) for t in scene["targets"]])
         self.dimage = torch.empty(3 * npix, device=dev)
         self.loss = torch.empty(self.vt.n, device=dev)
@@ -136,12 +137,14 @@ class Pipeline:
             self.dg = {k: torch.empty((r, G) if r > 1 else (G,), device=dev)
                        for k, r in (("mean", 3), ("log_scale", 3), ("quat", 4), ("logit", 1), ("rgb", 3))}
             dgs = B.Gaussians(*(self.dg[k].data_ptr() for k in ("mean", "log_scale", "quat", "logit", "rgb")), G)
+            self.dgs = dgs
             self.grads = B.Grads(self.g2d.data_ptr(), dgs, None, None, None, None)
             self.ws_dec = torch.empty(16, device=dev, dtype=torch.uint8)
         else:
             self.dg = {k: torch.empty((r, n) if r > 1 else (n,), device=dev)
                        for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
             dgs = B.Gaussians(*(self.dg[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "rgb")), n)
+            self.dgs = dgs
             p = self.params
             self.pgrad = {k: torch.empty_like(p[k]) for k in ("feat", "offs", "log_scale", "mlp")}
             self.grads = B.Grads(self.g2d.data_ptr(), dgs, self.pgrad["feat"].data_ptr(),
@@ -179,7 +182,11 @@ class Pipeline:
 
     def render(self, s=None):
         B.glam_render_fwd(self.proj, self.bins, self.vt.views, self.bg, self.image, self.T_final, self.n_contrib,
-                          s or self.stream())
+                          self.n_eval, s or self.stream())
+
+    def count_evaluations(self, on: bool = True):
+        """Makes render() also write per-pixel evaluation counts (self.n_eval)."""
+        self.n_eval = torch.zeros(self.vt.n_pix, device=self.device, dtype=torch.int32) if on else None
 
     def compute_loss(self, s=None):
         B.glam_loss(self.vt.views, self.image, self.target, self.ssim_weight, self.dimage, self.loss, self.ws_loss,
@@ -190,6 +197,20 @@ class Pipeline:
                           self.dimage if dimage is None else dimage, self.gauss,
                           None if self.plain else self.anchors, None if self.plain else self.params["mlp"],
                           self.n_parts, self.flags, self.grads, self.ws_dec, self.ws_dec.numel(), s or self.stream())
+
+    def composite_bwd(self, s=None, dimage=None):
+        B.glam_composite_bwd(self.proj, self.bins, self.vt.views, self.bg, self.T_final, self.n_contrib,
+                             self.dimage if dimage is None else dimage, self.g2d, s or self.stream())
+
+    def project_bwd(self, s=None):
+        B.glam_project_bwd(self.gauss, self.proj, self.vt.views, self.flags, self.g2d, self.dgs, s or self.stream())
+
+    def decode_bwd(self, s=None):
+        if not self.plain:
+            g = self.pgrad
+            B.glam_decode_bwd(self.anchors, self.params["mlp"], self.n_parts, self.vt.views, self.flags, self.dgs,
+                              g["feat"], g["offs"], g["log_scale"], g["mlp"], self.ws_dec, self.ws_dec.numel(),
+                              s or self.stream())
 
     def forward(self, s=None):
         self.decode(s)

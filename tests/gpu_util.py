@@ -11,6 +11,7 @@ AMB_VALUE = oracle.AMB_ALPHA | oracle.AMB_T | oracle.AMB_DEPTH
 
 def run(scene, steps=1):
     pipe = Pipeline(scene, device="cuda")
+    pipe.count_evaluations()
     pipe.fit_capacity()
     pipe.status.zero_()
     for _ in range(steps):
@@ -31,6 +32,7 @@ def host(pipe):
              ranges=pipe.ranges.cpu().numpy().reshape(-1, 2).astype(np.int64),
              image=pipe.image.cpu().numpy(), T_final=pipe.T_final.cpu().numpy(),
              n_contrib=pipe.n_contrib.cpu().numpy(), dimage=pipe.dimage.cpu().numpy(),
+             n_eval=None if pipe.n_eval is None else pipe.n_eval.cpu().numpy(),
              loss=pipe.loss.cpu().numpy(), g2d=pipe.g2d.cpu().numpy())
     if not pipe.plain:
         h["dec"] = {k: v.cpu().numpy() for k, v in pipe.dec.items()}

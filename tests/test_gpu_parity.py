@@ -106,6 +106,7 @@ def test_render_fwd_stagewise(case):
         assert err.max() <= 1e-4, err.max()
         assert np.abs(view_pixels(h, sl, "T_final") - ref["T_final"])[ok].max() <= 1e-4
         assert np.array_equal(view_pixels(h, sl, "n_contrib")[ok], ref["n_contrib"][ok])
+        assert np.array_equal(view_pixels(h, sl, "n_eval")[ok], ref["n_eval"][ok])
         # ambiguous pixels stay within the loose bound
         assert np.abs(img - ref["image"]).max() <= 0.02 or (~ok).sum() > 0
 
