@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched-vs-plain comparison")
     ap.add_argument("--stage-iters", type=int, default=10)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); partitions shard across GPUs "
@@ -187,6 +189,14 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                 "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
                         f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * 262144, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": "mapping iters/s fwd+bwd (500k Gaussians, 1226x370); batched vs plain speedup",

@@ -72,6 +72,59 @@ __device__ __forceinline__ bool box_meets(float bxf, float byf, const TileGeom& 
   return x0 <= g.qx1 && x1 >= g.qx0 && y0 <= g.qy1 && y1 >= g.qy0;
 }
 
+// Per-lane component index of the values reduce9 leaves in lanes 16r + k (k < 3), or -1:
+// the same swaps applied to the value tags (the swap instructions move whole rows, so
+// each lane's two swap outputs always belong to one component).
+struct Reduce9Map {
+  int comp;
+};
+
+__device__ __forceinline__ uint32_t swap32_first(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_permlane32_swap(a, b, false, false)[0];
+}
+__device__ __forceinline__ uint32_t swap16_first(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_permlane16_swap(a, b, false, false)[0];
+}
+
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_sum(float v) {
+  v += dpp<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
+  return v;
+}
+
+__device__ __forceinline__ Reduce9Map reduce9_map() {
+  const uint32_t none = 0xffffffffu;
+  const uint32_t w0 = swap32_first(0, 1), w1 = swap32_first(2, 3), w2 = swap32_first(4, 5), w3 = swap32_first(6, 7),
+                 w4 = swap32_first(8, none);
+  const uint32_t x0 = swap16_first(w0, w1), x1 = swap16_first(w2, w3), x2 = swap16_first(w4, none);
+  const int k = threadIdx.x & 15;
+  Reduce9Map m;
+  m.comp = k == 0 ? (int)x0 : (k == 1 ? (int)x1 : (k == 2 ? (int)x2 : -1));
+  return m;
+}
+
+// Sum of nine per-lane values over the wave, scattered so that nine lanes hold one
+// total each (reduce-scatter): two cross-half swaps halve the values per lane, then
+// each 16-lane row is reduced with DPP.  The caller's wave must be fully active.
+__device__ __forceinline__ float reduce9(const float v[9], const Reduce9Map& m) {
+  const float w0 = swap32_sum(v[0], v[1]), w1 = swap32_sum(v[2], v[3]), w2 = swap32_sum(v[4], v[5]),
+              w3 = swap32_sum(v[6], v[7]), w4 = swap32_sum(v[8], 0.f);
+  const float x0 = row_sum(swap16_sum(w0, w1)), x1 = row_sum(swap16_sum(w2, w3)), x2 = row_sum(swap16_sum(w4, 0.f));
+  const int k = threadIdx.x & 15;
+  return k == 0 ? x0 : (k == 1 ? x1 : x2);
+}
+
 __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict__ splat,
                                                          const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ ranges,
@@ -79,7 +132,9 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
                                                          const float* bg, float* image, float* T_final,
                                                          int32_t* n_contrib, int32_t* n_eval, uint32_t capacity,
                                                          uint32_t n_gauss) {
-  __shared__ float4 s_rec[3][kBatch];
+  __shared__ float4 s_r0[kBatch], s_r1[kBatch];
+  __shared__ float s_b[kBatch];
+  __shared__ uint2 s_box[kBatch];
   const int tile = blockIdx.x;
   const TileGeom tg = tile_geom(views, n_views, tile);
   const int t = threadIdx.x, lane = t & 63;
@@ -96,43 +151,45 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
     if (j < e) {
       const uint32_t gid = min(vals[j], n_gauss - 1);
       const float4* r = reinterpret_cast<const float4*>(splat + (size_t)gid * kSplatWords);
-      s_rec[0][t] = r[0];
-      s_rec[1][t] = r[1];
-      s_rec[2][t] = r[2];
+      s_r0[t] = r[0];
+      s_r1[t] = r[1];
+      const float4 r2 = r[2];
+      s_b[t] = r2.x;
+      s_box[t] = make_uint2(__float_as_uint(r2.y), __float_as_uint(r2.z));
     }
     __syncthreads();
     const int nb = (int)min((uint32_t)kBatch, e - b0);
+    const int base = (int)(b0 - s) + 1;
     if (quad_live && __ballot(!done) != 0) {
-      for (int k = 0; k < 4; ++k) {
+      bool wave_done = false;
+      for (int k = 0; k < 4 && !wave_done; ++k) {
         const int idx = 64 * k + lane;
-        const bool hit = idx < nb && box_meets(s_rec[2][idx].y, s_rec[2][idx].z, tg);
+        const bool hit = idx < nb && box_meets(__uint_as_float(s_box[idx].x), __uint_as_float(s_box[idx].y), tg);
         uint64_t m = __ballot(hit);
         while (m) {
-          const int bit = __ffsll((unsigned long long)m) - 1;
+          const int i = 64 * k + (int)__builtin_ctzll(m);
           m &= m - 1;
-          const int i = 64 * k + bit;
-          if (!done) {
-            const float4 r0 = s_rec[0][i], r1 = s_rec[1][i], r2 = s_rec[2][i];
-            float dx, dy, ep, raw;
-            const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
-            if (alpha >= kAlphaMin) {
-              const float Tn = T * (1.f - alpha);
-              if (Tn < kTMin) {
-                done = true;
-                stop = (int)(b0 - s) + i + 1;
-              } else {
-                const float wgt = alpha * T;
-                C0 = fmaf(r1.z, wgt, C0);
-                C1 = fmaf(r1.w, wgt, C1);
-                C2 = fmaf(r2.x, wgt, C2);
-                T = Tn;
-                last = (int)(b0 - s) + i + 1;
-              }
-            }
+          const float4 r0 = s_r0[i], r1 = s_r1[i];
+          const float cb = s_b[i];
+          float dx, dy, ep, raw;
+          const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+          const float Tn = T * (1.f - alpha);
+          const bool ok = !done && alpha >= kAlphaMin;
+          const bool halt = ok && Tn < kTMin;
+          const bool take = ok && !(Tn < kTMin);
+          const float wgt = take ? alpha * T : 0.f;
+          C0 = fmaf(r1.z, wgt, C0);
+          C1 = fmaf(r1.w, wgt, C1);
+          C2 = fmaf(cb, wgt, C2);
+          T = take ? Tn : T;
+          last = take ? base + i : last;
+          stop = halt ? base + i : stop;
+          done = done || halt;
+          if (__ballot(!done) == 0) {
+            wave_done = true;
+            break;
           }
-          if (__ballot(!done) == 0) break;
         }
-        if (__ballot(!done) == 0) break;
       }
     }
     __syncthreads();
@@ -158,7 +215,9 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restr
                                                             const float* bg, const float* T_final,
                                                             const int32_t* n_contrib, const float* dimage,
                                                             float* g2d, uint32_t capacity, uint32_t n_gauss) {
-  __shared__ float4 s_rec[3][kBatch];
+  __shared__ float4 s_r0[kBatch], s_r1[kBatch];
+  __shared__ float s_b[kBatch];
+  __shared__ uint2 s_box[kBatch];
   __shared__ uint32_t s_gid[kBatch];
   __shared__ int s_max;
   const int tile = blockIdx.x;
@@ -168,6 +227,7 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restr
   const uint32_t s = min(ranges[2 * tile], e);
   const float px = tg.x + 0.5f, py = tg.y + 0.5f;
   const bool quad_live = tg.qx0 <= tg.qx1 && tg.qy0 <= tg.qy1;
+  const Reduce9Map rmap = reduce9_map();
   float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   float B0 = bg ? bg[0] : 0.f, B1 = bg ? bg[1] : 0.f, B2 = bg ? bg[2] : 0.f;
   int last = 0;
@@ -190,59 +250,52 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restr
     if (t < nb) {
       const uint32_t gid = min(vals[s + lo + t], n_gauss - 1);
       const float4* r = reinterpret_cast<const float4*>(splat + (size_t)gid * kSplatWords);
-      s_rec[0][t] = r[0];
-      s_rec[1][t] = r[1];
-      s_rec[2][t] = r[2];
+      s_r0[t] = r[0];
+      s_r1[t] = r[1];
+      const float4 r2 = r[2];
+      s_b[t] = r2.x;
+      s_box[t] = make_uint2(__float_as_uint(r2.y), __float_as_uint(r2.z));
       s_gid[t] = gid;
     }
     __syncthreads();
     if (quad_live && __ballot(last > lo) != 0) {
       for (int k = 3; k >= 0; --k) {
         const int idx = 64 * k + lane;
-        const bool hit = idx < nb && box_meets(s_rec[2][idx].y, s_rec[2][idx].z, tg);
+        const bool hit = idx < nb && box_meets(__uint_as_float(s_box[idx].x), __uint_as_float(s_box[idx].y), tg);
         uint64_t m = __ballot(hit);
         while (m) {
           const int bit = 63 - __clzll((unsigned long long)m);
           m &= ~(1ull << bit);
           const int i = 64 * k + bit;
-          const int entry = lo + i;
-          const float4 r0 = s_rec[0][i], r1 = s_rec[1][i], r2 = s_rec[2][i];
-          float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-          bool contrib = false;
-          if (entry < last) {
-            float dx, dy, ep, raw;
-            const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
-            if (alpha >= kAlphaMin) {
-              contrib = true;
-              T = T * __builtin_amdgcn_rcpf(1.f - alpha);  // T in front of this Gaussian
-              const float wgt = alpha * T;
-              v[6] = g0 * wgt;
-              v[7] = g1 * wgt;
-              v[8] = g2 * wgt;
-              const float dal = T * (g0 * (r1.z - B0) + g1 * (r1.w - B1) + g2 * (r2.x - B2));
-              B0 = fmaf(alpha, r1.z - B0, B0);
-              B1 = fmaf(alpha, r1.w - B1, B1);
-              B2 = fmaf(alpha, r2.x - B2, B2);
-              if (raw <= kAlphaMax) {
-                v[5] = dal * ep;
-                const float dp = dal * alpha;
-                v[0] = -dp * (r0.z * dx + r0.w * dy);
-                v[1] = -dp * (r0.w * dx + r1.x * dy);
-                v[2] = -0.5f * dp * dx * dx;
-                v[3] = -dp * dx * dy;
-                v[4] = -0.5f * dp * dy * dy;
-              }
-            }
-          }
-          if (__ballot(contrib) != 0) {
-            float sum[9];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) sum[c] = wave_sum(v[c]);
-            float mine = sum[0];
-#pragma unroll
-            for (int c = 1; c < 9; ++c) mine = lane == c ? sum[c] : mine;
-            if (lane < 9) atomicAdd(&g2d[(size_t)s_gid[i] * 9 + lane], mine);
-          }
+          const float4 r0 = s_r0[i], r1 = s_r1[i];
+          const float cb = s_b[i];
+          float dx, dy, ep, raw;
+          const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+          const bool contrib = lo + i < last && alpha >= kAlphaMin;
+          if (__ballot(contrib) == 0) continue;
+          // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
+          T = contrib ? T * __builtin_amdgcn_rcpf(1.f - alpha) : T;
+          const float wgt = contrib ? alpha * T : 0.f;
+          const float dal = contrib ? T * (g0 * (r1.z - B0) + g1 * (r1.w - B1) + g2 * (cb - B2)) : 0.f;
+          const float aB = contrib ? alpha : 0.f;
+          B0 = fmaf(aB, r1.z - B0, B0);
+          B1 = fmaf(aB, r1.w - B1, B1);
+          B2 = fmaf(aB, cb - B2, B2);
+          const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
+          const float dop = free_alpha ? dal * ep : 0.f;
+          const float dp = free_alpha ? dal * alpha : 0.f;
+          float v[9];
+          v[0] = -dp * (r0.z * dx + r0.w * dy);
+          v[1] = -dp * (r0.w * dx + r1.x * dy);
+          v[2] = -0.5f * dp * dx * dx;
+          v[3] = -dp * dx * dy;
+          v[4] = -0.5f * dp * dy * dy;
+          v[5] = dop;
+          v[6] = g0 * wgt;
+          v[7] = g1 * wgt;
+          v[8] = g2 * wgt;
+          const float tot = reduce9(v, rmap);
+          if (rmap.comp >= 0) atomicAdd(&g2d[(size_t)s_gid[i] * 9 + rmap.comp], tot);
         }
       }
     }
