@@ -161,7 +161,11 @@ typedef struct {
                        pixel box x0|x1<<16 and y0|y1<<16 as bits, depth)            */
 } glam_projected;
 
-/* Sorted (tile, Gaussian) pairs and per-tile ranges. */
+/* Words of the compositing work-queue buffer (two kernels x (16 counters on separate
+   128-byte lines + an exit count)). */
+#define GLAM_QUEUE_WORDS 1088
+
+/* Sorted (tile, Gaussian) pairs, per-tile ranges and the compositing work order. */
 typedef struct {
   uint64_t* keys;   /* [capacity] sorted keys: tile << depth_bits | depth key        */
   uint32_t* vals;   /* [capacity] sorted view-Gaussian indices                       */
@@ -170,6 +174,11 @@ typedef struct {
   int32_t* status;  /* [8] device: [0] sticky status, [1] pair count (low word),
                        [2..3] required capacity (int64), [4] depth key bits,
                        [5] tile key bits, [6] radix passes; caller zeroes [0] once   */
+  uint32_t* order;  /* [n_tiles] tiles by decreasing range length (power-of-two
+                       classes), the order the compositing queue hands them out       */
+  uint32_t* queue;  /* [GLAM_QUEUE_WORDS] device work-queue counters of the
+                       compositing kernels; caller zeroes them once, every launch
+                       leaves them zeroed                                             */
 } glam_bins;
 
 /* Workspace bytes glam_bin_sort needs for this view table and pair capacity. */
@@ -196,13 +205,15 @@ glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, u
 
 /* Tile binning and device LSD radix sort by (global tile, depth): pairs emitted per
    view-Gaussian in index order (row-major over its tiles), stable sort, so equal
-   depths keep index order.  ranges of empty tiles are [0, 0). */
+   depths keep index order.  ranges of empty tiles are [0, 0).  Also writes order
+   (longest ranges first) for the compositing work queue. */
 glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, glam_bins* bins,
                           void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Eq. 1 per pixel centre (x+0.5, y+0.5), front to back over its tile's range:
    alpha = min(0.99, opacity exp(power)), skipped when alpha < 1/255, the walk stops
-   before an entry that would take T below 1e-4.  Writes image [3][H][W] per view,
+   before an entry that would take T below 1e-4.  A persistent grid pulls (tile,
+   quadrant) items from bins->queue in bins->order.  Writes image [3][H][W] per view,
    final transmittance T_final and n_contrib (1 + range position of the last
    composited entry) per pixel.  bg: [3] device (background colour, may be NULL).
    n_eval (may be NULL): per pixel, the range entries visited up to and including the

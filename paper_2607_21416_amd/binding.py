@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libglam.so")
 GLAM_OK, GLAM_ERR_INVALID_ARG, GLAM_ERR_WORKSPACE, GLAM_ERR_CAPACITY, GLAM_ERR_HIP, GLAM_ERR_UNSUPPORTED = range(6)
 GLAM_PLAIN = 1
 GLAM_OPACITY_SIGMOID = 2
+GLAM_QUEUE_WORDS = 1088
 
 EXPORTS = [
     "glam_status_string", "glam_mlp_param_count", "glam_views_build", "glam_bin_sort_workspace_bytes",
@@ -67,7 +68,7 @@ class Projected(C.Structure):
 
 class Bins(C.Structure):
     _fields_ = [("keys", C.c_void_p), ("vals", C.c_void_p), ("ranges", C.c_void_p), ("capacity", C.c_int64),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("order", C.c_void_p), ("queue", C.c_void_p)]
 
 
 class Grads(C.Structure):

@@ -68,8 +68,8 @@ bool proj_ok(const glam_projected* p) {
 }
 
 bool bins_ok(const glam_bins* b) {
-  return b && ok_ptr(b->keys) && ok_ptr(b->vals) && ok_ptr(b->ranges) && ok_ptr(b->status) && b->capacity > 0 &&
-         b->capacity < (1ll << 32);
+  return b && ok_ptr(b->keys) && ok_ptr(b->vals) && ok_ptr(b->ranges) && ok_ptr(b->status) && ok_ptr(b->order) &&
+         ok_ptr(b->queue) && b->capacity > 0 && b->capacity < (1ll << 32);
 }
 
 int max_partition(const glam_views* v) {

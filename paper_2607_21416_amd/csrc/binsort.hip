@@ -37,8 +37,10 @@ struct Plan {
   uint32_t pad[10];
 };
 
+constexpr int kLptBuckets = 32;
+
 struct Layout {
-  size_t partial_sum, partial_max, plan, keys_alt, vals_alt, hist, digit_total, total;
+  size_t partial_sum, partial_max, plan, keys_alt, vals_alt, hist, digit_total, lpt, total;
   int n_scan_blocks, n_sort_blocks;
 };
 
@@ -58,6 +60,7 @@ Layout layout(long long n_gauss, long long capacity) {
   L.vals_alt = o; o = align256(o + 4ull * (size_t)capacity);
   L.hist = o; o = align256(o + 4ull * kRadix * L.n_sort_blocks);
   L.digit_total = o; o = align256(o + 4ull * kRadix);
+  L.lpt = o; o = align256(o + 4ull * 2 * kLptBuckets);
   L.total = o;
   return L;
 }
@@ -349,9 +352,54 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
   }
 }
 
-__global__ void ranges_clear_kernel(uint32_t* ranges, long long n) {
+__global__ void ranges_clear_kernel(uint32_t* ranges, long long n, uint32_t* lpt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) ranges[i] = 0u;
+  if (i < 2 * kLptBuckets) lpt[i] = 0u;
+}
+
+// Work order of the compositing queue: tiles by power-of-two class of their range
+// length, longest first (empty tiles last).  Counting sort over 32 classes; the order
+// inside a class is arbitrary (it only schedules work).
+__device__ __forceinline__ int lpt_bucket(const uint32_t* ranges, long long t) {
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  const int bits = len ? 32 - __clz(len) : 0;  // bit length
+  return min(kLptBuckets - 1, 32 - bits);
+}
+
+__global__ void __launch_bounds__(256) lpt_count_kernel(const uint32_t* ranges, long long n_tiles, uint32_t* lpt) {
+  __shared__ uint32_t h[kLptBuckets];
+  if (threadIdx.x < kLptBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tiles) atomicAdd(&h[lpt_bucket(ranges, t)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kLptBuckets && h[threadIdx.x]) atomicAdd(&lpt[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t* ranges, long long n_tiles, uint32_t* lpt,
+                                                          uint32_t* order) {
+  __shared__ uint32_t base[kLptBuckets], h[kLptBuckets], blk[kLptBuckets];
+  if (threadIdx.x < kLptBuckets) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kLptBuckets; ++b) { base[b] = run; run += lpt[b]; }
+  }
+  __syncthreads();
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  uint32_t local = 0;
+  if (t < n_tiles) {
+    b = lpt_bucket(ranges, t);
+    local = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kLptBuckets) blk[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&lpt[kLptBuckets + threadIdx.x], h[threadIdx.x]) : 0u;
+  __syncthreads();
+  if (t < n_tiles) {
+    const uint32_t pos = base[b] + blk[b] + local;
+    if (pos < (uint64_t)n_tiles) order[pos] = (uint32_t)t;
+  }
 }
 
 __global__ void ranges_mark_kernel(const Plan* plan, const uint64_t* keys, uint32_t* ranges, long long n_tiles) {
@@ -400,10 +448,15 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                        L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
   }
   const long long nr = 2 * v.n_tiles;
-  hipLaunchKernelGGL(ranges_clear_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, bins.ranges, nr);
+  uint32_t* lpt = reinterpret_cast<uint32_t*>(w + L.lpt);
+  hipLaunchKernelGGL(ranges_clear_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, bins.ranges, nr, lpt);
   if (bins.capacity > 0)
     hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,
                        bins.keys, bins.ranges, (long long)v.n_tiles);
+  const unsigned tb = (unsigned)((v.n_tiles + 255) / 256);
+  hipLaunchKernelGGL(lpt_count_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt);
+  hipLaunchKernelGGL(lpt_scatter_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt,
+                     bins.order);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

@@ -160,8 +160,10 @@ class Pipeline:
         self.keys = torch.empty(self.capacity, device=dev, dtype=torch.int64)
         self.vals = torch.empty(self.capacity, device=dev, dtype=torch.int32)
         self.ranges = torch.empty(2 * self.vt.n_tiles, device=dev, dtype=torch.int32)
+        self.order = torch.empty(self.vt.n_tiles, device=dev, dtype=torch.int32)
+        self.queue = torch.zeros(B.GLAM_QUEUE_WORDS, device=dev, dtype=torch.int32)
         self.bins = B.Bins(self.keys.data_ptr(), self.vals.data_ptr(), self.ranges.data_ptr(), self.capacity,
-                           self.status.data_ptr())
+                           self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr())
         nb = B.glam_bin_sort_workspace_bytes(self.vt.views, self.capacity)
         self.ws_sort = torch.empty(nb, device=dev, dtype=torch.uint8)
 

@@ -89,12 +89,12 @@ def test_calls_reject_before_launch():
     proj = B.Projected(fake, fake, fake, fake, fake, fake)
     g_wrong = B.Gaussians(fake, fake, fake, fake, fake, 11)  # plain G must match the view table
     assert lib.glam_project(B.ref(g_wrong), B.ref(views), B.GLAM_PLAIN, B.ref(proj), None) == B.GLAM_ERR_INVALID_ARG
-    bins = B.Bins(fake, fake, fake, 1000, fake)
+    bins = B.Bins(fake, fake, fake, 1000, fake, fake, fake)
     need = lib.glam_bin_sort_workspace_bytes(B.ref(views), 1000)
     assert need > 12000
     assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins), C.c_void_p(fake), need - 1,
                              None) == B.GLAM_ERR_WORKSPACE
-    bins0 = B.Bins(fake, fake, fake, 0, fake)
+    bins0 = B.Bins(fake, fake, fake, 0, fake, fake, fake)
     assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins0), C.c_void_p(fake), need,
                              None) == B.GLAM_ERR_INVALID_ARG
     # anchor decode: unsupported feature width / offset count
