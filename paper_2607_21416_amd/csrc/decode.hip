@@ -277,22 +277,41 @@ __device__ __forceinline__ void store_dW2(const f4* dW2, float* red, int l) {
       }
 }
 
+// Work split of the adjoint: partition m owns workgroups [first[m], first[m+1]) of a 1-D
+// grid (about one workgroup per CU, shared in proportion to the partitions' anchor
+// counts); leader[m] is the first of the partition's (consecutive) views.
+constexpr int kMaxBwdParts = 256;
+constexpr int kBwdWaves = 4;
+struct BwdGrid {
+  int n_parts;
+  int first[kMaxBwdParts + 1];
+  int leader[kMaxBwdParts];
+  int n_views_of[kMaxBwdParts];
+};
+
+// Orders this wave's LDS traffic (the waves of a workgroup run independently).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int F, int K>
-__global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
-                                                         const glam_view_info* views, int n_views, int sigmoid_op,
-                                                         glam_gaussians dg, int blocks_per_part, float* dfeat,
-                                                         float* doffs, float* dlog_scale, float* partial) {
+__global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
+                                                                    const glam_view_info* views, int sigmoid_op,
+                                                                    glam_gaussians dg, BwdGrid grid, float* dfeat,
+                                                                    float* doffs, float* dlog_scale, float* partial) {
   using C = Cfg<F, K>;
   constexpr MlpOff O = mlp_offsets(F, K);
   constexpr int NT2 = 2 * (C::OT0 + C::OT1 + C::OT2);
   constexpr int NC1 = (C::NIN + 15) / 16;
   extern __shared__ float smem[];
-  const int v0 = blockIdx.y;
+  // partition of this workgroup
+  int m = 0;
+  while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
+  const int b_local = blockIdx.x - grid.first[m], nb = grid.first[m + 1] - grid.first[m];
+  const int v0 = grid.leader[m], v1 = v0 + grid.n_views_of[m];
   const glam_view_info lead = views[v0];
-  const int m = lead.cam.partition;
-  if (v0 > 0 && views[v0 - 1].cam.partition == m) return;  // not the first view of the run
-  int v1 = v0 + 1;
-  while (v1 < n_views && views[v1].cam.partition == m) ++v1;
   const int A = lead.anchor_count;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
   float* s_p = smem;
@@ -301,8 +320,8 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
   float* s_y = s_z + 16 * C::ZS;
   float* s_h = s_y + 16 * C::YS;
   float* s_ds = s_h + 16 * C::HS;
-  const float* pm = mlp + (size_t)m * C::P;
-  for (int i = t; i < C::P; i += 256) s_p[i] = pm[i];
+  const float* pm = mlp + (size_t)lead.cam.partition * C::P;
+  for (int i = t; i < C::P; i += 64 * kBwdWaves) s_p[i] = pm[i];
   __syncthreads();
   f4 dW2[NT2];
   f4 dW1[6 * NC1];
@@ -318,13 +337,8 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
   const long long n = dg.n;
   const size_t GK = (size_t)an.A * K;
   const int n_chunks = (A + 15) / 16;
-  // every wave walks chunks with a grid stride inside the partition; all waves run the
-  // same number of iterations so the workgroup barriers line up
-  const int stride = blocks_per_part * 4;
-  const int iters = (n_chunks + stride - 1) / stride;
-  for (int it = 0; it < iters; ++it) {
-    const int chunk = it * stride + blockIdx.x * 4 + w;
-    const bool live = chunk < n_chunks;
+  // each wave walks its chunks independently: no workgroup barrier until the end
+  for (int chunk = b_local * kBwdWaves + w; chunk < n_chunks; chunk += nb * kBwdWaves) {
     const int a0 = chunk * 16;
     f4 dZ[F / 16];
 #pragma unroll
@@ -333,8 +347,8 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
     if (l < 16) s_ds[l] = 0.f;
     for (int v = v0; v < v1; ++v) {
       const glam_view_info vw = views[v];
-      build_z<F, K>(an, vw, a0, s_z, l);  // zero rows when the chunk is past the partition
-      __syncthreads();
+      build_z<F, K>(an, vw, a0, s_z, l);  // zero rows past the partition
+      wave_sync();
       f4 H[6];
       layer1<F, K>(s_p, s_z, l, H);
       layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
@@ -345,14 +359,14 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
       for (int mt = 0; mt < 6; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = H[mt][r];
-      __syncthreads();
+      wave_sync();
       // activation adjoints, one lane per Gaussian; dY overwrites Y in place
       for (int q = 0; q < 3; ++q) {
         const int gi = l + 64 * q;
         if (gi >= 16 * K) break;
         const int ai = gi / K, j = gi % K, a = a0 + ai;
         float* y = s_y + ai * C::YS;
-        if (!live || a >= A) {
+        if (a >= A) {
           y[j] = 0.f;
           for (int c = 0; c < 3; ++c) y[K + 3 * j + c] = 0.f;
           for (int k = 0; k < 7; ++k) y[4 * K + 7 * j + k] = 0.f;
@@ -362,7 +376,6 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
         const long long g = vw.g_begin + (long long)a * K + j;
         const float es = expf(an.log_scale[ga]);
         float ds = 0.f;
-        // opacity
         const float yo = y[j];
         const float dop = dg.opacity[g];
         if (sigmoid_op) {
@@ -396,7 +409,7 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
         }
         atomicAdd(&s_ds[ai], ds);
       }
-      __syncthreads();
+      wave_sync();
       // dH = W2^T dY, masked by the ReLU (H > 0 exactly where pre > 0)
       f4 dP[6];
       dhidden<F, K, 0>(s_p, s_y, l, dP);
@@ -430,13 +443,13 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
         if (o < C::NY)
           for (int an_ = 0; an_ < 16; ++an_) db2[i] += s_y[an_ * C::YS + o];
       }
-      __syncthreads();
+      wave_sync();
       // dPre to LDS (reusing the H buffer) for dW1 += dPre^T Z, db1 += sum dPre
 #pragma unroll
       for (int mt = 0; mt < 6; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dP[mt][r];
-      __syncthreads();
+      wave_sync();
 #pragma unroll
       for (int mt = 0; mt < 6; ++mt)
 #pragma unroll
@@ -457,32 +470,31 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
         if (h < 96)
           for (int an_ = 0; an_ < 16; ++an_) db1[i] += s_h[an_ * C::HS + h];
       }
-      __syncthreads();
+      wave_sync();
     }
     // anchor gradients of this chunk (all views summed)
-    if (live) {
 #pragma unroll
-      for (int ft = 0; ft < F / 16; ++ft)
+    for (int ft = 0; ft < F / 16; ++ft)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = a0 + li;
-          if (a < A) dfeat[(size_t)(lead.anchor_begin + a) * F + ft * 16 + 4 * lg + r] = dZ[ft][r];
-        }
-      if (l < 16 && a0 + l < A) dlog_scale[lead.anchor_begin + a0 + l] = s_ds[l];
-      for (int q = 0; q < 3; ++q) {
-        const int gi = l + 64 * q;
-        if (gi >= 16 * K) break;
-        const int ai = gi / K, j = gi % K, a = a0 + ai;
-        if (a >= A) continue;
-        const size_t go = (size_t)(lead.anchor_begin + a) * K + j;
-        for (int i = 0; i < 3; ++i) doffs[i * GK + go] = doff[q][i];
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + li;
+        if (a < A) dfeat[(size_t)(lead.anchor_begin + a) * F + ft * 16 + 4 * lg + r] = dZ[ft][r];
       }
+    if (l < 16 && a0 + l < A) dlog_scale[lead.anchor_begin + a0 + l] = s_ds[l];
+    for (int q = 0; q < 3; ++q) {
+      const int gi = l + 64 * q;
+      if (gi >= 16 * K) break;
+      const int ai = gi / K, j = gi % K, a = a0 + ai;
+      if (a >= A) continue;
+      const size_t go = (size_t)(lead.anchor_begin + a) * K + j;
+      for (int i = 0; i < 3; ++i) doffs[i * GK + go] = doff[q][i];
     }
-    __syncthreads();
+    wave_sync();
   }
   // workgroup reduction of the weight gradients into the packed layout
+  __syncthreads();
   float* red = s_p;
-  for (int i = t; i < C::P; i += 256) red[i] = 0.f;
+  for (int i = t; i < C::P; i += 64 * kBwdWaves) red[i] = 0.f;
   __syncthreads();
   store_dW2<F, K, 0, C::OT0, 0>(dW2, red, l);
   store_dW2<F, K, 1, C::OT1, 2 * C::OT0>(dW2, red, l);
@@ -509,23 +521,33 @@ __global__ void __launch_bounds__(256) decode_bwd_kernel(glam_anchors an, const 
     if (h < 96) atomicAdd(&red[O.b1[h >> 5] + (h & 31)], db1[i]);
   }
   __syncthreads();
-  float* dst = partial + ((size_t)m * blocks_per_part + blockIdx.x) * C::P;
-  for (int i = t; i < C::P; i += 256) dst[i] = red[i];
+  float* dst = partial + (size_t)blockIdx.x * C::P;
+  for (int i = t; i < C::P; i += 64 * kBwdWaves) dst[i] = red[i];
 }
 
-// dmlp[m] = sum of the partials of partition m (zero for partitions without views).
-__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* partial, int blocks_per_part, int P,
-                                                              const glam_view_info* views, int n_views,
+// dmlp[m] = sum of partition m's workgroup partials (zero for partitions without
+// views).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
+__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* partial, BwdGrid grid, int P, int M,
                                                               float* dmlp) {
-  const int m = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= P) return;
-  bool has = false;
-  for (int v = 0; v < n_views; ++v) has |= views[v].cam.partition == m;
-  float s = 0.f;
-  if (has)
-    for (int b = 0; b < blocks_per_part; ++b) s += partial[((size_t)m * blocks_per_part + b) * P + i];
-  dmlp[(size_t)m * P + i] = s;
+  __shared__ float s[16][17];
+  const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + c;
+  const int slot = blockIdx.y;  // index into grid (partitions with views)
+  float acc = 0.f;
+  if (i < P)
+    for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16) acc += partial[(size_t)b * P + i];
+  s[r][c] = acc;
+  __syncthreads();
+  if (r == 0 && i < P) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += s[k][c];
+    dmlp[(size_t)grid.leader[slot] * P + i] = t;  // leader holds the partition index here
+  }
+}
+
+__global__ void zero_f32_kernel(float* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
 }
 
 template <int F, int K>
@@ -537,7 +559,7 @@ size_t fwd_smem() {
 template <int F, int K>
 size_t bwd_smem() {
   using C = Cfg<F, K>;
-  return sizeof(float) * (C::PA + 4 * (16 * C::ZS + 16 * C::YS + 16 * C::HS + 16));
+  return sizeof(float) * (C::PA + kBwdWaves * (16 * C::ZS + 16 * C::YS + 16 * C::HS + 16));
 }
 
 // Raises a kernel's dynamic LDS limit above the 64 KiB default.  Not a stream operation;
@@ -555,12 +577,43 @@ int max_anchors(const glam_views& v) {
   return mx;
 }
 
-int blocks_per_part(const glam_views& v, int n_parts) {
-  const int chunks = (max_anchors(v) + 63) / 64;
-  int b = (1024 + n_parts - 1) / (n_parts > 0 ? n_parts : 1);
-  if (b > 256) b = 256;
-  if (b > chunks) b = chunks;
-  return b < 1 ? 1 : b;
+// One workgroup per CU in total, shared by the partitions in proportion to their anchor
+// counts (at least one each, never more than their 16-anchor chunks / 8 waves).
+int total_bwd_blocks() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return cus;
+}
+
+bool bwd_grid(const glam_views& v, BwdGrid& g) {
+  g.n_parts = 0;
+  long long total_anchors = 0;
+  for (int i = 0; i < v.n; ++i) {
+    const glam_view_info& vi = v.host[i];
+    if (i > 0 && v.host[i - 1].cam.partition == vi.cam.partition) {
+      ++g.n_views_of[g.n_parts - 1];
+      continue;
+    }
+    if (g.n_parts == kMaxBwdParts) return false;
+    g.leader[g.n_parts] = i;
+    g.n_views_of[g.n_parts] = 1;
+    ++g.n_parts;
+    total_anchors += vi.anchor_count;
+  }
+  const int budget = total_bwd_blocks();
+  int b = 0;
+  for (int k = 0; k < g.n_parts; ++k) {
+    const int A = v.host[g.leader[k]].anchor_count;
+    const int cap = (A + 16 * kBwdWaves - 1) / (16 * kBwdWaves);
+    int nb = total_anchors > 0 ? (int)((double)budget * A / (double)total_anchors + 0.5) : 1;
+    nb = nb < 1 ? 1 : (nb > cap ? (cap < 1 ? 1 : cap) : nb);
+    g.first[k] = b;
+    b += nb;
+  }
+  g.first[g.n_parts] = b;
+  return true;
 }
 
 template <int F, int K>
@@ -580,16 +633,23 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
                            const glam_gaussians& dg, float* dfeat, float* doffs, float* dls, float* dmlp, void* ws,
                            hipStream_t s) {
   using C = Cfg<F, K>;
-  const int bpp = blocks_per_part(v, n_parts);
+  BwdGrid g;
+  if (!bwd_grid(v, g)) return GLAM_ERR_UNSUPPORTED;
   float* partial = static_cast<float*>(ws);
-  if (v.n > 0 && max_anchors(v) > 0) {
+  // partitions without views get zero gradients
+  const long long nm = (long long)n_parts * C::P;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, dmlp, nm);
+  if (g.first[g.n_parts] > 0) {
     const size_t sm = bwd_smem<F, K>();
     if (!set_smem_limit((const void*)decode_bwd_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
-    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(bpp, v.n), dim3(256), sm, s, a, mlp, v.dev, v.n, sig ? 1 : 0, dg,
-                       bpp, dfeat, doffs, dls, partial);
+    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(g.first[g.n_parts]), dim3(64 * kBwdWaves), sm, s, a, mlp,
+                       v.dev, sig ? 1 : 0, dg, g, dfeat, doffs, dls, partial);
+    // the reduction writes dmlp[partition of slot k]: pass partitions in place of leaders
+    BwdGrid r = g;
+    for (int k = 0; k < g.n_parts; ++k) r.leader[k] = v.host[g.leader[k]].cam.partition;
+    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((C::P + 15) / 16, g.n_parts), dim3(256), 0, s, partial, r, C::P,
+                       n_parts, dmlp);
   }
-  hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((C::P + 255) / 256, n_parts), dim3(256), 0, s, partial, bpp, C::P,
-                     v.dev, v.n, dmlp);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -606,8 +666,11 @@ glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_vi
 }
 
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts) {
+  (void)n_parts;
   const MlpOff o = mlp_offsets(a.F, a.K);
-  return sizeof(float) * (size_t)o.total * (size_t)n_parts * (size_t)blocks_per_part(v, n_parts);
+  BwdGrid g;
+  if (!bwd_grid(v, g)) return 0;
+  return sizeof(float) * (size_t)o.total * (size_t)(g.first[g.n_parts] > 0 ? g.first[g.n_parts] : 1);
 }
 
 glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v, bool sig,
