@@ -109,7 +109,20 @@ void composite(int n, GetG getg, IsCand cand, const double* uv, const double* co
     prev_depth = depth[g];
     const double Tn = r.T * (1.0 - e.alpha);
     if (std::fabs(Tn - kTMin) < 1e-8) r.amb |= ORC_AMB_T;
-    if (Tn < kTMin) { r.n_eval = i + 1; break; }
+    if (Tn < kTMin) {
+      r.n_eval = i + 1;
+      // the stopping entry swapped with a near-tie that follows it changes which of
+      // the two is composited: look ahead over the entries of equal depth
+      for (int j = i + 1; j < n; ++j) {
+        const int h = getg(j);
+        if (std::fabs(depth[h] - depth[g]) >= 1e-6 * depth[g]) break;
+        if (!cand(j)) continue;
+        const double ch[3] = {conic[h], conic[(size_t)G + h], conic[2 * (size_t)G + h]};
+        if (evaluate(uv[h], uv[(size_t)G + h], ch, opacity[h], x, y).alpha > kAlphaMin - 1e-6)
+          r.amb |= ORC_AMB_DEPTH;
+      }
+      break;
+    }
     for (int c = 0; c < 3; ++c) r.C[c] += rgb[c * (size_t)G + g] * e.alpha * r.T;
     r.list.push_back({g, r.T, e});
     r.T = Tn;

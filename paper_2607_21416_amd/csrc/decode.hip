@@ -61,6 +61,29 @@ __host__ __device__ constexpr MlpOff mlp_offsets(int F, int K) {
   return o;
 }
 
+// The weights as staged in LDS: rows padded by one word (W1 rows F+5, W2 rows 33) so
+// that lanes reading one column of consecutive rows fall in different banks.
+struct LdsOff {
+  int w1[3], b1[3], w2[3], b2[3];
+  int total;
+};
+
+__host__ __device__ constexpr LdsOff lds_offsets(int F, int K) {
+  LdsOff o{};
+  const int w1s = F + 5, w2s = kHid + 1;
+  const int outs[3] = {K, 3 * K, 7 * K};
+  int off = 0;
+  for (int l = 0; l < 3; ++l) {
+    o.w1[l] = off;
+    o.b1[l] = off + kHid * w1s;
+    o.w2[l] = o.b1[l] + kHid;
+    o.b2[l] = o.w2[l] + outs[l] * w2s;
+    off = o.b2[l] + outs[l];
+  }
+  o.total = off;
+  return o;
+}
+
 template <int F, int K>
 struct Cfg {
   static constexpr int NIN = F + 4;
@@ -71,9 +94,35 @@ struct Cfg {
   static constexpr int HS = 3 * kHid + 1;   // LDS row stride of H
   static constexpr int OT0 = (K + 15) / 16, OT1 = (3 * K + 15) / 16, OT2 = (7 * K + 15) / 16;
   static constexpr int P = mlp_offsets(F, K).total;
-  static constexpr int PA = (P + 3) & ~3;
+  static constexpr int W1S = F + 5;         // LDS row stride of W1
+  static constexpr int W2S = kHid + 1;      // LDS row stride of W2
+  static constexpr int PA = (lds_offsets(F, K).total + 3) & ~3;  // LDS words of the weights
   static_assert(NIN % 4 == 0, "F + 4 must be a multiple of 4");
 };
+
+// Copies one packed MLP set into the padded LDS layout.
+template <int F, int K>
+__device__ __forceinline__ void load_weights(const float* pm, float* s, int t, int nthreads) {
+  using C = Cfg<F, K>;
+  constexpr MlpOff O = mlp_offsets(F, K);
+  constexpr LdsOff L = lds_offsets(F, K);
+  for (int i = t; i < C::P; i += nthreads) {
+    const int l = i < O.w1[1] ? 0 : (i < O.w1[2] ? 1 : 2);
+    const int j = i - O.w1[l];
+    int dst;
+    if (j < kHid * C::NIN) {
+      dst = L.w1[l] + (j / C::NIN) * C::W1S + j % C::NIN;
+    } else if (j < kHid * C::NIN + kHid) {
+      dst = L.b1[l] + (j - kHid * C::NIN);
+    } else if (j < O.b2[l] - O.w1[l]) {
+      const int jj = j - kHid * C::NIN - kHid;
+      dst = L.w2[l] + (jj / kHid) * C::W2S + jj % kHid;
+    } else {
+      dst = L.b2[l] + (j - (O.b2[l] - O.w1[l]));
+    }
+    s[dst] = pm[i];
+  }
+}
 
 __device__ __forceinline__ void camera_centre(const glam_camera& c, float xc[3]) {
   for (int i = 0; i < 3; ++i) xc[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
@@ -111,12 +160,12 @@ __device__ __forceinline__ void build_z(const glam_anchors& an, const glam_view_
 template <int F, int K>
 __device__ __forceinline__ void layer1(const float* p, const float* z, int l, f4 H[6]) {
   using C = Cfg<F, K>;
-  constexpr MlpOff O = mlp_offsets(F, K);
+  constexpr LdsOff O = lds_offsets(F, K);
   const int li = l & 15, lg = l >> 4;
 #pragma unroll
   for (int mt = 0; mt < 6; ++mt) {
     const int h = mt * 16 + li, ml = h >> 5, hi = h & 31;
-    const float* W1 = p + O.w1[ml] + hi * C::NIN;
+    const float* W1 = p + O.w1[ml] + hi * C::W1S;
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < C::KS1; ++ks) acc = mfma(W1[ks * 4 + lg], z[li * C::ZS + ks * 4 + lg], acc);
@@ -134,6 +183,7 @@ template <int F, int K, int ML, int OT>
 __device__ __forceinline__ void layer2(const float* p, const f4 H[6], float* y, int l) {
   using C = Cfg<F, K>;
   constexpr MlpOff O = mlp_offsets(F, K);
+  constexpr LdsOff Ls = lds_offsets(F, K);
   const int li = l & 15, lg = l >> 4;
   constexpr int out = O.out[ML];
 #pragma unroll
@@ -145,60 +195,76 @@ __device__ __forceinline__ void layer2(const float* p, const f4 H[6], float* y, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int hc = t2 * 16 + 4 * lg + r;
-        const float a = o < out ? p[O.w2[ML] + o * kHid + hc] : 0.f;
+        const float a = o < out ? p[Ls.w2[ML] + o * C::W2S + hc] : 0.f;
         acc = mfma(a, H[2 * ML + t2][r], acc);
       }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int orow = ot * 16 + 4 * lg + r;
-      if (orow < out) y[li * C::YS + O.yoff[ML] + orow] = acc[r] + p[O.b2[ML] + orow];
+      if (orow < out) y[li * C::YS + O.yoff[ML] + orow] = acc[r] + p[Ls.b2[ML] + orow];
     }
   }
 }
 
+// Orders one wave's LDS writes before its later reads by other lanes of the wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One block stages its partition's weights once and then runs `chunks` consecutive
+// groups of 64 anchors; each wave owns 16 anchors of a group and its own LDS rows, so
+// after the weights are in place the waves proceed independently.
 template <int F, int K>
 __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const float* __restrict__ mlp,
-                                                     const glam_view_info* views, int sigmoid_op,
+                                                     const glam_view_info* views, int sigmoid_op, int chunks,
                                                      glam_gaussians out) {
   using C = Cfg<F, K>;
   extern __shared__ float smem[];
   const glam_view_info vw = views[blockIdx.y];
   const int A = vw.anchor_count;
-  const int chunk0 = blockIdx.x * 64;
-  if (chunk0 >= A) return;
+  const int block0 = blockIdx.x * chunks * 64;
+  if (block0 >= A) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   float* s_p = smem;
   float* s_z = s_p + C::PA + w * 16 * C::ZS;
   float* s_y = smem + C::PA + 4 * 16 * C::ZS + w * 16 * C::YS;
   const float* pm = mlp + (size_t)vw.cam.partition * C::P;
-  for (int i = t; i < C::P; i += 256) s_p[i] = pm[i];
-  const int a0 = chunk0 + w * 16;
-  build_z<F, K>(an, vw, a0, s_z, l);
-  __syncthreads();
-  f4 H[6];
-  layer1<F, K>(s_p, s_z, l, H);
-  layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
-  layer2<F, K, 1, C::OT1>(s_p, H, s_y, l);
-  layer2<F, K, 2, C::OT2>(s_p, H, s_y, l);
+  load_weights<F, K>(pm, s_p, t, 256);
   __syncthreads();
   const long long n = out.n;
   const size_t GK = (size_t)an.A * K;
-  for (int gi = l; gi < 16 * K; gi += 64) {
-    const int ai = gi / K, j = gi % K, a = a0 + ai;
-    if (a >= A) continue;
-    const int ga = vw.anchor_begin + a;
-    const float* y = s_y + ai * C::YS;
-    const long long g = vw.g_begin + (long long)a * K + j;
-    const float yo = y[j];
-    out.opacity[g] = sigmoid_op ? sigmoid(yo) : tanhf(yo);
-    for (int c = 0; c < 3; ++c) out.rgb[c * n + g] = sigmoid(y[K + 3 * j + c]);
-    const float es = expf(an.log_scale[ga]);
-    for (int k = 0; k < 3; ++k) out.scale[k * n + g] = es * sigmoid(y[4 * K + 7 * j + k]);
-    const float* q = y + 4 * K + 7 * j + 3;
-    const float inv = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] + 1e-24f);
-    for (int k = 0; k < 4; ++k) out.quat[k * n + g] = q[k] * inv;
-    const size_t go = (size_t)ga * K + j;
-    for (int i = 0; i < 3; ++i) out.mean[i * n + g] = fmaf(es, an.offs[i * GK + go], an.pos[(size_t)i * an.A + ga]);
+  for (int c = 0; c < chunks; ++c) {
+    const int a0 = block0 + c * 64 + w * 16;
+    if (a0 >= A) break;
+    build_z<F, K>(an, vw, a0, s_z, l);
+    wave_sync();
+    f4 H[6];
+    layer1<F, K>(s_p, s_z, l, H);
+    layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
+    layer2<F, K, 1, C::OT1>(s_p, H, s_y, l);
+    layer2<F, K, 2, C::OT2>(s_p, H, s_y, l);
+    wave_sync();
+    for (int gi = l; gi < 16 * K; gi += 64) {
+      const int ai = gi / K, j = gi % K, a = a0 + ai;
+      if (a >= A) continue;
+      const int ga = vw.anchor_begin + a;
+      const float* y = s_y + ai * C::YS;
+      const long long g = vw.g_begin + (long long)a * K + j;
+      const float yo = y[j];
+      out.opacity[g] = sigmoid_op ? sigmoid(yo) : tanhf(yo);
+      for (int c3 = 0; c3 < 3; ++c3) out.rgb[c3 * n + g] = sigmoid(y[K + 3 * j + c3]);
+      const float es = expf(an.log_scale[ga]);
+      for (int k = 0; k < 3; ++k) out.scale[k * n + g] = es * sigmoid(y[4 * K + 7 * j + k]);
+      const float* q = y + 4 * K + 7 * j + 3;
+      const float inv = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] + 1e-24f);
+      for (int k = 0; k < 4; ++k) out.quat[k * n + g] = q[k] * inv;
+      const size_t go = (size_t)ga * K + j;
+      for (int i = 0; i < 3; ++i) out.mean[i * n + g] = fmaf(es, an.offs[i * GK + go], an.pos[(size_t)i * an.A + ga]);
+    }
+    // the next group's inputs overwrite rows this group's outputs were read from
+    wave_sync();
   }
 }
 
@@ -228,7 +294,7 @@ __device__ __forceinline__ void dhidden(const float* p, const float* dy, int l, 
 #pragma unroll
     for (int ks = 0; ks < ks_n; ++ks) {
       const int o = ks * 4 + lg;
-      const float a = o < out ? p[O.w2[ML] + o * kHid + ht * 16 + li] : 0.f;
+      const float a = o < out ? p[lds_offsets(F, K).w2[ML] + o * C::W2S + ht * 16 + li] : 0.f;
       const float b = o < out ? dy[li * C::YS + O.yoff[ML] + o] : 0.f;
       acc = mfma(a, b, acc);
     }
@@ -290,11 +356,6 @@ struct BwdGrid {
 };
 
 // Orders this wave's LDS traffic (the waves of a workgroup run independently).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int F, int K>
 __global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
@@ -321,7 +382,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors
   float* s_h = s_y + 16 * C::YS;
   float* s_ds = s_h + 16 * C::HS;
   const float* pm = mlp + (size_t)lead.cam.partition * C::P;
-  for (int i = t; i < C::P; i += 64 * kBwdWaves) s_p[i] = pm[i];
+  load_weights<F, K>(pm, s_p, t, 64 * kBwdWaves);
   __syncthreads();
   f4 dW2[NT2];
   f4 dW1[6 * NC1];
@@ -428,7 +489,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int h = mt * 16 + 4 * lg + r;
-            const float a = s_p[O.w1[h >> 5] + (h & 31) * C::NIN + ft * 16 + li];
+            const float a = s_p[lds_offsets(F, K).w1[h >> 5] + (h & 31) * C::W1S + ft * 16 + li];
             acc = mfma(a, dP[mt][r], acc);
           }
         dZ[ft] = acc;
@@ -579,13 +640,7 @@ int max_anchors(const glam_views& v) {
 
 // One workgroup per CU in total, shared by the partitions in proportion to their anchor
 // counts (at least one each, never more than their 16-anchor chunks / 8 waves).
-int total_bwd_blocks() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    cus = 256;
-  return cus;
-}
+int total_bwd_blocks() { return cu_count(); }
 
 bool bwd_grid(const glam_views& v, BwdGrid& g) {
   g.n_parts = 0;
@@ -623,7 +678,14 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
   if (mx == 0 || v.n == 0) return GLAM_OK;
   const size_t sm = fwd_smem<F, K>();
   if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
-  hipLaunchKernelGGL((decode_kernel<F, K>), dim3((mx + 63) / 64, v.n), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0,
+  // groups of 64 anchors per block: enough blocks to fill every CU four times over,
+  // each staging the weights as few times as that allows
+  const int groups = (mx + 63) / 64;
+  const long long target = 4LL * cu_count();
+  int chunks = (int)(((long long)groups * v.n + target - 1) / target);
+  chunks = chunks < 1 ? 1 : (chunks > 16 ? 16 : chunks);
+  const int nbx = (groups + chunks - 1) / chunks;
+  hipLaunchKernelGGL((decode_kernel<F, K>), dim3(nbx, v.n), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0, chunks,
                      out);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }

@@ -9,6 +9,9 @@ namespace glam {
 
 constexpr int kTileEdge() { return 16; }
 
+// Compute units of the current device (256 if the runtime cannot say).
+int cu_count();
+
 glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain,
                            const glam_projected& out, hipStream_t s);
 glam_status launch_project_bwd(const glam_gaussians& g, const glam_projected& proj, const glam_views& v,

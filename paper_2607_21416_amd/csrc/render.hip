@@ -409,13 +409,17 @@ glam_status launch_background(const glam_views& v, const float* bg, float* image
 
 }  // namespace
 
-// Persistent grid: a fixed number of workgroups per CU, never more than the items need.
-unsigned persistent_blocks(long long n_items, int waves_per_block, int blocks_per_cu) {
+int cu_count() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  const long long want = (long long)cus * blocks_per_cu;
+  return cus;
+}
+
+// Persistent grid: a fixed number of workgroups per CU, never more than the items need.
+unsigned persistent_blocks(long long n_items, int waves_per_block, int blocks_per_cu) {
+  const long long want = (long long)cu_count() * blocks_per_cu;
   const long long need = (n_items + waves_per_block - 1) / waves_per_block;
   return (unsigned)(need < want ? (need > 0 ? need : 1) : want);
 }

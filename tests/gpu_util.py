@@ -6,7 +6,11 @@ import torch
 import oracle
 from paper_2607_21416_amd.pipeline import Pipeline
 
+# flags that mark a pixel whose value depends on a decision taken within rounding: a
+# threshold, the stop test, or (end to end only) the depth order of a near-tie
 AMB_VALUE = oracle.AMB_ALPHA | oracle.AMB_T | oracle.AMB_DEPTH
+# stage-wise the oracle composites in the GPU's own order, so depth ties cannot matter
+AMB_STAGE = oracle.AMB_ALPHA | oracle.AMB_T
 
 
 def run(scene, steps=1):
@@ -81,10 +85,17 @@ def view_pixels(h, sl, key):
     return h[key][p0:p0 + W * H].reshape(H, W)
 
 
-def grad_close(g, ref, rel=1e-3, floor=1e-6, norm_rel=1e-3, name=""):
-    """Per element |g - ref| <= rel |ref| + floor max|ref|, and relative L2 error."""
+def grad_close(g, ref, rel=1e-3, floor=1e-5, norm_rel=1e-3, name=""):
+    """Per element |g - ref| <= rel |ref| + floor max|ref|, and relative L2 error.
+
+    The floor is the cancellation allowance of an FP32 sum: an element that is the
+    small difference of many large per-pixel terms carries an absolute error of a few
+    ulp of those terms, which the largest element of the tensor bounds."""
     g = np.asarray(g, np.float64)
     ref = np.asarray(ref, np.float64)
+    assert g.shape == ref.shape, (name, g.shape, ref.shape)
+    if ref.size == 0:
+        return
     scale = np.abs(ref).max()
     if scale == 0:
         assert np.abs(g).max() == 0, name

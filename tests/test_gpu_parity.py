@@ -3,8 +3,9 @@
 Stage-wise: each GPU stage's output is compared with the oracle's same stage fed the
 GPU's own inputs to that stage, so that FP32-vs-FP64 differences upstream cannot move
 a discrete decision: tile assignment, sort order and ranges bit-exact; pixels within
-1e-4 absolute; gradients within 1e-3 relative (plus a floor of 1e-6 of the tensor's
-largest entry for cancelling sums); decode within 1e-5 relative.
+1e-4 absolute; gradients within 1e-3 relative (plus a floor of 1e-5 of the tensor's
+largest entry for cancelling sums); decode within 1e-5 relative (plus 1e-5 of the
+field's largest entry for cancelling dot products).
 End to end: raw inputs -> pixels within 1e-4 and gradients within 1e-3, on pixels the
 oracle does not flag as ambiguous (a threshold, stop or depth order within rounding).
 """
@@ -14,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import (AMB_VALUE, gpu_splats, grad_close, host, run, unpack_box, view_image, view_pixels,
+from gpu_util import (AMB_STAGE, AMB_VALUE, gpu_splats, grad_close, host, run, unpack_box, view_image, view_pixels,
                       view_slices)
 
 pytestmark = pytest.mark.gpu
@@ -29,7 +30,16 @@ def anchor_small():
     return synth.anchor_scene(1012, [1500, 800], 2, W=200, H=120, fx=140.0, ssim_weight=0.2, bias_std=0.2)
 
 
-SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "anchor_small": anchor_small}
+def partition_without_anchors():
+    # a partition whose only view has no anchors next to two populated ones
+    return synth.anchor_scene(1013, [600, 0, 300], 1, W=96, H=64, fx=70.0, ssim_weight=0.2)
+
+
+# full-size workloads: config 2 (20k anchors, one 1226x370 view) and config 3 (50k
+# anchors, four views, the benchmark's workload)
+SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "anchor_small": anchor_small,
+          "empty_partition": partition_without_anchors, "C2": lambda: synth.config("C2"),
+          "C3": lambda: synth.config("C3")}
 
 
 @pytest.fixture(scope="module", params=list(SCENES))
@@ -43,13 +53,23 @@ def oracle_gauss(scene, v):
     return oracle.view_gaussians(scene, v)
 
 
+def _gpu_gaussians(scene, h, v, sl):
+    """The Gaussians the GPU projected for view v: its own decode output in anchor
+    mode (so the projection is compared stage-wise), the plain activation otherwise."""
+    if scene["kind"] == "plain":
+        return oracle_gauss(scene, v)
+    return {k: h["dec"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in h["dec"]}
+
+
 def test_project(case):
     name, scene, pipe, h = case
     for v, sl in enumerate(view_slices(pipe)):
         cam = scene["cams"][v]
-        gs = oracle_gauss(scene, v)
-        ref = oracle.project(gs, cam)
         g0, g1 = sl["g0"], sl["g1"]
+        if g1 == g0:
+            continue
+        gs = _gpu_gaussians(scene, h, v, sl)
+        ref = oracle.project(gs, cam)
         vis_g = h["ntiles"][g0:g1] > 0
         vis_o = ref["ntiles"] > 0
         # visibility agrees except within rounding of the cull thresholds
@@ -57,10 +77,17 @@ def test_project(case):
         near = (np.abs(255 * gs["opacity"] - 1) < 1e-4) | (np.abs(ref["depth"] - 0.2) < 1e-5)
         assert not (diff & ~near).any()
         both = vis_g & vis_o
-        for key in ("uv", "conic", "ext"):
+        for key in ("uv", "conic"):
             a = h[key][:, g0:g1][:, both].astype(np.float64)
             b = ref[key][:, both]
             np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-5 * np.abs(b).max(), err_msg=key)
+        # the extent scales with sqrt(ln(255 opacity)): its relative rounding error grows
+        # like (ulp of 255 opacity) / (2 ln(255 opacity)) as the opacity nears 1/255
+        a = h["ext"][:, g0:g1][:, both].astype(np.float64)
+        b = ref["ext"][:, both]
+        lg = np.log(255.0 * gs["opacity"][both])
+        tol = 1e-5 * np.abs(b) + 1e-5 * np.abs(b).max() + np.abs(b) * 1e-6 / np.maximum(lg, 1e-12)
+        assert (np.abs(a - b) <= tol).all(), np.abs(a - b).max()
         np.testing.assert_allclose(h["depth"][g0:g1][both], ref["depth"][both], rtol=1e-6)
         # tile assignment bit-exact given the GPU's single-precision centre and extents
         prect, nt = oracle.rect_f32(h["uv"][0, g0:g1], h["uv"][1, g0:g1], h["ext"][0, g0:g1],
@@ -99,7 +126,7 @@ def test_render_fwd_stagewise(case):
         vals = h["vals"].astype(np.int64) - sl["g0"]
         ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
         ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v])
-        ok = (ref["amb"] & AMB_VALUE) == 0
+        ok = (ref["amb"] & AMB_STAGE) == 0
         assert ok.mean() > 0.95
         img = view_image(h, sl)
         err = np.abs(img - ref["image"])[:, ok]
@@ -132,7 +159,7 @@ def _masked_dimage(h, scene, pipe):
         ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
         ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v])
         _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
-        amb = (ref["amb"] & (AMB_VALUE | oracle.AMB_CLAMP)) != 0
+        amb = (ref["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0
         d[:, amb] = 0.0
         out.append(d)
         amb_all.append(amb)
@@ -186,9 +213,13 @@ def test_decode_stagewise(case):
         pytest.skip("plain scene has no decode")
     for v, sl in enumerate(view_slices(pipe)):
         ref = oracle.decode(scene, scene["cams"][v]["partition"], scene["cams"][v])
+        assert ref["opacity"].shape[-1] == sl["g1"] - sl["g0"]
+        if sl["g1"] == sl["g0"]:
+            continue
         for k in ("mean", "scale", "quat", "opacity", "rgb"):
             got = h["dec"][k][..., sl["g0"]:sl["g1"]]
-            np.testing.assert_allclose(got, ref[k], rtol=1e-5, atol=1e-6, err_msg=k)
+            np.testing.assert_allclose(got, ref[k], rtol=1e-5, atol=1e-5 * max(np.abs(ref[k]).max(), 1e-30),
+                                       err_msg=k)
 
 
 def test_end_to_end(case):
@@ -197,6 +228,7 @@ def test_end_to_end(case):
     dims = []
     for v, (sl, r) in enumerate(zip(view_slices(pipe), fwd)):
         ok = (r["amb"] & AMB_VALUE) == 0
+        assert ok.mean() > 0.85
         img = view_image(h, sl)
         assert np.abs(img - r["image"])[:, ok].max() <= 1e-4
         assert h["loss"][v] == pytest.approx(r["loss"], rel=1e-4)
