@@ -81,8 +81,12 @@ __device__ __forceinline__ bool box_meets(float bxf, float byf, const Item& it) 
 }
 
 // Work queue.  Device-scope atomics are served at the memory side, so one counter would
-// serialise every grab; the longest-first item list is dealt round-robin over kQueues
+// serialise every grab; the longest-first tile list is dealt round-robin over kQueues
 // counters (one 128-byte line each), and workgroup b pulls from counter b % kQueues.
+// Workgroups are dealt to the 8 XCDs round-robin, so all workgroups of one counter sit
+// on one XCD; the four quadrant items of a tile are consecutive grabs of one counter, so
+// the tile's records are fetched into that XCD's L2 once and read there four times.
+// An item is 4 * (tile rank) + quadrant.
 // Words [0, kQueues*32) of a queue region hold the counters, word kQueues*32 the exit
 // count.  The last wave to leave resets all of them for the next launch.
 constexpr int kQueues = 16;
@@ -94,7 +98,8 @@ __device__ __forceinline__ uint32_t next_item(uint32_t* q, int lane) {
   const uint32_t qi = blockIdx.x % nq;
   uint32_t v = 0;
   if (lane == 0) v = atomicAdd(&q[32 * qi], 1u);
-  return __builtin_amdgcn_readfirstlane(v) * nq + qi;
+  v = __builtin_amdgcn_readfirstlane(v);
+  return ((v >> 2) * nq + qi) * 4u + (v & 3u);
 }
 
 __device__ __forceinline__ void leave_queue(uint32_t* q, uint32_t total_waves, int lane) {
