@@ -109,6 +109,24 @@ def make_step(torch, pipe, use_graph):
     return g.replay, g
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    the compositing source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_config3.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return int(round(k["fetch_bytes"] + k["write_bytes"]))
+
+
 def cpu_baseline(scene, views):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -186,7 +204,7 @@ def main():
     flops = evals_fwd * FLOP_FWD if dom == "render_fwd" else evals_bwd * FLOP_BWD
     achieved = flops / (st[dom] * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(dom),
                 "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
                         f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
 
