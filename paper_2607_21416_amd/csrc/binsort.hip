@@ -24,7 +24,7 @@ namespace {
 constexpr int kScanThreads = 256, kScanItems = 8, kScanBlock = kScanThreads * kScanItems;
 constexpr int kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
-constexpr int kMaxSortBlocks = 1024;
+constexpr int kMaxSortBlocks = 4096;
 constexpr uint32_t kDepthBase = 0x3E4CCCCDu;  // bit pattern of 0.2f: every visible depth is above it
 
 struct Plan {
@@ -34,7 +34,8 @@ struct Plan {
   uint32_t tbits;      // tile key bits
   uint32_t tiles_per_block;
   uint32_t n_sort_tiles;
-  uint32_t pad[10];
+  uint32_t active_blocks;  // workgroups of a radix pass that have tiles
+  uint32_t pad[9];
 };
 
 constexpr int kLptBuckets = 32;
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
     const unsigned long long P = s_part[1023];
     const uint32_t maxbits = s_max[1023];
     Plan pl;
-    for (int k = 0; k < 10; ++k) pl.pad[k] = 0;
+    for (int k = 0; k < 9; ++k) pl.pad[k] = 0;
     long long Pc = (long long)P;
     if (Pc > capacity) {
       status[0] = GLAM_ERR_CAPACITY;
@@ -142,6 +143,7 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
     pl.npasses = Pc > 0 ? (pl.dbits + pl.tbits + kRadixBits - 1) / kRadixBits : 0u;
     pl.n_sort_tiles = (uint32_t)((Pc + kSortTile - 1) / kSortTile);
     pl.tiles_per_block = (pl.n_sort_tiles + n_sort_blocks - 1) / n_sort_blocks;
+    pl.active_blocks = pl.tiles_per_block ? (pl.n_sort_tiles + pl.tiles_per_block - 1) / pl.tiles_per_block : 0u;
     status[4] = (int32_t)pl.dbits;
     status[5] = (int32_t)pl.tbits;
     status[6] = (int32_t)pl.npasses;
@@ -149,60 +151,102 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
   }
 }
 
-// Pairs of every view-Gaussian; the first 2048-block scan is redone here in LDS.
+// Pairs of every view-Gaussian.  A workgroup takes the pairs of 2048 consecutive
+// view-Gaussians: it stages their tile boxes in LDS with the exclusive prefix of their
+// pair counts (the first-level scan redone in LDS), then each thread emits pairs
+// k = t, t + 256, ... of the workgroup's range, finding its Gaussian by binary search
+// in the prefix, so every pair costs the same and the stores are coalesced.
 __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* ntiles, const float* splat,
                                                                  long long n, const glam_view_info* views,
                                                                  int n_views, const uint32_t* psum,
                                                                  const Plan* plan, uint64_t* keys_out,
                                                                  uint32_t* vals_out, uint64_t* keys_alt,
                                                                  uint32_t* vals_alt) {
-  __shared__ uint32_t s_nt[kScanBlock];
+  __shared__ uint32_t s_pre[kScanBlock];   // count, then exclusive prefix within the workgroup
+  __shared__ uint32_t s_tile[kScanBlock];  // global tile of the box's top-left corner
+  __shared__ uint32_t s_dim[kScanBlock];   // box width in tiles | view tiles_x << 16
+  __shared__ uint32_t s_dkey[kScanBlock];  // depth key
   __shared__ uint32_t s_scan[kScanThreads];
+  __shared__ int s_view0;
   const Plan pl = *plan;
+  const int t = threadIdx.x;
   const long long base = (long long)blockIdx.x * kScanBlock;
+  if (t == 0) s_view0 = find_view(views, n_views, base, [](const glam_view_info& v) { return v.g_begin; });
+  int32_t cnt[kScanItems];
+  float4 rec[kScanItems];
+#pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int j = i * kScanThreads + threadIdx.x;
-    const long long g = base + j;
-    s_nt[j] = g < n ? (uint32_t)ntiles[g] : 0u;
+    const long long g = base + i * kScanThreads + t;
+    cnt[i] = g < n ? ntiles[g] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const long long g = base + i * kScanThreads + t;
+    rec[i] = cnt[i] > 0 ? reinterpret_cast<const float4*>(splat + g * kSplatWords)[2] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
-  // thread t owns entries [t*8, t*8+8)
+  const int v0 = s_view0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int j = i * kScanThreads + t;
+    const long long g = base + j;
+    uint32_t tile0 = 0, dim = 0, dkey = 0;
+    if (cnt[i] > 0) {
+      int vi = v0;
+      while (vi + 1 < n_views && views[vi + 1].g_begin <= g) ++vi;
+      const glam_view_info& vw = views[vi];
+      const uint32_t bx = __float_as_uint(rec[i].y), by = __float_as_uint(rec[i].z);
+      const int tx0 = (int)(bx & 0xffffu) / kTile, tx1 = (int)(bx >> 16) / kTile;
+      const int ty0 = (int)(by & 0xffffu) / kTile;
+      tile0 = (uint32_t)(vw.tile_begin + (long long)ty0 * vw.tiles_x + tx0);
+      dim = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vw.tiles_x << 16);
+      dkey = __float_as_uint(rec[i].w) - kDepthBase;
+    }
+    s_pre[j] = (uint32_t)cnt[i];
+    s_tile[j] = tile0;
+    s_dim[j] = dim;
+    s_dkey[j] = dkey;
+  }
+  __syncthreads();
+  // exclusive prefix: thread t scans entries [8t, 8t + 8), then the 256 thread sums
   uint32_t local[kScanItems];
   uint32_t sum = 0;
-  for (int i = 0; i < kScanItems; ++i) { local[i] = sum; sum += s_nt[threadIdx.x * kScanItems + i]; }
-  s_scan[threadIdx.x] = sum;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) { local[i] = sum; sum += s_pre[t * kScanItems + i]; }
+  s_scan[t] = sum;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0u;
+    const uint32_t v = t >= off ? s_scan[t - off] : 0u;
     __syncthreads();
-    s_scan[threadIdx.x] += v;
+    s_scan[t] += v;
     __syncthreads();
   }
-  const uint32_t before = s_scan[threadIdx.x] - sum + psum[blockIdx.x];
+  const uint32_t before = s_scan[t] - sum;
+  const uint32_t total = s_scan[kScanThreads - 1];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) s_pre[t * kScanItems + i] = before + local[i];
+  __syncthreads();
   uint64_t* kout = (pl.npasses & 1u) ? keys_alt : keys_out;
   uint32_t* vout = (pl.npasses & 1u) ? vals_alt : vals_out;
-  for (int i = 0; i < kScanItems; ++i) {
-    const long long g = base + threadIdx.x * kScanItems + i;
-    if (g >= n) break;
-    const uint32_t cnt = s_nt[threadIdx.x * kScanItems + i];
-    if (cnt == 0) continue;
-    uint32_t off = before + local[i];
-    const int vi = find_view(views, n_views, g, [](const glam_view_info& v) { return v.g_begin; });
-    const glam_view_info& vw = views[vi];
-    const float* rec = splat + g * kSplatWords;
-    const uint32_t bx = __float_as_uint(rec[9]), by = __float_as_uint(rec[10]);
-    const uint32_t dkey = __float_as_uint(rec[11]) - kDepthBase;
-    const int tx0 = (int)(bx & 0xffffu) / kTile, tx1 = (int)(bx >> 16) / kTile;
-    const int ty0 = (int)(by & 0xffffu) / kTile, ty1 = (int)(by >> 16) / kTile;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (off < pl.P) {
-          const uint64_t tile = (uint64_t)(vw.tile_begin + ty * vw.tiles_x + tx);
-          kout[off] = (tile << pl.dbits) | (uint64_t)dkey;
-          vout[off] = (uint32_t)g;
-        }
-        ++off;
-      }
+  const uint32_t gbase = psum[blockIdx.x];
+  for (uint32_t k = t; k < total; k += kScanThreads) {
+    // last entry whose prefix is <= k (zero-count entries share the next one's prefix)
+    int lo = 0, hi = kScanBlock - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t r = k - s_pre[lo];
+    const uint32_t dim = s_dim[lo];
+    const uint32_t w = dim & 0xffffu, tx = dim >> 16;
+    const uint32_t ty = r / w;
+    const uint64_t tile = (uint64_t)(s_tile[lo] + ty * tx + (r - ty * w));
+    const uint32_t off = gbase + k;
+    if (off < pl.P) {
+      kout[off] = (tile << pl.dbits) | (uint64_t)s_dkey[lo];
+      vout[off] = (uint32_t)(base + lo);
+    }
   }
 }
 
@@ -227,7 +271,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan*
                                                                      const uint64_t* keys_out,
                                                                      const uint64_t* keys_alt, uint32_t* hist) {
   const Plan pl = *plan;
-  if ((uint32_t)pass >= pl.npasses) return;
+  if ((uint32_t)pass >= pl.npasses || blockIdx.x >= pl.active_blocks) return;
   __shared__ uint32_t s_cnt[kRadix];
   s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -237,12 +281,17 @@ __global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan*
   const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
   for (uint32_t tile = t0; tile < t1; ++tile) {
     const uint32_t start = tile * kSortTile;
-    for (int i = 0; i < kSortItems; ++i) {
+    uint32_t d[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {  // all loads in flight first
       const uint32_t idx = start + i * kSortThreads + threadIdx.x;
-      const bool valid = idx < pl.P;
-      const uint32_t d = valid ? (uint32_t)(src[idx] >> shift) & (kRadix - 1) : 0u;
-      const uint64_t peers = match_digit(d, valid);
-      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+      d[i] = idx < pl.P ? (uint32_t)(src[idx] >> shift) & (kRadix - 1) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const bool valid = start + i * kSortThreads + threadIdx.x < pl.P;
+      const uint64_t peers = match_digit(d[i], valid);
+      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d[i]], (uint32_t)__popcll(peers));
     }
   }
   __syncthreads();
@@ -256,8 +305,9 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(const Plan* plan, int p
   if ((uint32_t)pass >= pl.npasses) return;
   __shared__ uint32_t s[256];
   uint32_t* row = hist + blockIdx.x * n_blocks;
-  const int per = (n_blocks + 255) / 256;
-  const int lo = min(n_blocks, (int)threadIdx.x * per), hi = min(n_blocks, lo + per);
+  const int nb = (int)min((uint32_t)n_blocks, pl.active_blocks);
+  const int per = (nb + 255) / 256;
+  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
   uint32_t local = 0;
   for (int i = lo; i < hi; ++i) local += row[i];
   s[threadIdx.x] = local;
@@ -283,7 +333,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
                                                                        uint64_t* keys_out, uint32_t* vals_out,
                                                                        uint64_t* keys_alt, uint32_t* vals_alt) {
   const Plan pl = *plan;
-  if ((uint32_t)pass >= pl.npasses) return;
+  if ((uint32_t)pass >= pl.npasses || blockIdx.x >= pl.active_blocks) return;
   __shared__ uint32_t s_cnt[kSortItems][kSortThreads / 64][kRadix];
   __shared__ uint32_t s_run[kRadix];
   __shared__ uint32_t s_scan[kRadix];
@@ -317,11 +367,14 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
     uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
     bool valid[kSortItems];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < kSortItems; ++i) {  // all loads in flight first
       const uint32_t idx = start + i * kSortThreads + t;
       valid[i] = idx < pl.P;
       key[i] = valid[i] ? ksrc[idx] : 0ull;
       val[i] = valid[i] ? vsrc[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
       dig[i] = (uint32_t)(key[i] >> shift) & (kRadix - 1);
       const uint64_t peers = match_digit(dig[i], valid[i]);
       rank[i] = (uint32_t)__popcll(peers & lanemask_lt());

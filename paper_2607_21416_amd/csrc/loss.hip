@@ -1,13 +1,21 @@
 // Photometric loss of Eq. 3 per view: L = mean |C - target| + w (1 - mean SSIM), SSIM
 // with an 11x11 box window and zero padding, and dL/dC.
 //
-// Two stencil passes over 16x16 tiles, each staging a 26x26 halo in LDS and summing
-// the window separably (rows, then columns):
-//   A: window means of x, y, x^2, y^2, xy -> SSIM map value and its partials with
-//      respect to mean(x), E[x^2], E[xy] (three maps per channel), per-tile sums;
-//   B: window sums of those partials (the adjoint of the window mean is the same
-//      box) combined with the L1 sign into dL/dC.
-// A last kernel reduces the per-tile sums of each view in double precision.
+// One fused kernel per (32x32 output tile, channel).  With q ranging over the window
+// centres that touch the tile (a 42x42 region) and the inputs those windows read (a
+// 52x52 region, zero outside the image), the workgroup
+//   1. stages x = image and y = target of the 52x52 region in LDS,
+//   2. sums x, y, x^2, y^2, xy along rows (11 wide) for the 42 window columns,
+//   3. sums those down columns (11 tall) to the window statistics at every q, and
+//      writes SSIM(q) and its partials with respect to mean(x), E[x^2] and E[xy]
+//      (zero where q is outside the image) to LDS,
+//   4-5. box-sums the partials over the window around every output pixel (the adjoint
+//      of the window mean is the same box) and combines them with the L1 sign into
+//      dL/dC, written once.
+// Row and column sums slide along short register-held runs (add the entering term,
+// subtract the leaving one).  Per-(tile, channel) sums of |x - y| and SSIM go to a
+// small workspace; a last kernel reduces each view's sums in double precision.
+// Nothing but the image, the target and dL/dC touches HBM.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -15,148 +23,228 @@ namespace glam {
 
 namespace {
 
-constexpr int kR = 5, kWin = 2 * kR + 1, kHalo = kTile + 2 * kR;  // 26
+constexpr int kR = 5, kWin = 2 * kR + 1;
+constexpr int kT = 32;               // output tile edge
+constexpr int kQ = kT + 2 * kR;      // 42: window centres touching the tile
+constexpr int kI = kT + 4 * kR;      // 52: inputs those windows read
+constexpr int kIS = kI + 1, kQS = kQ + 1, kTS = kT + 1;  // padded LDS row strides
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
-struct LossGeom {
-  int view, W, H, x0, y0;
-  long long pix_begin, tile_local;
-};
+// LDS plan (floats): region A holds the staged inputs, later the partial maps;
+// region B holds the row sums of the statistics, later the row sums of the partials.
+constexpr int kA = 2 * kI * kIS;     // 5512 >= 3 * kQ * kQS = 5418
+constexpr int kB = 5 * kI * kQS;     // 11180 >= 3 * kQ * kTS = 4158
+static_assert(3 * kQ * kQS <= kA && 3 * kQ * kTS <= kB, "LDS aliasing");
 
-__device__ __forceinline__ LossGeom loss_geom(const glam_view_info* views, int n_views, int tile) {
-  LossGeom g;
-  g.view = find_view(views, n_views, tile, [](const glam_view_info& v) { return (long long)v.tile_begin; });
-  const glam_view_info& vw = views[g.view];
-  const int lt = tile - vw.tile_begin;
-  g.W = vw.cam.width;
-  g.H = vw.cam.height;
-  g.x0 = (lt % vw.tiles_x) * kTile;
-  g.y0 = (lt / vw.tiles_x) * kTile;
-  g.pix_begin = vw.pix_begin;
-  g.tile_local = lt;
-  return g;
-}
+__device__ __forceinline__ float sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
 
-// Loads a 26x26 halo of one plane (zero outside the image) into s.
-__device__ __forceinline__ void load_halo(const float* plane, const LossGeom& g, float (*s)[kHalo]) {
-  for (int k = threadIdx.x; k < kHalo * kHalo; k += 256) {
-    const int hy = k / kHalo, hx = k % kHalo;
-    const int x = g.x0 - kR + hx, y = g.y0 - kR + hy;
-    s[hy][hx] = (x >= 0 && x < g.W && y >= 0 && y < g.H) ? plane[(long long)y * g.W + x] : 0.f;
-  }
-}
-
-__global__ void __launch_bounds__(256) ssim_fwd_kernel(const glam_view_info* views, int n_views, const float* image,
-                                                       const float* target, float w_ssim, float* maps,
-                                                       long long n_pix, float* partial) {
-  __shared__ float s_x[kHalo][kHalo], s_y[kHalo][kHalo];
-  __shared__ float s_h[5][kHalo][kTile];
-  __shared__ float s_red[2][256];
-  const LossGeom g = loss_geom(views, n_views, blockIdx.x);
-  const int t = threadIdx.x, lx = t & 15, ly = t >> 4;
-  const int x = g.x0 + lx, y = g.y0 + ly;
-  const bool inside = x < g.W && y < g.H;
-  const long long HW = (long long)g.W * g.H;
-  const long long p = (long long)y * g.W + x;
-  float l1 = 0.f, ssum = 0.f;
-  for (int c = 0; c < 3; ++c) {
-    const float* xp = image + 3 * g.pix_begin + c * HW;
-    const float* yp = target + 3 * g.pix_begin + c * HW;
-    if (inside) l1 += fabsf(xp[p] - yp[p]);
-    if (w_ssim == 0.f) continue;
+__global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, int max_t32, const float* image,
+                                                   const float* target, float w_ssim, float* dimage,
+                                                   float* partial) {
+  __shared__ float sA[kA];
+  __shared__ float sB[kB];
+  __shared__ float s_red[2][8];
+  const glam_view_info vw = views[blockIdx.y];
+  const int W = vw.cam.width, H = vw.cam.height;
+  const int tx_n = (W + kT - 1) / kT, ty_n = (H + kT - 1) / kT;
+  const int t32 = blockIdx.x;
+  if (t32 >= tx_n * ty_n) return;
+  const int c = blockIdx.z;
+  const int x0 = (t32 % tx_n) * kT, y0 = (t32 / tx_n) * kT;
+  const long long HW = (long long)W * H;
+  const float* xp = image + 3 * vw.pix_begin + c * HW;
+  const float* yp = target + 3 * vw.pix_begin + c * HW;
+  const int t = threadIdx.x;
+  float ssum = 0.f;
+  // partials of the window around output pixel (io, jo) are summed in step 5
+  float* sP = sA;                    // [3][kQ][kQS]
+  float* sHP = sB;                   // [3][kQ][kTS]
+  if (w_ssim != 0.f) {
+    // 1. inputs of the 52x52 region
+    float* sx = sA;
+    float* sy = sA + kI * kIS;
+    // all loads in flight before the first LDS store
+    constexpr int kLoads = (kI * kI + 255) / 256;
+    float vx[kLoads], vy[kLoads];
+#pragma unroll
+    for (int n = 0; n < kLoads; ++n) {
+      const int k = t + 256 * n;
+      const int r = k / kI, j = k % kI;
+      const int gx = x0 - 2 * kR + j, gy = y0 - 2 * kR + r;
+      const bool in = k < kI * kI && gx >= 0 && gx < W && gy >= 0 && gy < H;
+      const long long o = in ? (long long)gy * W + gx : 0;
+      vx[n] = in ? xp[o] : 0.f;
+      vy[n] = in ? yp[o] : 0.f;
+    }
+#pragma unroll
+    for (int n = 0; n < kLoads; ++n) {
+      const int k = t + 256 * n;
+      if (k < kI * kI) {
+        const int r = k / kI, j = k % kI;
+        sx[r * kIS + j] = vx[n];
+        sy[r * kIS + j] = vy[n];
+      }
+    }
     __syncthreads();
-    load_halo(xp, g, s_x);
-    load_halo(yp, g, s_y);
-    __syncthreads();
-    for (int k = t; k < kHalo * kTile; k += 256) {
-      const int hy = k / kTile, cx = k % kTile;
+    // 2. row sums: 52 rows x 42 window columns, runs of 7 columns
+    float* sH = sB;                  // [5][kI][kQS]
+    for (int task = t; task < kI * 6; task += 256) {
+      const int r = task % kI, j0 = (task / kI) * 7;
+      const float* rx = sx + r * kIS + j0;
+      const float* ry = sy + r * kIS + j0;
       float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+#pragma unroll
       for (int o = 0; o < kWin; ++o) {
-        const float u = s_x[hy][cx + o], v = s_y[hy][cx + o];
+        const float u = rx[o], v = ry[o];
         a += u; b += v; aa += u * u; bb += v * v; ab += u * v;
       }
-      s_h[0][hy][cx] = a; s_h[1][hy][cx] = b; s_h[2][hy][cx] = aa; s_h[3][hy][cx] = bb; s_h[4][hy][cx] = ab;
-    }
-    __syncthreads();
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int o = 0; o < kWin; ++o)
-      for (int q = 0; q < 5; ++q) m[q] += s_h[q][ly + o][lx];
-    if (inside) {
-      const float inv = 1.f / 121.f;
-      const float mx = m[0] * inv, my = m[1] * inv;
-      const float vx = m[2] * inv - mx * mx, vy = m[3] * inv - my * my, cxy = m[4] * inv - mx * my;
-      const float n1 = 2.f * mx * my + kC1, n2 = 2.f * cxy + kC2;
-      const float d1 = mx * mx + my * my + kC1, d2 = vx + vy + kC2;
-      const float id = 1.f / (d1 * d2);
-      const float sv = n1 * n2 * id;
-      ssum += sv;
-      float* mp = maps + (long long)c * 3 * n_pix + g.pix_begin;
-      mp[p] = (2.f * my * n2 - 2.f * my * n1) * id - sv * (2.f * mx * d2 - 2.f * mx * d1) * id;
-      mp[n_pix + p] = -sv / d2;
-      mp[2 * n_pix + p] = 2.f * n1 * id;
-    }
-  }
-  s_red[0][t] = l1;
-  s_red[1][t] = ssum;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off) { s_red[0][t] += s_red[0][t + off]; s_red[1][t] += s_red[1][t + off]; }
-    __syncthreads();
-  }
-  if (t == 0) { partial[2 * blockIdx.x] = s_red[0][0]; partial[2 * blockIdx.x + 1] = s_red[1][0]; }
-}
-
-__global__ void __launch_bounds__(256) ssim_bwd_kernel(const glam_view_info* views, int n_views, const float* image,
-                                                       const float* target, float w_ssim, const float* maps,
-                                                       long long n_pix, float* dimage) {
-  __shared__ float s_m[3][kHalo][kHalo];
-  __shared__ float s_h[3][kHalo][kTile];
-  const LossGeom g = loss_geom(views, n_views, blockIdx.x);
-  const int t = threadIdx.x, lx = t & 15, ly = t >> 4;
-  const int x = g.x0 + lx, y = g.y0 + ly;
-  const bool inside = x < g.W && y < g.H;
-  const long long HW = (long long)g.W * g.H;
-  const long long p = (long long)y * g.W + x;
-  const float inv_n = 1.f / (3.f * (float)HW);
-  for (int c = 0; c < 3; ++c) {
-    const float* xp = image + 3 * g.pix_begin + c * HW;
-    const float* yp = target + 3 * g.pix_begin + c * HW;
-    float grad = 0.f;
-    float xv = 0.f, yv = 0.f;
-    if (inside) {
-      xv = xp[p]; yv = yp[p];
-      const float d = xv - yv;
-      grad = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * inv_n;
-    }
-    if (w_ssim != 0.f) {
-      __syncthreads();
-      const float* mp = maps + (long long)c * 3 * n_pix + g.pix_begin;
-      for (int q = 0; q < 3; ++q) load_halo(mp + q * n_pix, g, s_m[q]);
-      __syncthreads();
-      for (int k = t; k < kHalo * kTile; k += 256) {
-        const int hy = k / kTile, cx = k % kTile;
-        float a = 0.f, b = 0.f, cc = 0.f;
-        for (int o = 0; o < kWin; ++o) { a += s_m[0][hy][cx + o]; b += s_m[1][hy][cx + o]; cc += s_m[2][hy][cx + o]; }
-        s_h[0][hy][cx] = a; s_h[1][hy][cx] = b; s_h[2][hy][cx] = cc;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const int idx = r * kQS + j0 + m;
+        sH[idx] = a; sH[kI * kQS + idx] = b; sH[2 * kI * kQS + idx] = aa;
+        sH[3 * kI * kQS + idx] = bb; sH[4 * kI * kQS + idx] = ab;
+        if (m < 6) {
+          const float ui = rx[m + kWin], vi = ry[m + kWin], uo = rx[m], vo = ry[m];
+          a += ui - uo; b += vi - vo; aa += ui * ui - uo * uo; bb += vi * vi - vo * vo; ab += ui * vi - uo * vo;
+        }
       }
-      __syncthreads();
-      float a = 0.f, b = 0.f, cc = 0.f;
-      for (int o = 0; o < kWin; ++o) { a += s_h[0][ly + o][lx]; b += s_h[1][ly + o][lx]; cc += s_h[2][ly + o][lx]; }
-      grad -= w_ssim * inv_n * (1.f / 121.f) * (a + 2.f * xv * b + yv * cc);
     }
-    if (inside) dimage[3 * g.pix_begin + c * HW + p] = grad;
+    __syncthreads();
+    // 3. column sums -> window statistics, SSIM and its partials at 42x42 centres,
+    //    runs of 7 rows
+    float sp0[7], sp1[7], sp2[7];
+    int jj = 0, i0 = 0;
+    const bool has3 = t < kQ * 6;
+    if (has3) {
+      jj = t % kQ;
+      i0 = (t / kQ) * 7;
+      float m5[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) acc += sH[q * kI * kQS + (i0 + o) * kQS + jj];
+        m5[q] = acc;
+      }
+      const int gx = x0 - kR + jj;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const int i = i0 + m, gy = y0 - kR + i;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const float inv = 1.f / 121.f;
+        const float mx = m5[0] * inv, my = m5[1] * inv;
+        const float vx = m5[2] * inv - mx * mx, vy = m5[3] * inv - my * my, cxy = m5[4] * inv - mx * my;
+        const float n1 = 2.f * mx * my + kC1, n2 = 2.f * cxy + kC2;
+        const float d1 = mx * mx + my * my + kC1, d2 = vx + vy + kC2;
+        // hardware reciprocals (1 ulp): d1, d2 >= C1, C2 > 0
+        const float rd2 = __builtin_amdgcn_rcpf(d2);
+        const float id = __builtin_amdgcn_rcpf(d1) * rd2;
+        const float sv = n1 * n2 * id;
+        const bool own = i >= kR && i < kR + kT && jj >= kR && jj < kR + kT;
+        if (in && own) ssum += sv;
+        sp0[m] = in ? (2.f * my * n2 - 2.f * my * n1) * id - sv * (2.f * mx * d2 - 2.f * mx * d1) * id : 0.f;
+        sp1[m] = in ? -sv * rd2 : 0.f;
+        sp2[m] = in ? 2.f * n1 * id : 0.f;
+        if (m < 6) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q)
+            m5[q] += sH[q * kI * kQS + (i + kWin) * kQS + jj] - sH[q * kI * kQS + i * kQS + jj];
+        }
+      }
+    }
+    __syncthreads();  // region A (inputs) is dead: the partial maps take its place
+    if (has3) {
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const int idx = (i0 + m) * kQS + jj;
+        sP[idx] = sp0[m]; sP[kQ * kQS + idx] = sp1[m]; sP[2 * kQ * kQS + idx] = sp2[m];
+      }
+    }
+    __syncthreads();
+    // 4. row sums of the partials: 42 rows x 32 output columns, runs of 8
+    for (int task = t; task < kQ * 4; task += 256) {
+      const int i = task % kQ, j0 = (task / kQ) * 8;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const float* row = sP + p * kQ * kQS + i * kQS + j0;
+        float acc = 0.f;
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) acc += row[o];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          sHP[p * kQ * kTS + i * kTS + j0 + m] = acc;
+          if (m < 7) acc += row[m + kWin] - row[m];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // 5. column sums of the partials and dL/dC: 32 output columns x runs of 4 rows
+  const long long n_all = 3 * HW;
+  const float inv_n = 1.f / (float)n_all;
+  const int jo = t % kT, io0 = (t / kT) * 4;
+  float pa = 0.f, pb = 0.f, pc = 0.f;
+  if (w_ssim != 0.f) {
+#pragma unroll
+    for (int o = 0; o < kWin; ++o) {
+      pa += sHP[(io0 + o) * kTS + jo];
+      pb += sHP[kQ * kTS + (io0 + o) * kTS + jo];
+      pc += sHP[2 * kQ * kTS + (io0 + o) * kTS + jo];
+    }
+  }
+  float l1 = 0.f;
+  const int gx = x0 + jo;
+  float xs[4], ys[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int gy = y0 + io0 + m;
+    const bool in = gx < W && gy < H;
+    const long long o = in ? (long long)gy * W + gx : 0;
+    xs[m] = in ? xp[o] : 0.f;
+    ys[m] = in ? yp[o] : 0.f;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int io = io0 + m, gy = y0 + io;
+    if (gx < W && gy < H) {
+      const long long o = (long long)gy * W + gx;
+      const float xv = xs[m], yv = ys[m];
+      const float d = xv - yv;
+      l1 += fabsf(d);
+      float g = sgn(d) * inv_n;
+      if (w_ssim != 0.f) g -= w_ssim * inv_n * (1.f / 121.f) * (pa + 2.f * xv * pb + yv * pc);
+      dimage[3 * vw.pix_begin + c * HW + o] = g;
+    }
+    if (w_ssim != 0.f && m < 3) {
+      pa += sHP[(io + kWin) * kTS + jo] - sHP[io * kTS + jo];
+      pb += sHP[kQ * kTS + (io + kWin) * kTS + jo] - sHP[kQ * kTS + io * kTS + jo];
+      pc += sHP[2 * kQ * kTS + (io + kWin) * kTS + jo] - sHP[2 * kQ * kTS + io * kTS + jo];
+    }
+  }
+  // per-(tile, channel) sums
+  l1 = wave_sum(l1);
+  ssum = wave_sum(ssum);
+  if ((t & 63) == 0) { s_red[0][t >> 6] = l1; s_red[1][t >> 6] = ssum; }
+  __syncthreads();
+  if (t == 0) {
+    float a = 0.f, b = 0.f;
+    for (int w = 0; w < 4; ++w) { a += s_red[0][w]; b += s_red[1][w]; }
+    float* pp = partial + 2 * (((long long)blockIdx.y * max_t32 + t32) * 3 + c);
+    pp[0] = a;
+    pp[1] = b;
   }
 }
 
-__global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* views, const float* partial,
-                                                          float w_ssim, float* loss) {
+__global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* views, int max_t32,
+                                                          const float* partial, float w_ssim, float* loss) {
   __shared__ double s_a[256], s_b[256];
   const glam_view_info& vw = views[blockIdx.x];
-  const int n = vw.tiles_x * vw.tiles_y;
+  const int n = 3 * ((vw.cam.width + kT - 1) / kT) * ((vw.cam.height + kT - 1) / kT);
+  const float* pv = partial + 2 * 3 * (long long)blockIdx.x * max_t32;
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < n; k += 256) {
-    a += partial[2 * (vw.tile_begin + k)];
-    b += partial[2 * (vw.tile_begin + k) + 1];
+    a += pv[2 * k];
+    b += pv[2 * k + 1];
   }
   s_a[threadIdx.x] = a;
   s_b[threadIdx.x] = b;
@@ -173,24 +261,30 @@ __global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* 
   }
 }
 
+int max_tiles32(const glam_views& v) {
+  int mx = 0;
+  for (int i = 0; i < v.n; ++i) {
+    const glam_camera& c = v.host[i].cam;
+    const int n = ((c.width + kT - 1) / kT) * ((c.height + kT - 1) / kT);
+    mx = n > mx ? n : mx;
+  }
+  return mx;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-size_t loss_workspace(const glam_views& v) {
-  return align256(4ull * 9 * (size_t)v.n_pix) + align256(8ull * (size_t)v.n_tiles);
-}
+size_t loss_workspace(const glam_views& v) { return align256(8ull * 3 * (size_t)max_tiles32(v) * (size_t)v.n); }
 
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
                         float* dimage, float* loss, void* ws, hipStream_t s) {
-  if (v.n_tiles == 0) return GLAM_OK;
-  float* maps = static_cast<float*>(ws);
-  float* partial = reinterpret_cast<float*>(static_cast<char*>(ws) + align256(4ull * 9 * (size_t)v.n_pix));
-  hipLaunchKernelGGL(ssim_fwd_kernel, dim3((unsigned)v.n_tiles), dim3(256), 0, s, v.dev, v.n, image, target, w_ssim,
-                     maps, (long long)v.n_pix, partial);
-  hipLaunchKernelGGL(ssim_bwd_kernel, dim3((unsigned)v.n_tiles), dim3(256), 0, s, v.dev, v.n, image, target, w_ssim,
-                     maps, (long long)v.n_pix, dimage);
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, partial, w_ssim, loss);
+  if (v.n_tiles == 0 || v.n == 0) return GLAM_OK;
+  const int mt = max_tiles32(v);
+  float* partial = static_cast<float*>(ws);
+  hipLaunchKernelGGL(loss_kernel, dim3((unsigned)mt, (unsigned)v.n, 3), dim3(256), 0, s, v.dev, mt, image, target,
+                     w_ssim, dimage, partial);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, mt, partial, w_ssim, loss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
