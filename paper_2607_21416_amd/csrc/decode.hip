@@ -272,82 +272,42 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
 // adjoint
 // ---------------------------------------------------------------------------------
 
-template <int F, int K>
-struct BwdAcc {
-  f4 dW2[2 * (Cfg<F, K>::OT0 + Cfg<F, K>::OT1 + Cfg<F, K>::OT2)];
-  f4 dW1[6 * ((Cfg<F, K>::NIN + 15) / 16)];
-  float db2[(11 * K + 63) / 64];
-  float db1[2];
+// The adjoint is split by MLP: a workgroup differentiates one of the three MLPs (for
+// the covariance MLP, the largest, two workgroups share the work), so a wave holds
+// only that MLP's weight-gradient accumulators in registers and stages only its
+// weights in LDS.  Everything the three MLPs share (the input rows Z and the ReLU
+// pattern of their own hidden layer) is cheap to rebuild.
+constexpr int kBwdWaves = 4;
+constexpr int kBwdBlocksPerCU = 2;  // workgroups resident per CU (registers: two waves per SIMD)
+
+template <int F, int K, int ML>
+struct MCfg {
+  static constexpr int NIN = F + 4;
+  static constexpr int OUT = ML == 0 ? K : (ML == 1 ? 3 * K : 7 * K);
+  static constexpr int OT = (OUT + 15) / 16;   // 16-row tiles of the outputs
+  static constexpr int KS1 = NIN / 4;          // K-steps of layer 1
+  static constexpr int KS2 = (OUT + 3) / 4;    // K-steps over the outputs
+  static constexpr int NC1 = (NIN + 15) / 16;  // 16-column tiles of W1
+  static constexpr int W1S = NIN + 1, W2S = kHid + 1;  // padded LDS rows
+  static constexpr int LW1 = 0, LB1 = kHid * W1S, LW2 = LB1 + kHid, LB2 = LW2 + OUT * W2S;
+  static constexpr int PW = (LB2 + OUT + 3) & ~3;
+  static constexpr int PM = kHid * NIN + kHid + OUT * kHid + OUT;  // packed parameters
+  static constexpr int ZS = NIN + 1, YS = OUT + 1, HS = kHid + 1;
+  static constexpr int WAVE_WORDS = 16 * (ZS + YS + HS) + 16;
+  static constexpr int SMEM = PW + kBwdWaves * WAVE_WORDS;
 };
 
-// dH^T of MLP ML: A[i][k] = W2[k][i] over the outputs (K-steps of 4), B = dY^T from LDS.
-template <int F, int K, int ML>
-__device__ __forceinline__ void dhidden(const float* p, const float* dy, int l, f4 dH[6]) {
-  using C = Cfg<F, K>;
-  constexpr MlpOff O = mlp_offsets(F, K);
-  constexpr int out = O.out[ML];
-  constexpr int ks_n = (out + 3) / 4;
-  const int li = l & 15, lg = l >> 4;
-#pragma unroll
-  for (int ht = 0; ht < 2; ++ht) {
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < ks_n; ++ks) {
-      const int o = ks * 4 + lg;
-      const float a = o < out ? p[lds_offsets(F, K).w2[ML] + o * C::W2S + ht * 16 + li] : 0.f;
-      const float b = o < out ? dy[li * C::YS + O.yoff[ML] + o] : 0.f;
-      acc = mfma(a, b, acc);
-    }
-    dH[2 * ML + ht] = acc;
-  }
+template <int F, int K>
+constexpr int bwd_smem_words() {
+  constexpr int a = MCfg<F, K, 0>::SMEM, b = MCfg<F, K, 1>::SMEM, c = MCfg<F, K, 2>::SMEM;
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-// dW2 of MLP ML += dY^T H over the 16 anchors of the chunk (A from dY, B from H in LDS).
-template <int F, int K, int ML, int OT, int BASE>
-__device__ __forceinline__ void acc_dW2(const float* dy, const float* hs, int l, f4* dW2) {
-  using C = Cfg<F, K>;
-  constexpr MlpOff O = mlp_offsets(F, K);
-  constexpr int out = O.out[ML];
-  const int li = l & 15, lg = l >> 4;
-#pragma unroll
-  for (int ot = 0; ot < OT; ++ot) {
-    const int o = ot * 16 + li;
-#pragma unroll
-    for (int ht = 0; ht < 2; ++ht) {
-      f4 acc = dW2[BASE + ot * 2 + ht];
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int an = ks * 4 + lg;
-        const float a = o < out ? dy[an * C::YS + O.yoff[ML] + o] : 0.f;
-        const float b = hs[an * C::HS + ML * 32 + ht * 16 + li];
-        acc = mfma(a, b, acc);
-      }
-      dW2[BASE + ot * 2 + ht] = acc;
-    }
-  }
-}
-
-template <int F, int K, int ML, int OT, int BASE>
-__device__ __forceinline__ void store_dW2(const f4* dW2, float* red, int l) {
-  constexpr MlpOff O = mlp_offsets(F, K);
-  constexpr int out = O.out[ML];
-  const int li = l & 15, lg = l >> 4;
-#pragma unroll
-  for (int ot = 0; ot < OT; ++ot)
-#pragma unroll
-    for (int ht = 0; ht < 2; ++ht)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = ot * 16 + 4 * lg + r;
-        if (o < out) atomicAdd(&red[O.w2[ML] + o * kHid + ht * 16 + li], dW2[BASE + ot * 2 + ht][r]);
-      }
-}
-
-// Work split of the adjoint: partition m owns workgroups [first[m], first[m+1]) of a 1-D
-// grid (about one workgroup per CU, shared in proportion to the partitions' anchor
-// counts); leader[m] is the first of the partition's (consecutive) views.
+// Work split: partition slot k owns units [first[k], first[k+1]) (about three per CU in
+// total, in proportion to anchor counts); gridDim.y = 4 selects the MLP: 0 opacity,
+// 1 colour, 2 and 3 the two halves of the covariance MLP.  leader[k] is the first of
+// the slot's (consecutive) views.
 constexpr int kMaxBwdParts = 256;
-constexpr int kBwdWaves = 4;
 struct BwdGrid {
   int n_parts;
   int first[kMaxBwdParts + 1];
@@ -355,46 +315,52 @@ struct BwdGrid {
   int n_views_of[kMaxBwdParts];
 };
 
-// Orders this wave's LDS traffic (the waves of a workgroup run independently).
-
-template <int F, int K>
-__global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
-                                                                    const glam_view_info* views, int sigmoid_op,
-                                                                    glam_gaussians dg, BwdGrid grid, float* dfeat,
-                                                                    float* doffs, float* dlog_scale, float* partial) {
-  using C = Cfg<F, K>;
+template <int F, int K, int ML>
+__device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__ mlp,
+                               const glam_view_info* views, int sigmoid_op, const glam_gaussians& dg,
+                               const BwdGrid& grid, int half, float* doffs, float* dfeat_part, float* dls_part,
+                               float* partial, float* smem) {
+  using C = MCfg<F, K, ML>;
   constexpr MlpOff O = mlp_offsets(F, K);
-  constexpr int NT2 = 2 * (C::OT0 + C::OT1 + C::OT2);
-  constexpr int NC1 = (C::NIN + 15) / 16;
-  extern __shared__ float smem[];
-  // partition of this workgroup
+  constexpr int OUT = C::OUT;
   int m = 0;
   while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
-  const int b_local = blockIdx.x - grid.first[m], nb = grid.first[m + 1] - grid.first[m];
+  const int nb0 = grid.first[m + 1] - grid.first[m];
+  const int b_local = ML == 2 ? 2 * ((int)blockIdx.x - grid.first[m]) + half : (int)blockIdx.x - grid.first[m];
+  const int nb = ML == 2 ? 2 * nb0 : nb0;
   const int v0 = grid.leader[m], v1 = v0 + grid.n_views_of[m];
   const glam_view_info lead = views[v0];
   const int A = lead.anchor_count;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
   float* s_p = smem;
-  float* base = smem + C::PA + w * (16 * C::ZS + 16 * C::YS + 16 * C::HS + 16);
-  float* s_z = base;
+  float* s_z = smem + C::PW + w * C::WAVE_WORDS;
   float* s_y = s_z + 16 * C::ZS;
   float* s_h = s_y + 16 * C::YS;
   float* s_ds = s_h + 16 * C::HS;
-  const float* pm = mlp + (size_t)lead.cam.partition * C::P;
-  load_weights<F, K>(pm, s_p, t, 64 * kBwdWaves);
+  {  // this MLP's weights, padded rows
+    const float* pm = mlp + (size_t)lead.cam.partition * O.total + O.w1[ML];
+    for (int i = t; i < C::PM; i += 64 * kBwdWaves) {
+      int dst;
+      if (i < kHid * C::NIN) dst = C::LW1 + (i / C::NIN) * C::W1S + i % C::NIN;
+      else if (i < kHid * C::NIN + kHid) dst = C::LB1 + (i - kHid * C::NIN);
+      else if (i < kHid * C::NIN + kHid + OUT * kHid) {
+        const int j = i - kHid * C::NIN - kHid;
+        dst = C::LW2 + (j / kHid) * C::W2S + j % kHid;
+      } else dst = C::LB2 + (i - kHid * C::NIN - kHid - OUT * kHid);
+      s_p[dst] = pm[i];
+    }
+  }
   __syncthreads();
-  f4 dW2[NT2];
-  f4 dW1[6 * NC1];
-  float db2[(C::NY + 63) / 64];
-  float db1[2];
+  f4 dW2[2 * C::OT];
+  f4 dW1[2 * C::NC1];
+  float db2[(OUT + 63) / 64];
+  float db1 = 0.f;
 #pragma unroll
-  for (int i = 0; i < NT2; ++i) dW2[i] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 2 * C::OT; ++i) dW2[i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < 6 * NC1; ++i) dW1[i] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 2 * C::NC1; ++i) dW1[i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < (C::NY + 63) / 64; ++i) db2[i] = 0.f;
-  db1[0] = db1[1] = 0.f;
+  for (int i = 0; i < (OUT + 63) / 64; ++i) db2[i] = 0.f;
   const long long n = dg.n;
   const size_t GK = (size_t)an.A * K;
   const int n_chunks = (A + 15) / 16;
@@ -410,14 +376,39 @@ __global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors
       const glam_view_info vw = views[v];
       build_z<F, K>(an, vw, a0, s_z, l);  // zero rows past the partition
       wave_sync();
-      f4 H[6];
-      layer1<F, K>(s_p, s_z, l, H);
-      layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
-      layer2<F, K, 1, C::OT1>(s_p, H, s_y, l);
-      layer2<F, K, 2, C::OT2>(s_p, H, s_y, l);
-      // H to LDS (anchor-major) for the dW2 contraction
+      // layer 1, this MLP's 32 hidden rows: H^T tiles in the MFMA output layout
+      f4 H[2];
 #pragma unroll
-      for (int mt = 0; mt < 6; ++mt)
+      for (int mt = 0; mt < 2; ++mt) {
+        const float* W1 = s_p + C::LW1 + (mt * 16 + li) * C::W1S;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < C::KS1; ++ks) acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = fmaxf(acc[r] + s_p[C::LB1 + mt * 16 + 4 * lg + r], 0.f);
+        H[mt] = acc;
+      }
+      // layer 2 into LDS (Y^T tiles from the H^T registers, permuted K)
+#pragma unroll
+      for (int ot = 0; ot < C::OT; ++ot) {
+        const int o = ot * 16 + li;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float a = o < OUT ? s_p[C::LW2 + o * C::W2S + t2 * 16 + 4 * lg + r] : 0.f;
+            acc = mfma(a, H[t2][r], acc);
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = ot * 16 + 4 * lg + r;
+          if (orow < OUT) s_y[li * C::YS + orow] = acc[r] + s_p[C::LB2 + orow];
+        }
+      }
+      // H to LDS, anchor-major, for dW2
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = H[mt][r];
       wave_sync();
@@ -428,181 +419,264 @@ __global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors
         const int ai = gi / K, j = gi % K, a = a0 + ai;
         float* y = s_y + ai * C::YS;
         if (a >= A) {
-          y[j] = 0.f;
-          for (int c = 0; c < 3; ++c) y[K + 3 * j + c] = 0.f;
-          for (int k = 0; k < 7; ++k) y[4 * K + 7 * j + k] = 0.f;
+          if (ML == 0) y[j] = 0.f;
+          if (ML == 1)
+            for (int c = 0; c < 3; ++c) y[3 * j + c] = 0.f;
+          if (ML == 2)
+            for (int k = 0; k < 7; ++k) y[7 * j + k] = 0.f;
           continue;
         }
         const int ga = vw.anchor_begin + a;
         const long long g = vw.g_begin + (long long)a * K + j;
-        const float es = expf(an.log_scale[ga]);
-        float ds = 0.f;
-        const float yo = y[j];
-        const float dop = dg.opacity[g];
-        if (sigmoid_op) {
-          const float al = sigmoid(yo);
-          y[j] = dop * al * (1.f - al);
+        if (ML == 0) {
+          const float yo = y[j];
+          const float dop = dg.opacity[g];
+          if (sigmoid_op) {
+            const float al = sigmoid(yo);
+            y[j] = dop * al * (1.f - al);
+          } else {
+            const float al = tanhf(yo);
+            y[j] = al > 0.f ? dop * (1.f - al * al) : 0.f;
+          }
+          // the mean is x_a + e^{s_a} o: offsets and log-scale
+          const float es = expf(an.log_scale[ga]);
+          const size_t go = (size_t)ga * K + j;
+          float ds = 0.f;
+          for (int i = 0; i < 3; ++i) {
+            const float dm = dg.mean[i * n + g];
+            doff[q][i] = fmaf(es, dm, doff[q][i]);
+            ds = fmaf(es * an.offs[i * GK + go], dm, ds);
+          }
+          atomicAdd(&s_ds[ai], ds);
+        } else if (ML == 1) {
+          for (int c = 0; c < 3; ++c) {
+            const float col = sigmoid(y[3 * j + c]);
+            y[3 * j + c] = dg.rgb[c * n + g] * col * (1.f - col);
+          }
         } else {
-          const float al = tanhf(yo);
-          y[j] = al > 0.f ? dop * (1.f - al * al) : 0.f;
+          const float es = expf(an.log_scale[ga]);
+          float* yc = y + 7 * j;
+          float ds = 0.f;
+          for (int k = 0; k < 3; ++k) {
+            const float sg = sigmoid(yc[k]);
+            const float dsc = dg.scale[k * n + g];
+            yc[k] = dsc * es * sg * (1.f - sg);
+            ds = fmaf(dsc, es * sg, ds);
+          }
+          const float nr = sqrtf(yc[3] * yc[3] + yc[4] * yc[4] + yc[5] * yc[5] + yc[6] * yc[6] + 1e-24f);
+          const float inv = 1.f / nr;
+          float dq[4], qd = 0.f;
+          for (int k = 0; k < 4; ++k) { dq[k] = dg.quat[k * n + g]; qd = fmaf(yc[3 + k] * inv, dq[k], qd); }
+          for (int k = 0; k < 4; ++k) yc[3 + k] = (dq[k] - yc[3 + k] * inv * qd) * inv;
+          atomicAdd(&s_ds[ai], ds);
         }
-        for (int c = 0; c < 3; ++c) {
-          const float col = sigmoid(y[K + 3 * j + c]);
-          y[K + 3 * j + c] = dg.rgb[c * n + g] * col * (1.f - col);
-        }
-        float* yc = y + 4 * K + 7 * j;
-        for (int k = 0; k < 3; ++k) {
-          const float sg = sigmoid(yc[k]);
-          const float dsc = dg.scale[k * n + g];
-          yc[k] = dsc * es * sg * (1.f - sg);
-          ds = fmaf(dsc, es * sg, ds);
-        }
-        const float nr = sqrtf(yc[3] * yc[3] + yc[4] * yc[4] + yc[5] * yc[5] + yc[6] * yc[6] + 1e-24f);
-        const float inv = 1.f / nr;
-        float dq[4], qd = 0.f;
-        for (int k = 0; k < 4; ++k) { dq[k] = dg.quat[k * n + g]; qd = fmaf(yc[3 + k] * inv, dq[k], qd); }
-        for (int k = 0; k < 4; ++k) yc[3 + k] = (dq[k] - yc[3 + k] * inv * qd) * inv;
-        const size_t go = (size_t)ga * K + j;
-        for (int i = 0; i < 3; ++i) {
-          const float dm = dg.mean[i * n + g];
-          doff[q][i] = fmaf(es, dm, doff[q][i]);
-          ds = fmaf(es * an.offs[i * GK + go], dm, ds);
-        }
-        atomicAdd(&s_ds[ai], ds);
       }
       wave_sync();
-      // dH = W2^T dY, masked by the ReLU (H > 0 exactly where pre > 0)
-      f4 dP[6];
-      dhidden<F, K, 0>(s_p, s_y, l, dP);
-      dhidden<F, K, 1>(s_p, s_y, l, dP);
-      dhidden<F, K, 2>(s_p, s_y, l, dP);
+      // dH^T = W2^T dY^T, masked by the ReLU (H > 0 exactly where the pre-activation is)
+      f4 dP[2];
 #pragma unroll
-      for (int mt = 0; mt < 6; ++mt)
+      for (int ht = 0; ht < 2; ++ht) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dP[mt][r] = H[mt][r] > 0.f ? dP[mt][r] : 0.f;
-      // dZ (feature rows only) = W1^T dPre, K-steps over hidden rows in register order
+        for (int ks = 0; ks < C::KS2; ++ks) {
+          const int o = ks * 4 + lg;
+          const float a = o < OUT ? s_p[C::LW2 + o * C::W2S + ht * 16 + li] : 0.f;
+          const float b = o < OUT ? s_y[li * C::YS + o] : 0.f;
+          acc = mfma(a, b, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = H[ht][r] > 0.f ? acc[r] : 0.f;
+        dP[ht] = acc;
+      }
+      // dZ (feature rows) += W1^T dPre, K-steps over hidden rows in register order
 #pragma unroll
       for (int ft = 0; ft < F / 16; ++ft) {
         f4 acc = dZ[ft];
 #pragma unroll
-        for (int mt = 0; mt < 6; ++mt)
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int h = mt * 16 + 4 * lg + r;
-            const float a = s_p[lds_offsets(F, K).w1[h >> 5] + (h & 31) * C::W1S + ft * 16 + li];
-            acc = mfma(a, dP[mt][r], acc);
-          }
+          for (int r = 0; r < 4; ++r)
+            acc = mfma(s_p[C::LW1 + (mt * 16 + 4 * lg + r) * C::W1S + ft * 16 + li], dP[mt][r], acc);
         dZ[ft] = acc;
       }
-      // dW2 += dY^T H, db2 += sum dY
-      acc_dW2<F, K, 0, C::OT0, 0>(s_y, s_h, l, dW2);
-      acc_dW2<F, K, 1, C::OT1, 2 * C::OT0>(s_y, s_h, l, dW2);
-      acc_dW2<F, K, 2, C::OT2, 2 * (C::OT0 + C::OT1)>(s_y, s_h, l, dW2);
+      // dW2 += dY^T H over the chunk's 16 anchors, db2 += sum of dY
 #pragma unroll
-      for (int i = 0; i < (C::NY + 63) / 64; ++i) {
+      for (int ot = 0; ot < C::OT; ++ot) {
+        const int o = ot * 16 + li;
+#pragma unroll
+        for (int ht = 0; ht < 2; ++ht) {
+          f4 acc = dW2[ot * 2 + ht];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int an_ = ks * 4 + lg;
+            const float a = o < OUT ? s_y[an_ * C::YS + o] : 0.f;
+            acc = mfma(a, s_h[an_ * C::HS + ht * 16 + li], acc);
+          }
+          dW2[ot * 2 + ht] = acc;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < (OUT + 63) / 64; ++i) {
         const int o = l + 64 * i;
-        if (o < C::NY)
+        if (o < OUT)
           for (int an_ = 0; an_ < 16; ++an_) db2[i] += s_y[an_ * C::YS + o];
       }
       wave_sync();
-      // dPre to LDS (reusing the H buffer) for dW1 += dPre^T Z, db1 += sum dPre
+      // dPre to LDS (reusing the H rows) for dW1 += dPre^T Z, db1 += sum of dPre
 #pragma unroll
-      for (int mt = 0; mt < 6; ++mt)
+      for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dP[mt][r];
       wave_sync();
 #pragma unroll
-      for (int mt = 0; mt < 6; ++mt)
+      for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int ct = 0; ct < NC1; ++ct) {
-          f4 acc = dW1[mt * NC1 + ct];
+        for (int ct = 0; ct < C::NC1; ++ct) {
+          f4 acc = dW1[mt * C::NC1 + ct];
           const int col = ct * 16 + li;
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int an_ = ks * 4 + lg;
-            const float a = s_h[an_ * C::HS + mt * 16 + li];
             const float b = col < C::NIN ? s_z[an_ * C::ZS + col] : 0.f;
-            acc = mfma(a, b, acc);
+            acc = mfma(s_h[an_ * C::HS + mt * 16 + li], b, acc);
           }
-          dW1[mt * NC1 + ct] = acc;
+          dW1[mt * C::NC1 + ct] = acc;
         }
-      for (int i = 0; i < 2; ++i) {
-        const int h = l + 64 * i;
-        if (h < 96)
-          for (int an_ = 0; an_ < 16; ++an_) db1[i] += s_h[an_ * C::HS + h];
-      }
+      if (l < kHid)
+        for (int an_ = 0; an_ < 16; ++an_) db1 += s_h[an_ * C::HS + l];
       wave_sync();
     }
-    // anchor gradients of this chunk (all views summed)
+    // this MLP's share of the anchor gradients (all views summed)
 #pragma unroll
     for (int ft = 0; ft < F / 16; ++ft)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = a0 + li;
-        if (a < A) dfeat[(size_t)(lead.anchor_begin + a) * F + ft * 16 + 4 * lg + r] = dZ[ft][r];
+        if (a < A) dfeat_part[(size_t)(lead.anchor_begin + a) * F + ft * 16 + 4 * lg + r] = dZ[ft][r];
       }
-    if (l < 16 && a0 + l < A) dlog_scale[lead.anchor_begin + a0 + l] = s_ds[l];
-    for (int q = 0; q < 3; ++q) {
-      const int gi = l + 64 * q;
-      if (gi >= 16 * K) break;
-      const int ai = gi / K, j = gi % K, a = a0 + ai;
-      if (a >= A) continue;
-      const size_t go = (size_t)(lead.anchor_begin + a) * K + j;
-      for (int i = 0; i < 3; ++i) doffs[i * GK + go] = doff[q][i];
-    }
+    if (ML != 1 && l < 16 && a0 + l < A) dls_part[lead.anchor_begin + a0 + l] = s_ds[l];
+    if (ML == 0)
+      for (int q = 0; q < 3; ++q) {
+        const int gi = l + 64 * q;
+        if (gi >= 16 * K) break;
+        const int ai = gi / K, j = gi % K, a = a0 + ai;
+        if (a >= A) continue;
+        const size_t go = (size_t)(lead.anchor_begin + a) * K + j;
+        for (int i = 0; i < 3; ++i) doffs[i * GK + go] = doff[q][i];
+      }
     wave_sync();
   }
-  // workgroup reduction of the weight gradients into the packed layout
+  // workgroup reduction of this MLP's weight gradients into the packed layout
   __syncthreads();
-  float* red = s_p;
-  for (int i = t; i < C::P; i += 64 * kBwdWaves) red[i] = 0.f;
+  float* red = s_p;  // packed offsets relative to this MLP's first parameter
+  for (int i = t; i < C::PM; i += 64 * kBwdWaves) red[i] = 0.f;
   __syncthreads();
-  store_dW2<F, K, 0, C::OT0, 0>(dW2, red, l);
-  store_dW2<F, K, 1, C::OT1, 2 * C::OT0>(dW2, red, l);
-  store_dW2<F, K, 2, C::OT2, 2 * (C::OT0 + C::OT1)>(dW2, red, l);
+  constexpr int RW2 = kHid * C::NIN + kHid, RB2 = RW2 + OUT * kHid, RB1 = kHid * C::NIN;
 #pragma unroll
-  for (int i = 0; i < (C::NY + 63) / 64; ++i) {
+  for (int ot = 0; ot < C::OT; ++ot)
+#pragma unroll
+    for (int ht = 0; ht < 2; ++ht)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = ot * 16 + 4 * lg + r;
+        if (o < OUT) atomicAdd(&red[RW2 + o * kHid + ht * 16 + li], dW2[ot * 2 + ht][r]);
+      }
+#pragma unroll
+  for (int i = 0; i < (OUT + 63) / 64; ++i) {
     const int o = l + 64 * i;
-    if (o < C::NY) {
-      const int ml = o < K ? 0 : (o < 4 * K ? 1 : 2);
-      atomicAdd(&red[O.b2[ml] + o - O.yoff[ml]], db2[i]);
-    }
+    if (o < OUT) atomicAdd(&red[RB2 + o], db2[i]);
   }
 #pragma unroll
-  for (int mt = 0; mt < 6; ++mt)
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int ct = 0; ct < NC1; ++ct)
+    for (int ct = 0; ct < C::NC1; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h = mt * 16 + 4 * lg + r, col = ct * 16 + li;
-        if (col < C::NIN) atomicAdd(&red[O.w1[h >> 5] + (h & 31) * C::NIN + col], dW1[mt * NC1 + ct][r]);
+        if (col < C::NIN) atomicAdd(&red[h * C::NIN + col], dW1[mt * C::NC1 + ct][r]);
       }
-  for (int i = 0; i < 2; ++i) {
-    const int h = l + 64 * i;
-    if (h < 96) atomicAdd(&red[O.b1[h >> 5] + (h & 31)], db1[i]);
-  }
+  if (l < kHid) atomicAdd(&red[RB1 + l], db1);
   __syncthreads();
-  float* dst = partial + (size_t)blockIdx.x * C::P;
-  for (int i = t; i < C::P; i += 64 * kBwdWaves) dst[i] = red[i];
+  // partial rows: plane 0 holds every MLP's share, plane 1 the second covariance half
+  float* dst = partial + ((size_t)(ML == 2 ? half : 0) * gridDim.x + blockIdx.x) * O.total + O.w1[ML];
+  for (int i = t; i < C::PM; i += 64 * kBwdWaves) dst[i] = red[i];
 }
 
-// dmlp[m] = sum of partition m's workgroup partials (zero for partitions without
-// views).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
-__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* partial, BwdGrid grid, int P, int M,
-                                                              float* dmlp) {
+template <int F, int K>
+__global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
+                                                                    const glam_view_info* views, int sigmoid_op,
+                                                                    glam_gaussians dg, BwdGrid grid, float* doffs,
+                                                                    float* dfeat_part, float* dls_part,
+                                                                    float* partial) {
+  extern __shared__ float smem[];
+  const size_t AF = (size_t)an.A * F;
+  switch (blockIdx.y) {
+    case 0:
+      decode_bwd_mlp<F, K, 0>(an, mlp, views, sigmoid_op, dg, grid, 0, doffs, dfeat_part, dls_part, partial, smem);
+      break;
+    case 1:
+      decode_bwd_mlp<F, K, 1>(an, mlp, views, sigmoid_op, dg, grid, 0, doffs, dfeat_part + AF, dls_part, partial,
+                              smem);
+      break;
+    default:
+      decode_bwd_mlp<F, K, 2>(an, mlp, views, sigmoid_op, dg, grid, (int)blockIdx.y - 2, doffs, dfeat_part + 2 * AF,
+                              dls_part + an.A, partial, smem);
+      break;
+  }
+}
+
+// dmlp[m] = sum of partition m's workgroup partials (plane 1 only holds covariance
+// parameters).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
+__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* partial, BwdGrid grid, int P, int cov0,
+                                                              int n_units, float* dmlp) {
   __shared__ float s[16][17];
   const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
   const int i = blockIdx.x * 16 + c;
   const int slot = blockIdx.y;  // index into grid (partitions with views)
   float acc = 0.f;
-  if (i < P)
+  if (i < P) {
     for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16) acc += partial[(size_t)b * P + i];
+    if (i >= cov0)
+      for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16)
+        acc += partial[((size_t)n_units + b) * P + i];
+  }
   s[r][c] = acc;
   __syncthreads();
   if (r == 0 && i < P) {
     float t = 0.f;
     for (int k = 0; k < 16; ++k) t += s[k][c];
     dmlp[(size_t)grid.leader[slot] * P + i] = t;  // leader holds the partition index here
+  }
+}
+
+// Anchor ranges that some view covers, sorted by start.
+struct Covered {
+  int n;
+  int begin[kMaxBwdParts];
+  int end[kMaxBwdParts];
+};
+
+// dfeat = sum of the three MLPs' parts, dlog_scale = mean part + scale part; anchors of
+// partitions without views get zero gradients (offsets included).
+template <int F, int K>
+__global__ void __launch_bounds__(256) anchor_grad_combine_kernel(const float* dfeat_part, const float* dls_part,
+                                                                  int A, Covered cov, float* dfeat, float* doffs,
+                                                                  float* dls) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long AF = (long long)A * F;
+  if (i >= AF) return;
+  const int a = (int)(i / F);
+  int lo = 0, hi = cov.n - 1;  // last range starting at or before a
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cov.begin[mid] <= a) lo = mid; else hi = mid - 1;
+  }
+  const bool in = cov.n > 0 && cov.begin[lo] <= a && a < cov.end[lo];
+  dfeat[i] = in ? dfeat_part[i] + dfeat_part[AF + i] + dfeat_part[2 * AF + i] : 0.f;
+  if (i % F == 0) {
+    dls[a] = in ? dls_part[a] + dls_part[A + a] : 0.f;
+    if (!in)
+      for (int k = 0; k < 3 * K; ++k) doffs[(size_t)(k / K) * A * K + (size_t)a * K + k % K] = 0.f;
   }
 }
 
@@ -615,12 +689,6 @@ template <int F, int K>
 size_t fwd_smem() {
   using C = Cfg<F, K>;
   return sizeof(float) * (C::PA + 4 * 16 * C::ZS + 4 * 16 * C::YS);
-}
-
-template <int F, int K>
-size_t bwd_smem() {
-  using C = Cfg<F, K>;
-  return sizeof(float) * (C::PA + kBwdWaves * (16 * C::ZS + 16 * C::YS + 16 * C::HS + 16));
 }
 
 // Raises a kernel's dynamic LDS limit above the 64 KiB default.  Not a stream operation;
@@ -638,9 +706,11 @@ int max_anchors(const glam_views& v) {
   return mx;
 }
 
-// One workgroup per CU in total, shared by the partitions in proportion to their anchor
-// counts (at least one each, never more than their 16-anchor chunks / 8 waves).
-int total_bwd_blocks() { return cu_count(); }
+// Units (one workgroup for each of the opacity and colour MLPs, two for the covariance
+// MLP) in total: enough for kBwdBlocksPerCU resident workgroups on every CU, shared by
+// the partitions in proportion to their anchor counts (at least one each, never more
+// than their 16-anchor chunks / waves).
+int total_bwd_units() { return cu_count() * kBwdBlocksPerCU / 4; }
 
 bool bwd_grid(const glam_views& v, BwdGrid& g) {
   g.n_parts = 0;
@@ -657,7 +727,7 @@ bool bwd_grid(const glam_views& v, BwdGrid& g) {
     ++g.n_parts;
     total_anchors += vi.anchor_count;
   }
-  const int budget = total_bwd_blocks();
+  const int budget = total_bwd_units();
   int b = 0;
   for (int k = 0; k < g.n_parts; ++k) {
     const int A = v.host[g.leader[k]].anchor_count;
@@ -690,27 +760,68 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
+// Workspace of the adjoint: weight-gradient partials (two planes of units x P),
+// per-MLP anchor feature gradients [3][A][F] and log-scale parts [2][A].
+struct BwdWs {
+  size_t partial, dfeat, dls, total;
+};
+
+BwdWs bwd_ws(int F, int K, int A, int units) {
+  const MlpOff o = mlp_offsets(F, K);
+  BwdWs w;
+  const size_t u = units > 0 ? (size_t)units : 1;
+  w.partial = 0;
+  w.dfeat = (2 * u * (size_t)o.total * 4 + 255) & ~size_t(255);
+  w.dls = w.dfeat + ((3 * (size_t)A * F * 4 + 255) & ~size_t(255));
+  w.total = w.dls + ((2 * (size_t)A * 4 + 255) & ~size_t(255));
+  return w;
+}
+
 template <int F, int K>
 glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v, bool sig,
                            const glam_gaussians& dg, float* dfeat, float* doffs, float* dls, float* dmlp, void* ws,
                            hipStream_t s) {
-  using C = Cfg<F, K>;
+  constexpr int P = mlp_offsets(F, K).total;
   BwdGrid g;
   if (!bwd_grid(v, g)) return GLAM_ERR_UNSUPPORTED;
-  float* partial = static_cast<float*>(ws);
+  const int units = g.first[g.n_parts];
+  const BwdWs W = bwd_ws(F, K, a.A, units);
+  char* w = static_cast<char*>(ws);
+  float* partial = reinterpret_cast<float*>(w + W.partial);
+  float* dfp = reinterpret_cast<float*>(w + W.dfeat);
+  float* dlp = reinterpret_cast<float*>(w + W.dls);
   // partitions without views get zero gradients
-  const long long nm = (long long)n_parts * C::P;
+  const long long nm = (long long)n_parts * P;
   hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, dmlp, nm);
-  if (g.first[g.n_parts] > 0) {
-    const size_t sm = bwd_smem<F, K>();
+  if (units > 0) {
+    const size_t sm = sizeof(float) * bwd_smem_words<F, K>();
     if (!set_smem_limit((const void*)decode_bwd_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
-    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(g.first[g.n_parts]), dim3(64 * kBwdWaves), sm, s, a, mlp,
-                       v.dev, sig ? 1 : 0, dg, g, dfeat, doffs, dls, partial);
+    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(units, 4), dim3(64 * kBwdWaves), sm, s, a, mlp, v.dev,
+                       sig ? 1 : 0, dg, g, doffs, dfp, dlp, partial);
     // the reduction writes dmlp[partition of slot k]: pass partitions in place of leaders
     BwdGrid r = g;
     for (int k = 0; k < g.n_parts; ++k) r.leader[k] = v.host[g.leader[k]].cam.partition;
-    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((C::P + 15) / 16, g.n_parts), dim3(256), 0, s, partial, r, C::P,
-                       n_parts, dmlp);
+    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((P + 15) / 16, g.n_parts), dim3(256), 0, s, partial, r, P,
+                       mlp_offsets(F, K).w1[2], units, dmlp);
+  }
+  if (a.A > 0) {
+    Covered cov;
+    cov.n = 0;
+    for (int k = 0; k < g.n_parts; ++k) {
+      const glam_view_info& vi = v.host[g.leader[k]];
+      if (vi.anchor_count == 0) continue;
+      int pos = cov.n++;
+      while (pos > 0 && cov.begin[pos - 1] > vi.anchor_begin) {
+        cov.begin[pos] = cov.begin[pos - 1];
+        cov.end[pos] = cov.end[pos - 1];
+        --pos;
+      }
+      cov.begin[pos] = vi.anchor_begin;
+      cov.end[pos] = vi.anchor_begin + vi.anchor_count;
+    }
+    const long long AF = (long long)a.A * F;
+    hipLaunchKernelGGL((anchor_grad_combine_kernel<F, K>), dim3((unsigned)((AF + 255) / 256)), dim3(256), 0, s, dfp,
+                       dlp, a.A, cov, dfeat, doffs, dls);
   }
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
@@ -729,10 +840,9 @@ glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_vi
 
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts) {
   (void)n_parts;
-  const MlpOff o = mlp_offsets(a.F, a.K);
   BwdGrid g;
   if (!bwd_grid(v, g)) return 0;
-  return sizeof(float) * (size_t)o.total * (size_t)(g.first[g.n_parts] > 0 ? g.first[g.n_parts] : 1);
+  return bwd_ws(a.F, a.K, a.A, g.first[g.n_parts]).total;
 }
 
 glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v, bool sig,

@@ -112,6 +112,15 @@ __device__ __forceinline__ void leave_queue(uint32_t* q, uint32_t total_waves, i
   }
 }
 
+// The few longest items (horizon tiles, thousands of entries) bound the kernel's end:
+// their waves get a higher issue priority on their SIMD, the short items fill in around
+// them.
+constexpr uint32_t kLongRange = 1024;
+__device__ __forceinline__ void long_item_priority(uint32_t len) {
+  if (len >= kLongRange) __builtin_amdgcn_s_setprio(2);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
 // Gathered record of one range entry.
@@ -154,6 +163,7 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
     const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
+    long_item_priority(e - s);
     const float px = it.x + 0.5f, py = it.y + 0.5f;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int last = 0, stop = (int)(e - s);
@@ -296,6 +306,7 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restr
     const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
+    long_item_priority(e - s);
     const float px = it.x + 0.5f, py = it.y + 0.5f;
     float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     float B0 = bg ? bg[0] : 0.f, B1 = bg ? bg[1] : 0.f, B2 = bg ? bg[2] : 0.f;
