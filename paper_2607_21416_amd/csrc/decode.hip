@@ -367,6 +367,35 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   // each wave walks its chunks independently: no workgroup barrier until the end
   for (int chunk = b_local * kBwdWaves + w; chunk < n_chunks; chunk += nb * kBwdWaves) {
     const int a0 = chunk * 16;
+    // view-independent inputs, loaded once per chunk: features into Z, anchor
+    // positions, and (per Gaussian of this lane) e^{s_a} and the offsets
+    {
+      float fv[16 * F / 64];
+#pragma unroll
+      for (int k = 0; k < 16 * F / 64; ++k) {
+        const int idx = l + 64 * k, ai = idx / F, a = a0 + ai;
+        fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < 16 * F / 64; ++k) {
+        const int idx = l + 64 * k;
+        s_z[(idx / F) * C::ZS + idx % F] = fv[k];
+      }
+    }
+    float apos[3] = {0.f, 0.f, 0.f};
+    if (l < 16 && a0 + l < A)
+      for (int i = 0; i < 3; ++i) apos[i] = an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l];
+    float es[3] = {0.f, 0.f, 0.f}, off[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int gi = l + 64 * q, ai = gi / K, a = a0 + ai;
+      if (ML != 1 && gi < 16 * K && a < A) {
+        const int ga = lead.anchor_begin + a;
+        es[q] = expf(an.log_scale[ga]);
+        if (ML == 0)
+          for (int i = 0; i < 3; ++i) off[q][i] = an.offs[i * GK + (size_t)ga * K + gi % K];
+      }
+    }
     f4 dZ[F / 16];
 #pragma unroll
     for (int i = 0; i < F / 16; ++i) dZ[i] = f4{0.f, 0.f, 0.f, 0.f};
@@ -374,7 +403,43 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
     if (l < 16) s_ds[l] = 0.f;
     for (int v = v0; v < v1; ++v) {
       const glam_view_info vw = views[v];
-      build_z<F, K>(an, vw, a0, s_z, l);  // zero rows past the partition
+      // this view's incoming Gaussian gradients, in flight while the MLP is recomputed
+      float pg[3][7];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int gi = l + 64 * q, a = a0 + gi / K;
+        const bool ok = gi < 16 * K && a < A;
+        const long long g = vw.g_begin + (long long)a * K + gi % K;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) pg[q][k] = 0.f;
+        if (ok) {
+          if (ML == 0) {
+            pg[q][0] = dg.opacity[g];
+            for (int i = 0; i < 3; ++i) pg[q][1 + i] = dg.mean[i * n + g];
+          } else if (ML == 1) {
+            for (int c = 0; c < 3; ++c) pg[q][c] = dg.rgb[c * n + g];
+          } else {
+            for (int k = 0; k < 3; ++k) pg[q][k] = dg.scale[k * n + g];
+            for (int k = 0; k < 4; ++k) pg[q][3 + k] = dg.quat[k * n + g];
+          }
+        }
+      }
+      // direction and distance from this view's camera centre (zero rows past the partition)
+      if (l < 16) {
+        float d[3] = {0.f, 0.f, 0.f}, delta = 0.f;
+        if (a0 + l < A) {
+          float xc[3];
+          camera_centre(vw.cam, xc);
+          for (int i = 0; i < 3; ++i) d[i] = apos[i] - xc[i];
+          delta = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          const float inv = 1.f / delta;
+          for (int i = 0; i < 3; ++i) d[i] *= inv;
+        }
+        s_z[l * C::ZS + F + 0] = d[0];
+        s_z[l * C::ZS + F + 1] = d[1];
+        s_z[l * C::ZS + F + 2] = d[2];
+        s_z[l * C::ZS + F + 3] = delta;
+      }
       wave_sync();
       // layer 1, this MLP's 32 hidden rows: H^T tiles in the MFMA output layout
       f4 H[2];
@@ -413,6 +478,7 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = H[mt][r];
       wave_sync();
       // activation adjoints, one lane per Gaussian; dY overwrites Y in place
+#pragma unroll
       for (int q = 0; q < 3; ++q) {
         const int gi = l + 64 * q;
         if (gi >= 16 * K) break;
@@ -426,11 +492,9 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
             for (int k = 0; k < 7; ++k) y[7 * j + k] = 0.f;
           continue;
         }
-        const int ga = vw.anchor_begin + a;
-        const long long g = vw.g_begin + (long long)a * K + j;
         if (ML == 0) {
           const float yo = y[j];
-          const float dop = dg.opacity[g];
+          const float dop = pg[q][0];
           if (sigmoid_op) {
             const float al = sigmoid(yo);
             y[j] = dop * al * (1.f - al);
@@ -439,35 +503,32 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
             y[j] = al > 0.f ? dop * (1.f - al * al) : 0.f;
           }
           // the mean is x_a + e^{s_a} o: offsets and log-scale
-          const float es = expf(an.log_scale[ga]);
-          const size_t go = (size_t)ga * K + j;
           float ds = 0.f;
           for (int i = 0; i < 3; ++i) {
-            const float dm = dg.mean[i * n + g];
-            doff[q][i] = fmaf(es, dm, doff[q][i]);
-            ds = fmaf(es * an.offs[i * GK + go], dm, ds);
+            const float dm = pg[q][1 + i];
+            doff[q][i] = fmaf(es[q], dm, doff[q][i]);
+            ds = fmaf(es[q] * off[q][i], dm, ds);
           }
           atomicAdd(&s_ds[ai], ds);
         } else if (ML == 1) {
           for (int c = 0; c < 3; ++c) {
             const float col = sigmoid(y[3 * j + c]);
-            y[3 * j + c] = dg.rgb[c * n + g] * col * (1.f - col);
+            y[3 * j + c] = pg[q][c] * col * (1.f - col);
           }
         } else {
-          const float es = expf(an.log_scale[ga]);
           float* yc = y + 7 * j;
           float ds = 0.f;
           for (int k = 0; k < 3; ++k) {
             const float sg = sigmoid(yc[k]);
-            const float dsc = dg.scale[k * n + g];
-            yc[k] = dsc * es * sg * (1.f - sg);
-            ds = fmaf(dsc, es * sg, ds);
+            const float dsc = pg[q][k];
+            yc[k] = dsc * es[q] * sg * (1.f - sg);
+            ds = fmaf(dsc, es[q] * sg, ds);
           }
           const float nr = sqrtf(yc[3] * yc[3] + yc[4] * yc[4] + yc[5] * yc[5] + yc[6] * yc[6] + 1e-24f);
           const float inv = 1.f / nr;
-          float dq[4], qd = 0.f;
-          for (int k = 0; k < 4; ++k) { dq[k] = dg.quat[k * n + g]; qd = fmaf(yc[3 + k] * inv, dq[k], qd); }
-          for (int k = 0; k < 4; ++k) yc[3 + k] = (dq[k] - yc[3 + k] * inv * qd) * inv;
+          float qd = 0.f;
+          for (int k = 0; k < 4; ++k) qd = fmaf(yc[3 + k] * inv, pg[q][3 + k], qd);
+          for (int k = 0; k < 4; ++k) yc[3 + k] = (pg[q][3 + k] - yc[3 + k] * inv * qd) * inv;
           atomicAdd(&s_ds[ai], ds);
         }
       }

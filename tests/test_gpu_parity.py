@@ -35,10 +35,20 @@ def partition_without_anchors():
     return synth.anchor_scene(1013, [600, 0, 300], 1, W=96, H=64, fx=70.0, ssim_weight=0.2)
 
 
+def partition_without_views():
+    # the middle partition has anchors but no view: its gradients must be zero
+    s = synth.anchor_scene(1014, [500, 400, 300], 1, W=96, H=64, fx=70.0, ssim_weight=0.2)
+    keep = [i for i, c in enumerate(s["cams"]) if c["partition"] != 1]
+    s["cams"] = [s["cams"][i] for i in keep]
+    s["targets"] = [s["targets"][i] for i in keep]
+    return s
+
+
 # full-size workloads: config 2 (20k anchors, one 1226x370 view) and config 3 (50k
 # anchors, four views, the benchmark's workload)
 SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "anchor_small": anchor_small,
-          "empty_partition": partition_without_anchors, "C2": lambda: synth.config("C2"),
+          "empty_partition": partition_without_anchors, "viewless_partition": partition_without_views,
+          "C2": lambda: synth.config("C2"),
           "C3": lambda: synth.config("C3")}
 
 
