@@ -128,56 +128,6 @@ __device__ __forceinline__ void camera_centre(const glam_camera& c, float xc[3])
   for (int i = 0; i < 3; ++i) xc[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
 }
 
-// Z rows of 16 anchors [a0, a0+16) of one view into z (zero rows past the partition).
-template <int F, int K>
-__device__ __forceinline__ void build_z(const glam_anchors& an, const glam_view_info& vw, int a0, float* z, int l) {
-  using C = Cfg<F, K>;
-  const int A = vw.anchor_count;
-  for (int idx = l; idx < 16 * F; idx += 64) {
-    const int ai = idx / F, k = idx % F, a = a0 + ai;
-    z[ai * C::ZS + k] = a < A ? an.feat[(size_t)(vw.anchor_begin + a) * F + k] : 0.f;
-  }
-  if (l < 16) {
-    const int a = a0 + l;
-    float d[3] = {0.f, 0.f, 0.f}, delta = 0.f;
-    if (a < A) {
-      float xc[3];
-      camera_centre(vw.cam, xc);
-      const int ga = vw.anchor_begin + a;
-      for (int i = 0; i < 3; ++i) d[i] = an.pos[(size_t)i * an.A + ga] - xc[i];
-      delta = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const float inv = 1.f / delta;
-      for (int i = 0; i < 3; ++i) d[i] *= inv;
-    }
-    z[l * C::ZS + F + 0] = d[0];
-    z[l * C::ZS + F + 1] = d[1];
-    z[l * C::ZS + F + 2] = d[2];
-    z[l * C::ZS + F + 3] = delta;
-  }
-}
-
-// Layer 1 for all three MLPs: H^T tiles (ReLU applied), lane layout of the MFMA output.
-template <int F, int K>
-__device__ __forceinline__ void layer1(const float* p, const float* z, int l, f4 H[6]) {
-  using C = Cfg<F, K>;
-  constexpr LdsOff O = lds_offsets(F, K);
-  const int li = l & 15, lg = l >> 4;
-#pragma unroll
-  for (int mt = 0; mt < 6; ++mt) {
-    const int h = mt * 16 + li, ml = h >> 5, hi = h & 31;
-    const float* W1 = p + O.w1[ml] + hi * C::W1S;
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < C::KS1; ++ks) acc = mfma(W1[ks * 4 + lg], z[li * C::ZS + ks * 4 + lg], acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int hr = mt * 16 + 4 * lg + r;
-      acc[r] = fmaxf(acc[r] + p[O.b1[hr >> 5] + (hr & 31)], 0.f);
-    }
-    H[mt] = acc;
-  }
-}
-
 // Layer 2 of MLP ml: Y^T tiles from the H^T registers (permuted K), stored to y.
 template <int F, int K, int ML, int OT>
 __device__ __forceinline__ void layer2(const float* p, const f4 H[6], float* y, int l) {
@@ -213,58 +163,142 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One block stages its partition's weights once and then runs `chunks` consecutive
-// groups of 64 anchors; each wave owns 16 anchors of a group and its own LDS rows, so
-// after the weights are in place the waves proceed independently.
+// Work split of the decode and its adjoint over partitions: partition slot k (a run of
+// consecutive views of one partition) owns workgroups [first[k], first[k+1]) of a 1-D
+// grid, shared in proportion to the partitions' anchor counts; leader[k] is the first
+// of the slot's views.
+constexpr int kMaxBwdParts = 256;
+struct BwdGrid {
+  int n_parts;
+  int first[kMaxBwdParts + 1];
+  int leader[kMaxBwdParts];
+  int n_views_of[kMaxBwdParts];
+};
+
+// A workgroup stages its partition's weights once; each wave then takes 16-anchor
+// chunks and, for every view of the partition, decodes the chunk's Gaussians.  What
+// does not depend on the view (features, the features' share of layer 1, positions,
+// scales, offsets) is loaded and computed once per chunk.
 template <int F, int K>
 __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const float* __restrict__ mlp,
-                                                     const glam_view_info* views, int sigmoid_op, int chunks,
+                                                     const glam_view_info* views, int sigmoid_op, BwdGrid grid,
                                                      glam_gaussians out) {
   using C = Cfg<F, K>;
+  constexpr LdsOff L = lds_offsets(F, K);
   extern __shared__ float smem[];
-  const glam_view_info vw = views[blockIdx.y];
-  const int A = vw.anchor_count;
-  const int block0 = blockIdx.x * chunks * 64;
-  if (block0 >= A) return;
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  int m = 0;
+  while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
+  const int b_local = (int)blockIdx.x - grid.first[m], nb = grid.first[m + 1] - grid.first[m];
+  const int v0 = grid.leader[m], v1 = v0 + grid.n_views_of[m];
+  const glam_view_info lead = views[v0];
+  const int A = lead.anchor_count;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
   float* s_p = smem;
   float* s_z = s_p + C::PA + w * 16 * C::ZS;
   float* s_y = smem + C::PA + 4 * 16 * C::ZS + w * 16 * C::YS;
-  const float* pm = mlp + (size_t)vw.cam.partition * C::P;
-  load_weights<F, K>(pm, s_p, t, 256);
+  load_weights<F, K>(mlp + (size_t)lead.cam.partition * C::P, s_p, t, 256);
   __syncthreads();
   const long long n = out.n;
   const size_t GK = (size_t)an.A * K;
-  for (int c = 0; c < chunks; ++c) {
-    const int a0 = block0 + c * 64 + w * 16;
-    if (a0 >= A) break;
-    build_z<F, K>(an, vw, a0, s_z, l);
-    wave_sync();
-    f4 H[6];
-    layer1<F, K>(s_p, s_z, l, H);
-    layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
-    layer2<F, K, 1, C::OT1>(s_p, H, s_y, l);
-    layer2<F, K, 2, C::OT2>(s_p, H, s_y, l);
-    wave_sync();
-    for (int gi = l; gi < 16 * K; gi += 64) {
-      const int ai = gi / K, j = gi % K, a = a0 + ai;
-      if (a >= A) continue;
-      const int ga = vw.anchor_begin + a;
-      const float* y = s_y + ai * C::YS;
-      const long long g = vw.g_begin + (long long)a * K + j;
-      const float yo = y[j];
-      out.opacity[g] = sigmoid_op ? sigmoid(yo) : tanhf(yo);
-      for (int c3 = 0; c3 < 3; ++c3) out.rgb[c3 * n + g] = sigmoid(y[K + 3 * j + c3]);
-      const float es = expf(an.log_scale[ga]);
-      for (int k = 0; k < 3; ++k) out.scale[k * n + g] = es * sigmoid(y[4 * K + 7 * j + k]);
-      const float* q = y + 4 * K + 7 * j + 3;
-      const float inv = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] + 1e-24f);
-      for (int k = 0; k < 4; ++k) out.quat[k * n + g] = q[k] * inv;
-      const size_t go = (size_t)ga * K + j;
-      for (int i = 0; i < 3; ++i) out.mean[i * n + g] = fmaf(es, an.offs[i * GK + go], an.pos[(size_t)i * an.A + ga]);
+  const int n_chunks = (A + 15) / 16;
+  for (int chunk = b_local * 4 + w; chunk < n_chunks; chunk += nb * 4) {
+    const int a0 = chunk * 16;
+    {
+      float fv[16 * F / 64];
+#pragma unroll
+      for (int k = 0; k < 16 * F / 64; ++k) {
+        const int idx = l + 64 * k, a = a0 + idx / F;
+        fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < 16 * F / 64; ++k) {
+        const int idx = l + 64 * k;
+        s_z[(idx / F) * C::ZS + idx % F] = fv[k];
+      }
     }
-    // the next group's inputs overwrite rows this group's outputs were read from
+    float apos[3] = {0.f, 0.f, 0.f};
+    if (l < 16 && a0 + l < A)
+      for (int i = 0; i < 3; ++i) apos[i] = an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l];
+    // per Gaussian of this lane: e^{s_a} and its (view-independent) mean
+    float es[3] = {0.f, 0.f, 0.f}, mu[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int gi = l + 64 * q, a = a0 + gi / K;
+      if (gi < 16 * K && a < A) {
+        const int ga = lead.anchor_begin + a;
+        es[q] = expf(an.log_scale[ga]);
+        for (int i = 0; i < 3; ++i)
+          mu[q][i] = fmaf(es[q], an.offs[i * GK + (size_t)ga * K + gi % K], an.pos[(size_t)i * an.A + ga]);
+      }
+    }
     wave_sync();
+    // the features' share of layer 1 (all K-steps but the last, which holds d and delta)
+    f4 PF[6];
+#pragma unroll
+    for (int mt = 0; mt < 6; ++mt) {
+      const int h = mt * 16 + li;
+      const float* W1 = s_p + L.w1[h >> 5] + (h & 31) * C::W1S;
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < C::KS1 - 1; ++ks) acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], acc);
+      PF[mt] = acc;
+    }
+    for (int v = v0; v < v1; ++v) {
+      const glam_view_info vw = views[v];
+      if (l < 16) {
+        float d[3] = {0.f, 0.f, 0.f}, delta = 0.f;
+        if (a0 + l < A) {
+          float xc[3];
+          camera_centre(vw.cam, xc);
+          for (int i = 0; i < 3; ++i) d[i] = apos[i] - xc[i];
+          delta = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          const float inv = 1.f / delta;
+          for (int i = 0; i < 3; ++i) d[i] *= inv;
+        }
+        s_z[l * C::ZS + F + 0] = d[0];
+        s_z[l * C::ZS + F + 1] = d[1];
+        s_z[l * C::ZS + F + 2] = d[2];
+        s_z[l * C::ZS + F + 3] = delta;
+      }
+      wave_sync();
+      f4 H[6];
+#pragma unroll
+      for (int mt = 0; mt < 6; ++mt) {
+        const int h = mt * 16 + li;
+        const float* W1 = s_p + L.w1[h >> 5] + (h & 31) * C::W1S;
+        constexpr int ks = C::KS1 - 1;
+        f4 acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], PF[mt]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int hr = mt * 16 + 4 * lg + r;
+          acc[r] = fmaxf(acc[r] + s_p[L.b1[hr >> 5] + (hr & 31)], 0.f);
+        }
+        H[mt] = acc;
+      }
+      layer2<F, K, 0, C::OT0>(s_p, H, s_y, l);
+      layer2<F, K, 1, C::OT1>(s_p, H, s_y, l);
+      layer2<F, K, 2, C::OT2>(s_p, H, s_y, l);
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int gi = l + 64 * q;
+        if (gi >= 16 * K) break;
+        const int ai = gi / K, j = gi % K, a = a0 + ai;
+        if (a >= A) continue;
+        const float* y = s_y + ai * C::YS;
+        const long long g = vw.g_begin + (long long)a * K + j;
+        const float yo = y[j];
+        out.opacity[g] = sigmoid_op ? sigmoid(yo) : tanhf(yo);
+        for (int c3 = 0; c3 < 3; ++c3) out.rgb[c3 * n + g] = sigmoid(y[K + 3 * j + c3]);
+        for (int k = 0; k < 3; ++k) out.scale[k * n + g] = es[q] * sigmoid(y[4 * K + 7 * j + k]);
+        const float* qv = y + 4 * K + 7 * j + 3;
+        const float inv = 1.f / sqrtf(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3] + 1e-24f);
+        for (int k = 0; k < 4; ++k) out.quat[k * n + g] = qv[k] * inv;
+        for (int i = 0; i < 3; ++i) out.mean[i * n + g] = mu[q][i];
+      }
+      // the next view's rows overwrite rows these outputs were read from
+      wave_sync();
+    }
   }
 }
 
@@ -303,17 +337,8 @@ constexpr int bwd_smem_words() {
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-// Work split: partition slot k owns units [first[k], first[k+1]) (about three per CU in
-// total, in proportion to anchor counts); gridDim.y = 4 selects the MLP: 0 opacity,
-// 1 colour, 2 and 3 the two halves of the covariance MLP.  leader[k] is the first of
-// the slot's (consecutive) views.
-constexpr int kMaxBwdParts = 256;
-struct BwdGrid {
-  int n_parts;
-  int first[kMaxBwdParts + 1];
-  int leader[kMaxBwdParts];
-  int n_views_of[kMaxBwdParts];
-};
+// In the adjoint, gridDim.y = 4 selects the MLP: 0 opacity, 1 colour, 2 and 3 the two
+// halves of the covariance MLP.
 
 template <int F, int K, int ML>
 __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__ mlp,
@@ -773,7 +798,7 @@ int max_anchors(const glam_views& v) {
 // than their 16-anchor chunks / waves).
 int total_bwd_units() { return cu_count() * kBwdBlocksPerCU / 4; }
 
-bool bwd_grid(const glam_views& v, BwdGrid& g) {
+bool bwd_grid(const glam_views& v, BwdGrid& g, int budget) {
   g.n_parts = 0;
   long long total_anchors = 0;
   for (int i = 0; i < v.n; ++i) {
@@ -788,7 +813,6 @@ bool bwd_grid(const glam_views& v, BwdGrid& g) {
     ++g.n_parts;
     total_anchors += vi.anchor_count;
   }
-  const int budget = total_bwd_units();
   int b = 0;
   for (int k = 0; k < g.n_parts; ++k) {
     const int A = v.host[g.leader[k]].anchor_count;
@@ -805,18 +829,12 @@ bool bwd_grid(const glam_views& v, BwdGrid& g) {
 template <int F, int K>
 glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig,
                        const glam_gaussians& out, hipStream_t s) {
-  const int mx = max_anchors(v);
-  if (mx == 0 || v.n == 0) return GLAM_OK;
+  if (max_anchors(v) == 0 || v.n == 0) return GLAM_OK;
+  BwdGrid g;
+  if (!bwd_grid(v, g, 2 * cu_count())) return GLAM_ERR_UNSUPPORTED;  // two workgroups per CU
   const size_t sm = fwd_smem<F, K>();
   if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
-  // groups of 64 anchors per block: enough blocks to fill every CU four times over,
-  // each staging the weights as few times as that allows
-  const int groups = (mx + 63) / 64;
-  const long long target = 4LL * cu_count();
-  int chunks = (int)(((long long)groups * v.n + target - 1) / target);
-  chunks = chunks < 1 ? 1 : (chunks > 16 ? 16 : chunks);
-  const int nbx = (groups + chunks - 1) / chunks;
-  hipLaunchKernelGGL((decode_kernel<F, K>), dim3(nbx, v.n), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0, chunks,
+  hipLaunchKernelGGL((decode_kernel<F, K>), dim3(g.first[g.n_parts]), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0, g,
                      out);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
@@ -844,7 +862,7 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
                            hipStream_t s) {
   constexpr int P = mlp_offsets(F, K).total;
   BwdGrid g;
-  if (!bwd_grid(v, g)) return GLAM_ERR_UNSUPPORTED;
+  if (!bwd_grid(v, g, total_bwd_units())) return GLAM_ERR_UNSUPPORTED;
   const int units = g.first[g.n_parts];
   const BwdWs W = bwd_ws(F, K, a.A, units);
   char* w = static_cast<char*>(ws);
@@ -902,7 +920,7 @@ glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_vi
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts) {
   (void)n_parts;
   BwdGrid g;
-  if (!bwd_grid(v, g)) return 0;
+  if (!bwd_grid(v, g, total_bwd_units())) return 0;
   return bwd_ws(a.F, a.K, a.A, g.first[g.n_parts]).total;
 }
 
