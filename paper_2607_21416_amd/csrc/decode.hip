@@ -421,9 +421,18 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
           for (int i = 0; i < 3; ++i) off[q][i] = an.offs[i * GK + (size_t)ga * K + gi % K];
       }
     }
-    f4 dZ[F / 16];
+    wave_sync();
+    // the features' share of layer 1 (all K-steps but the last, which holds d and delta)
+    f4 PF[2], dPsum[2];
 #pragma unroll
-    for (int i = 0; i < F / 16; ++i) dZ[i] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < 2; ++mt) {
+      const float* W1 = s_p + C::LW1 + (mt * 16 + li) * C::W1S;
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < C::KS1 - 1; ++ks) acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], acc);
+      PF[mt] = acc;
+      dPsum[mt] = f4{0.f, 0.f, 0.f, 0.f};
+    }
     float doff[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     if (l < 16) s_ds[l] = 0.f;
     for (int v = v0; v < v1; ++v) {
@@ -471,9 +480,8 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
         const float* W1 = s_p + C::LW1 + (mt * 16 + li) * C::W1S;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < C::KS1; ++ks) acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], acc);
+        constexpr int ks = C::KS1 - 1;
+        f4 acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], PF[mt]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = fmaxf(acc[r] + s_p[C::LB1 + mt * 16 + 4 * lg + r], 0.f);
         H[mt] = acc;
@@ -574,17 +582,9 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         for (int r = 0; r < 4; ++r) acc[r] = H[ht][r] > 0.f ? acc[r] : 0.f;
         dP[ht] = acc;
       }
-      // dZ (feature rows) += W1^T dPre, K-steps over hidden rows in register order
+      // the features' gradients and weight gradients are linear in dPre: sum it over views
 #pragma unroll
-      for (int ft = 0; ft < F / 16; ++ft) {
-        f4 acc = dZ[ft];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc = mfma(s_p[C::LW1 + (mt * 16 + 4 * lg + r) * C::W1S + ft * 16 + li], dP[mt][r], acc);
-        dZ[ft] = acc;
-      }
+      for (int mt = 0; mt < 2; ++mt) dPsum[mt] += dP[mt];
       // dW2 += dY^T H over the chunk's 16 anchors, db2 += sum of dY
 #pragma unroll
       for (int ot = 0; ot < C::OT; ++ot) {
@@ -614,23 +614,54 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dP[mt][r];
       wave_sync();
+      // dW1 columns of d and delta (the last column tile), this view
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        constexpr int ct = F / 16;
+        f4 acc = dW1[mt * C::NC1 + ct];
+        const int col = ct * 16 + li;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int an_ = ks * 4 + lg;
+          const float b = col < C::NIN ? s_z[an_ * C::ZS + col] : 0.f;
+          acc = mfma(s_h[an_ * C::HS + mt * 16 + li], b, acc);
+        }
+        dW1[mt * C::NC1 + ct] = acc;
+      }
+      wave_sync();
+    }
+    // per chunk, from the view sum of dPre: feature columns of dW1, db1, and the
+    // features' gradients dZ = W1_f^T dPre
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dPsum[mt][r];
+    wave_sync();
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int ct = 0; ct < F / 16; ++ct) {
+        f4 acc = dW1[mt * C::NC1 + ct];
+        const int col = ct * 16 + li;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int an_ = ks * 4 + lg;
+          acc = mfma(s_h[an_ * C::HS + mt * 16 + li], s_z[an_ * C::ZS + col], acc);
+        }
+        dW1[mt * C::NC1 + ct] = acc;
+      }
+    if (l < kHid)
+      for (int an_ = 0; an_ < 16; ++an_) db1 += s_h[an_ * C::HS + l];
+    f4 dZ[F / 16];
+#pragma unroll
+    for (int ft = 0; ft < F / 16; ++ft) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int ct = 0; ct < C::NC1; ++ct) {
-          f4 acc = dW1[mt * C::NC1 + ct];
-          const int col = ct * 16 + li;
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int an_ = ks * 4 + lg;
-            const float b = col < C::NIN ? s_z[an_ * C::ZS + col] : 0.f;
-            acc = mfma(s_h[an_ * C::HS + mt * 16 + li], b, acc);
-          }
-          dW1[mt * C::NC1 + ct] = acc;
-        }
-      if (l < kHid)
-        for (int an_ = 0; an_ < 16; ++an_) db1 += s_h[an_ * C::HS + l];
-      wave_sync();
+        for (int r = 0; r < 4; ++r)
+          acc = mfma(s_p[C::LW1 + (mt * 16 + 4 * lg + r) * C::W1S + ft * 16 + li], dPsum[mt][r], acc);
+      dZ[ft] = acc;
     }
     // this MLP's share of the anchor gradients (all views summed)
 #pragma unroll
