@@ -29,6 +29,7 @@ namespace glam {
 namespace {
 
 constexpr int kWaves = 4;        // waves per workgroup (independent)
+constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
 constexpr int kBlocksPerCU = 8;  // persistent workgroups per CU
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
@@ -145,7 +146,7 @@ struct WaveLds {
   float2 bx[64];
 };
 
-__global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict__ splat,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBlocksPerCU))) render_fwd_kernel(const float* __restrict__ splat,
                                                          const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ order, uint32_t* queue,
@@ -188,11 +189,8 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
       const int nhit = __popcll(hm);
       const int base = (int)(b0 - s) + 1;
       bool wave_done = false;
-      for (int i = 0; i < nhit; ++i) {
-        const float4 r0 = L.r0[i], r1 = L.r1[i];
-        const float2 bx = L.bx[i];
-        float dx, dy, ep, raw;
-        const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+      // One hit, in order: the skip and stop rules of Eq. 1 on this lane's pixel.
+      auto apply = [&](float alpha, const float4& r1, const float2& bx) {
         const float Tn = T * (1.f - alpha);
         const bool ok = !done && alpha >= kAlphaMin;
         const bool halt = ok && Tn < kTMin;
@@ -206,10 +204,38 @@ __global__ void __launch_bounds__(256) render_fwd_kernel(const float* __restrict
         last = take ? entry : last;
         stop = halt ? entry : stop;
         done = done || halt;
+      };
+      // groups of kIlp hits: their alphas are independent and computed side by side,
+      // only the transmittance updates run in sequence
+      int i = 0;
+      for (; i + kIlp <= nhit; i += kIlp) {
+        float4 r0[kIlp], r1[kIlp];
+        float2 bx[kIlp];
+        float alpha[kIlp];
+#pragma unroll
+        for (int k = 0; k < kIlp; ++k) {
+          r0[k] = L.r0[i + k];
+          r1[k] = L.r1[i + k];
+          bx[k] = L.bx[i + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kIlp; ++k) {
+          float dx, dy, ep, raw;
+          alpha[k] = splat_alpha(r0[k], r1[k], px, py, dx, dy, ep, raw);
+        }
+#pragma unroll
+        for (int k = 0; k < kIlp; ++k) apply(alpha[k], r1[k], bx[k]);
         if (__ballot(!done) == 0) {
           wave_done = true;
           break;
         }
+      }
+      for (; !wave_done && i < nhit; ++i) {
+        const float4 r0 = L.r0[i], r1 = L.r1[i];
+        const float2 bx = L.bx[i];
+        float dx, dy, ep, raw;
+        apply(splat_alpha(r0, r1, px, py, dx, dy, ep, raw), r1, bx);
+        if (__ballot(!done) == 0) wave_done = true;
       }
       __builtin_amdgcn_wave_barrier();
       if (wave_done) break;
