@@ -162,7 +162,7 @@ typedef struct {
 } glam_projected;
 
 /* Words of the compositing work-queue buffer (two kernels x (16 counters on separate
-   128-byte lines + an exit count)). */
+   128-byte lines + a line holding the exit count and the long-tile counter)). */
 #define GLAM_QUEUE_WORDS 1088
 
 /* Sorted (tile, Gaussian) pairs, per-tile ranges and the compositing work order. */
@@ -173,7 +173,9 @@ typedef struct {
   int64_t capacity;
   int32_t* status;  /* [8] device: [0] sticky status, [1] pair count (low word),
                        [2..3] required capacity (int64), [4] depth key bits,
-                       [5] tile key bits, [6] radix passes; caller zeroes [0] once   */
+                       [5] tile key bits, [6] radix passes, [7] long tiles (range
+                       of 1024 entries or more, listed first in order, composited
+                       by whole workgroups); caller zeroes [0] once                 */
   uint32_t* order;  /* [n_tiles] tiles by decreasing range length (power-of-two
                        classes), the order the compositing queue hands them out       */
   uint32_t* queue;  /* [GLAM_QUEUE_WORDS] device work-queue counters of the

@@ -430,13 +430,19 @@ __global__ void __launch_bounds__(256) lpt_count_kernel(const uint32_t* ranges, 
   if (threadIdx.x < kLptBuckets && h[threadIdx.x]) atomicAdd(&lpt[threadIdx.x], h[threadIdx.x]);
 }
 
+// Also records in status[7] the number of long tiles (range length at least
+// 2^kLongTileLog2), which are exactly the first classes of the order.
 __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t* ranges, long long n_tiles, uint32_t* lpt,
-                                                          uint32_t* order) {
+                                                          uint32_t* order, int32_t* status) {
   __shared__ uint32_t base[kLptBuckets], h[kLptBuckets], blk[kLptBuckets];
   if (threadIdx.x < kLptBuckets) h[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    for (int b = 0; b < kLptBuckets; ++b) { base[b] = run; run += lpt[b]; }
+    for (int b = 0; b < kLptBuckets; ++b) {
+      base[b] = run;
+      run += lpt[b];
+      if (b == kLptBuckets - 1 - kLongTileLog2 && blockIdx.x == 0) status[7] = (int32_t)run;
+    }
   }
   __syncthreads();
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -509,7 +515,7 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
   const unsigned tb = (unsigned)((v.n_tiles + 255) / 256);
   hipLaunchKernelGGL(lpt_count_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt);
   hipLaunchKernelGGL(lpt_scatter_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt,
-                     bins.order);
+                     bins.order, bins.status);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

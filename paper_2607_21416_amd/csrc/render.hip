@@ -3,10 +3,7 @@
 // Work decomposition.  Gaussians are binned to 16x16 tiles; each tile is split into
 // four 8x8 quadrants, and one wave64 composites one quadrant (one pixel per lane).
 // The (tile, quadrant) items are pulled from a device work queue by a persistent grid
-// (a few workgroups per CU, their four waves fully independent: no workgroup barrier
-// anywhere), in longest-range-first order, so that the few very long tiles near the
-// horizon start first and the short ones fill in behind them.  The queue counter
-// resets itself when the last wave of a launch leaves.
+// (a few workgroups per CU), in longest-range-first order.
 //
 // Per item, a wave walks its tile's depth-sorted range in batches of 64: lane l
 // gathers the 48-byte record of entry b0+l from HBM (the next batch is prefetched into
@@ -16,11 +13,27 @@
 // same record (LDS broadcast) and composite their own pixel.  The wave leaves as soon
 // as all 64 of its pixels have stopped.
 //
+// Long tiles.  A few tiles near the horizon hold thousands of entries whose pixels
+// never saturate; walked by one wave they would set the kernel's length.  Their
+// quadrants are taken first, each by a whole workgroup: the range is cut into rounds
+// of four chunks, one chunk per wave.  Compositing over a chunk is an affine map of
+// the state in front of it -- the colour grows by T times the chunk's own colour L
+// and T is scaled by the chunk's own transmittance P, both computed from T = 1 -- so
+// each wave first composites its chunk locally (no stop rule), the waves exchange
+// (L, P) through LDS, and every wave then knows the transmittance in front of its
+// chunk.  The one chunk in which a pixel's transmittance falls below the stop
+// threshold (the product crosses it there and nowhere else, since it only decreases)
+// is composited again exactly, entry by entry, from that transmittance.
+//
 // The backward walks the same ranges from the wave's last contributor down,
-// recovering T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance.  Per
-// Gaussian, the nine gradient terms of the wave's pixels are summed with a
-// reduce-scatter (two gfx950 lane-swap stages, then DPP within 16-lane rows) and nine
-// lanes add the totals to HBM with one atomic instruction.
+// recovering T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance and
+// carrying the colour behind, B <- B + alpha_i (c_i - B).  Per Gaussian, the nine
+// gradient terms of the wave's pixels are summed with a reduce-scatter (two gfx950
+// lane-swap stages, then DPP within 16-lane rows) and nine lanes add the totals to HBM
+// with one atomic instruction.  For long tiles the workgroup takes rounds of four
+// chunks from the back: each wave composites its chunk locally, and the state behind
+// a chunk follows from the chunks behind it in the round (T divided by their P, B
+// mapped through their affine maps B -> L + P B).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -28,9 +41,10 @@ namespace glam {
 
 namespace {
 
-constexpr int kWaves = 4;        // waves per workgroup (independent)
+constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
 constexpr int kBlocksPerCU = 8;  // persistent workgroups per CU
+constexpr int kChunk = 256;      // entries per wave and round of a long tile
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
 // skip and stop decisions are bit-identical.
@@ -45,10 +59,16 @@ __device__ __forceinline__ float splat_alpha(const float4& r0, const float4& r1,
   return fminf(kAlphaMax, raw);
 }
 
+__device__ __forceinline__ float splat_alpha(const float4& r0, const float4& r1, float px, float py) {
+  float dx, dy, ep, raw;
+  return splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+}
+
 struct Item {
   int x, y;                // this lane's pixel
   bool inside;
-  int qx0, qx1, qy0, qy1;  // the wave's quadrant, clipped to the image (empty if qx0 > qx1)
+  bool live;               // the quadrant has pixels in the image
+  int qx0, qx1, qy0, qy1;  // the wave's quadrant, clipped to the image
   int W, H;
   long long pix_begin;
   long long pix;           // this lane's pixel in the batched per-pixel arrays
@@ -69,6 +89,7 @@ __device__ __forceinline__ Item make_item(const glam_view_info* views, int n_vie
   it.qy0 = qy;
   it.qx1 = min(qx + 7, it.W - 1);
   it.qy1 = min(qy + 7, it.H - 1);
+  it.live = it.qx0 <= it.qx1 && it.qy0 <= it.qy1;
   it.pix_begin = vw.pix_begin;
   it.pix = vw.pix_begin + (long long)it.y * it.W + it.x;
   return it;
@@ -82,16 +103,18 @@ __device__ __forceinline__ bool box_meets(float bxf, float byf, const Item& it) 
 }
 
 // Work queue.  Device-scope atomics are served at the memory side, so one counter would
-// serialise every grab; the longest-first tile list is dealt round-robin over kQueues
-// counters (one 128-byte line each), and workgroup b pulls from counter b % kQueues.
-// Workgroups are dealt to the 8 XCDs round-robin, so all workgroups of one counter sit
-// on one XCD; the four quadrant items of a tile are consecutive grabs of one counter, so
-// the tile's records are fetched into that XCD's L2 once and read there four times.
-// An item is 4 * (tile rank) + quadrant.
+// serialise every grab; the longest-first tile list (after the long tiles) is dealt
+// round-robin over kQueues counters (one 128-byte line each), and workgroup b pulls
+// from counter b % kQueues.  Workgroups are dealt to the 8 XCDs round-robin, so all
+// workgroups of one counter sit on one XCD; the four quadrant items of a tile are
+// consecutive grabs of one counter, so the tile's records are fetched into that XCD's
+// L2 once and read there four times.  An item is 4 * (tile rank) + quadrant.
 // Words [0, kQueues*32) of a queue region hold the counters, word kQueues*32 the exit
-// count.  The last wave to leave resets all of them for the next launch.
+// count and word kQueues*32 + 1 the counter of the long-tile items (taken by whole
+// workgroups).  The last wave to leave resets all of them for the next launch.
 constexpr int kQueues = 16;
 constexpr int kQueueWords = kQueues * 32 + 32;
+constexpr int kExitWord = kQueues * 32, kLongWord = kQueues * 32 + 1;
 static_assert(2 * kQueueWords == GLAM_QUEUE_WORDS, "queue layout");
 
 __device__ __forceinline__ uint32_t next_item(uint32_t* q, int lane) {
@@ -103,23 +126,24 @@ __device__ __forceinline__ uint32_t next_item(uint32_t* q, int lane) {
   return ((v >> 2) * nq + qi) * 4u + (v & 3u);
 }
 
-__device__ __forceinline__ void leave_queue(uint32_t* q, uint32_t total_waves, int lane) {
-  if (lane == 0) {
-    const uint32_t n = atomicAdd(&q[32 * kQueues], 1u);
-    if (n == total_waves - 1) {
-      for (int i = 0; i < kQueues; ++i) atomicExch(&q[32 * i], 0u);
-      atomicExch(&q[32 * kQueues], 0u);
-    }
-  }
+// Next long-tile item for the whole workgroup (every thread must call it).
+__device__ __forceinline__ uint32_t next_long_item(uint32_t* q, uint32_t* s_item) {
+  if (threadIdx.x == 0) *s_item = atomicAdd(&q[kLongWord], 1u);
+  __syncthreads();
+  const uint32_t v = *s_item;
+  __syncthreads();
+  return v;
 }
 
-// The few longest items (horizon tiles, thousands of entries) bound the kernel's end:
-// their waves get a higher issue priority on their SIMD, the short items fill in around
-// them.
-constexpr uint32_t kLongRange = 1024;
-__device__ __forceinline__ void long_item_priority(uint32_t len) {
-  if (len >= kLongRange) __builtin_amdgcn_s_setprio(2);
-  else __builtin_amdgcn_s_setprio(0);
+__device__ __forceinline__ void leave_queue(uint32_t* q, uint32_t total_waves, int lane) {
+  if (lane == 0) {
+    const uint32_t n = atomicAdd(&q[kExitWord], 1u);
+    if (n == total_waves - 1) {
+      for (int i = 0; i < kQueues; ++i) atomicExch(&q[32 * i], 0u);
+      atomicExch(&q[kLongWord], 0u);
+      atomicExch(&q[kExitWord], 0u);
+    }
+  }
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
@@ -138,119 +162,256 @@ __device__ __forceinline__ Rec load_rec(const float* splat, uint32_t gid) {
   return o;
 }
 
-// Wave-private compacted batch: (u, v, A, B), (C, opacity, r, g), (b, entry offset or
-// Gaussian index as bits).
+// Wave-private compacted batch: (u, v, A, B), (C, opacity, r, g), (b, tag as bits).
 struct WaveLds {
   float4 r0[64];
   float4 r1[64];
   float2 bx[64];
 };
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBlocksPerCU))) render_fwd_kernel(const float* __restrict__ splat,
-                                                         const uint32_t* __restrict__ vals,
-                                                         const uint32_t* __restrict__ ranges,
-                                                         const uint32_t* __restrict__ order, uint32_t* queue,
-                                                         const glam_view_info* views, int n_views, int n_tiles,
-                                                         const float* bg, float* image, float* T_final,
-                                                         int32_t* n_contrib, int32_t* n_eval, uint32_t capacity,
-                                                         uint32_t n_gauss) {
+// Exchange of a long-tile round: per wave and lane, up to eight values.
+struct RoundLds {
+  float v[kWaves][8][64];
+};
+
+// Walks entries [c0, c1) (absolute positions in vals) front to back in batches of 64
+// with a register prefetch of the next batch; the hits of each batch are compacted into
+// L (tag: the entry's offset within the batch) and on_batch(nhit, b0) is called; it
+// returns true to end the walk.
+template <class OnBatch>
+__device__ __forceinline__ void walk_front(const float* splat, const uint32_t* vals, uint32_t c0, uint32_t c1,
+                                           uint32_t n_gauss, const Item& it, WaveLds& L, int lane,
+                                           OnBatch on_batch) {
+  if (!it.live || c0 >= c1) return;
+  Rec nxt;
+  if (c0 + lane < c1) nxt = load_rec(splat, min(vals[c0 + lane], n_gauss - 1));
+  for (uint32_t b0 = c0; b0 < c1; b0 += 64) {
+    const Rec cur = nxt;
+    const bool valid = b0 + lane < c1;
+    if (b0 + 64 + lane < c1) nxt = load_rec(splat, min(vals[b0 + 64 + lane], n_gauss - 1));
+    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
+    const uint64_t hm = __ballot(hit);
+    if (hit) {
+      const int pos = __popcll(hm & lanemask_lt(lane));
+      L.r0[pos] = cur.r0;
+      L.r1[pos] = cur.r1;
+      L.bx[pos] = make_float2(cur.r2.x, __int_as_float(lane));
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool end = on_batch(__popcll(hm), b0);
+    __builtin_amdgcn_wave_barrier();
+    if (end) break;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------------
+
+// Per-pixel compositing state; entries are numbered 1.. within the tile range.
+struct FwdState {
+  float T, C0, C1, C2;
+  int last;  // entry of the last composited Gaussian (0: none)
+  int stop;  // entry that stopped the walk, or the range length
+  bool done;
+};
+
+// One hit, in order: the skip and stop rules of Eq. 1 on this lane's pixel.
+__device__ __forceinline__ void fwd_apply(FwdState& st, float alpha, const float4& r1, const float2& bx, int entry) {
+  const float Tn = st.T * (1.f - alpha);
+  const bool ok = !st.done && alpha >= kAlphaMin;
+  const bool halt = ok && Tn < kTMin;
+  const bool take = ok && !(Tn < kTMin);
+  const float wgt = take ? alpha * st.T : 0.f;
+  st.C0 = fmaf(r1.z, wgt, st.C0);
+  st.C1 = fmaf(r1.w, wgt, st.C1);
+  st.C2 = fmaf(bx.x, wgt, st.C2);
+  st.T = take ? Tn : st.T;
+  st.last = take ? entry : st.last;
+  st.stop = halt ? entry : st.stop;
+  st.done = st.done || halt;
+}
+
+// The exact walk of Eq. 1 over entries [c0, c1) of the range starting at s.  Groups of
+// kIlp hits evaluate their alphas side by side; only the updates run in sequence.
+__device__ void fwd_exact(const float* splat, const uint32_t* vals, uint32_t s, uint32_t c0, uint32_t c1,
+                          uint32_t n_gauss, const Item& it, WaveLds& L, int lane, float px, float py, FwdState& st) {
+  if (__ballot(!st.done) == 0) return;
+  walk_front(splat, vals, c0, c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
+    const int base = (int)(b0 - s) + 1;
+    int i = 0;
+    for (; i + kIlp <= nhit; i += kIlp) {
+      float4 r0[kIlp], r1[kIlp];
+      float2 bx[kIlp];
+      float alpha[kIlp];
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) {
+        r0[k] = L.r0[i + k];
+        r1[k] = L.r1[i + k];
+        bx[k] = L.bx[i + k];
+      }
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) alpha[k] = splat_alpha(r0[k], r1[k], px, py);
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) fwd_apply(st, alpha[k], r1[k], bx[k], base + __float_as_int(bx[k].y));
+      if (__ballot(!st.done) == 0) return true;
+    }
+    for (; i < nhit; ++i) {
+      const float4 r0 = L.r0[i], r1 = L.r1[i];
+      const float2 bx = L.bx[i];
+      fwd_apply(st, splat_alpha(r0, r1, px, py), r1, bx, base + __float_as_int(bx.y));
+      if (__ballot(!st.done) == 0) return true;
+    }
+    return false;
+  });
+}
+
+// Local compositing of entries [c0, c1) from T = 1 without the stop rule (pixels with
+// `dead` set take no part): the chunk's own colour L, transmittance P and last
+// composited entry.  Ends early once every live pixel's P is below the stop threshold
+// (such a pixel stops inside this chunk whatever lies in front of it).
+__device__ void fwd_local(const float* splat, const uint32_t* vals, uint32_t s, uint32_t c0, uint32_t c1,
+                          uint32_t n_gauss, const Item& it, WaveLds& L, int lane, float px, float py, bool dead,
+                          float& P, float& L0, float& L1, float& L2, int& last) {
+  P = 1.f;
+  L0 = L1 = L2 = 0.f;
+  last = 0;
+  if (__ballot(!dead) == 0) return;
+  walk_front(splat, vals, c0, c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
+    const int base = (int)(b0 - s) + 1;
+    for (int i = 0; i < nhit; i += kIlp) {
+      float4 r1[kIlp];
+      float2 bx[kIlp];
+      float alpha[kIlp];
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) {
+        const int j = min(i + k, nhit - 1);
+        r1[k] = L.r1[j];
+        bx[k] = L.bx[j];
+        alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) {
+        const bool take = !dead && alpha[k] >= kAlphaMin;
+        const float wgt = take ? alpha[k] * P : 0.f;
+        L0 = fmaf(r1[k].z, wgt, L0);
+        L1 = fmaf(r1[k].w, wgt, L1);
+        L2 = fmaf(bx[k].x, wgt, L2);
+        P = take ? P * (1.f - alpha[k]) : P;
+        last = take ? base + __float_as_int(bx[k].y) : last;
+      }
+    }
+    return __ballot(!dead && !(P < kTMin)) == 0;
+  });
+}
+
+__device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, const float* bgc, float* image,
+                                          float* T_final, int32_t* n_contrib, int32_t* n_eval) {
+  if (!it.inside) return;
+  const long long HW = (long long)it.W * it.H;
+  const long long p = (long long)it.y * it.W + it.x;
+  float* img = image + 3 * it.pix_begin;
+  img[p] = fmaf(st.T, bgc[0], st.C0);
+  img[HW + p] = fmaf(st.T, bgc[1], st.C1);
+  img[2 * HW + p] = fmaf(st.T, bgc[2], st.C2);
+  T_final[it.pix] = st.T;
+  n_contrib[it.pix] = st.last;
+  if (n_eval) n_eval[it.pix] = st.stop;
+}
+
+// A long tile's quadrant, composited by the whole workgroup in rounds of four chunks.
+__device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
+                         const Item& it, WaveLds& L, RoundLds& R, int w, int lane, const float* bgc, float* image,
+                         float* T_final, int32_t* n_contrib, int32_t* n_eval) {
+  const float px = it.x + 0.5f, py = it.y + 0.5f;
+  const int n = (int)(e - s);
+  FwdState st{1.f, 0.f, 0.f, 0.f, 0, n, !it.inside};
+  for (uint32_t r0 = s; r0 < e; r0 += kWaves * kChunk) {
+    const uint32_t c0 = min(r0 + (uint32_t)w * kChunk, e), c1 = min(c0 + kChunk, e);
+    // 1. this wave's chunk, locally
+    float P, L0, L1, L2;
+    int llast;
+    fwd_local(splat, vals, s, c0, c1, n_gauss, it, L, lane, px, py, st.done, P, L0, L1, L2, llast);
+    R.v[w][0][lane] = P;
+    __syncthreads();
+    // 2. transmittance in front of the chunk; the chunk where the pixel stops is redone
+    //    exactly from it
+    float Tin = st.T;
+    bool before = st.done;
+    for (int j = 0; j < w; ++j) {
+      const float Pj = R.v[j][0][lane];
+      if (!before) {
+        if (Tin * Pj < kTMin) before = true;
+        else Tin *= Pj;
+      }
+    }
+    const bool here = !before && Tin * P < kTMin;
+    FwdState ex{Tin, 0.f, 0.f, 0.f, 0, n, !here};
+    fwd_exact(splat, vals, s, c0, c1, n_gauss, it, L, lane, px, py, ex);
+    __syncthreads();  // every wave has read the P values
+    const int state = before ? 0 : (here ? 2 : 1);
+    R.v[w][0][lane] = here ? ex.T : Tin * P;
+    R.v[w][1][lane] = here ? ex.C0 : Tin * L0;
+    R.v[w][2][lane] = here ? ex.C1 : Tin * L1;
+    R.v[w][3][lane] = here ? ex.C2 : Tin * L2;
+    R.v[w][4][lane] = __int_as_float(here ? ex.last : llast);
+    R.v[w][5][lane] = __int_as_float(here ? ex.stop : n);
+    R.v[w][6][lane] = __int_as_float(state);
+    __syncthreads();
+    // 3. every wave merges the four chunks in order (identically)
+    for (int j = 0; j < kWaves; ++j) {
+      const int sj = __float_as_int(R.v[j][6][lane]);
+      if (sj == 0) continue;
+      st.T = R.v[j][0][lane];
+      st.C0 += R.v[j][1][lane];
+      st.C1 += R.v[j][2][lane];
+      st.C2 += R.v[j][3][lane];
+      const int lj = __float_as_int(R.v[j][4][lane]);
+      st.last = lj > 0 ? lj : st.last;
+      if (sj == 2) {
+        st.stop = __float_as_int(R.v[j][5][lane]);
+        st.done = true;
+      }
+    }
+    if (__ballot(!st.done) == 0) break;  // the same decision in every wave
+    __syncthreads();                      // R is rewritten by the next round
+  }
+  if (w == 0) fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
+}
+
+__global__ void __launch_bounds__(256)
+render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
+                  uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, const float* bg,
+                  float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval, uint32_t capacity,
+                  uint32_t n_gauss) {
   __shared__ WaveLds lds[kWaves];
-  const int lane = threadIdx.x & 63;
-  WaveLds& L = lds[threadIdx.x >> 6];
-  const uint32_t n_items = 4u * (uint32_t)n_tiles;
-  const float b0c = bg ? bg[0] : 0.f, b1c = bg ? bg[1] : 0.f, b2c = bg ? bg[2] : 0.f;
+  __shared__ RoundLds round;
+  __shared__ uint32_t s_item;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  WaveLds& L = lds[w];
+  const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
+  const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
+  // long tiles first, one quadrant per workgroup
+  __builtin_amdgcn_s_setprio(2);
+  for (uint32_t li = next_long_item(queue, &s_item); li < 4u * n_long; li = next_long_item(queue, &s_item)) {
+    const int tile = (int)min(order[li >> 2], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(li & 3u), lane);
+    const uint32_t e = min(ranges[2 * tile + 1], capacity);
+    const uint32_t s = min(ranges[2 * tile], e);
+    fwd_long(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
+  }
+  __builtin_amdgcn_s_setprio(0);
+  // the other tiles, one quadrant per wave
+  const uint32_t n_items = 4u * ((uint32_t)n_tiles - n_long);
   for (uint32_t item = next_item(queue, lane); item < n_items; item = next_item(queue, lane)) {
-    const int tile = (int)min(order[item >> 2], (uint32_t)n_tiles - 1);
+    const int tile = (int)min(order[n_long + (item >> 2)], (uint32_t)n_tiles - 1);
     const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
-    long_item_priority(e - s);
-    const float px = it.x + 0.5f, py = it.y + 0.5f;
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    int last = 0, stop = (int)(e - s);
-    bool done = !it.inside;
-    const bool live = it.qx0 <= it.qx1 && it.qy0 <= it.qy1;
-    // prefetch the first batch
-    Rec nxt;
-    if (live && s + lane < e) nxt = load_rec(splat, min(vals[s + lane], n_gauss - 1));
-    for (uint32_t b0 = s; live && b0 < e; b0 += 64) {
-      const Rec cur = nxt;
-      const bool valid = b0 + lane < e;
-      if (b0 + 64 + lane < e) nxt = load_rec(splat, min(vals[b0 + 64 + lane], n_gauss - 1));
-      const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
-      const uint64_t hm = __ballot(hit);
-      if (hit) {
-        const int pos = __popcll(hm & lanemask_lt(lane));
-        L.r0[pos] = cur.r0;
-        L.r1[pos] = cur.r1;
-        L.bx[pos] = make_float2(cur.r2.x, __int_as_float(lane));
-      }
-      __builtin_amdgcn_wave_barrier();
-      const int nhit = __popcll(hm);
-      const int base = (int)(b0 - s) + 1;
-      bool wave_done = false;
-      // One hit, in order: the skip and stop rules of Eq. 1 on this lane's pixel.
-      auto apply = [&](float alpha, const float4& r1, const float2& bx) {
-        const float Tn = T * (1.f - alpha);
-        const bool ok = !done && alpha >= kAlphaMin;
-        const bool halt = ok && Tn < kTMin;
-        const bool take = ok && !(Tn < kTMin);
-        const float wgt = take ? alpha * T : 0.f;
-        C0 = fmaf(r1.z, wgt, C0);
-        C1 = fmaf(r1.w, wgt, C1);
-        C2 = fmaf(bx.x, wgt, C2);
-        T = take ? Tn : T;
-        const int entry = base + __float_as_int(bx.y);
-        last = take ? entry : last;
-        stop = halt ? entry : stop;
-        done = done || halt;
-      };
-      // groups of kIlp hits: their alphas are independent and computed side by side,
-      // only the transmittance updates run in sequence
-      int i = 0;
-      for (; i + kIlp <= nhit; i += kIlp) {
-        float4 r0[kIlp], r1[kIlp];
-        float2 bx[kIlp];
-        float alpha[kIlp];
-#pragma unroll
-        for (int k = 0; k < kIlp; ++k) {
-          r0[k] = L.r0[i + k];
-          r1[k] = L.r1[i + k];
-          bx[k] = L.bx[i + k];
-        }
-#pragma unroll
-        for (int k = 0; k < kIlp; ++k) {
-          float dx, dy, ep, raw;
-          alpha[k] = splat_alpha(r0[k], r1[k], px, py, dx, dy, ep, raw);
-        }
-#pragma unroll
-        for (int k = 0; k < kIlp; ++k) apply(alpha[k], r1[k], bx[k]);
-        if (__ballot(!done) == 0) {
-          wave_done = true;
-          break;
-        }
-      }
-      for (; !wave_done && i < nhit; ++i) {
-        const float4 r0 = L.r0[i], r1 = L.r1[i];
-        const float2 bx = L.bx[i];
-        float dx, dy, ep, raw;
-        apply(splat_alpha(r0, r1, px, py, dx, dy, ep, raw), r1, bx);
-        if (__ballot(!done) == 0) wave_done = true;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (wave_done) break;
-    }
-    if (it.inside) {
-      const long long HW = (long long)it.W * it.H;
-      const long long p = (long long)it.y * it.W + it.x;
-      float* img = image + 3 * it.pix_begin;
-      img[p] = fmaf(T, b0c, C0);
-      img[HW + p] = fmaf(T, b1c, C1);
-      img[2 * HW + p] = fmaf(T, b2c, C2);
-      T_final[it.pix] = T;
-      n_contrib[it.pix] = last;
-      if (n_eval) n_eval[it.pix] = stop;
-    }
+    FwdState st{1.f, 0.f, 0.f, 0.f, 0, (int)(e - s), !it.inside};
+    fwd_exact(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
+    fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
   }
   leave_queue(queue, gridDim.x * kWaves, lane);
 }
@@ -313,115 +474,215 @@ __device__ __forceinline__ int wave_max(int v) {
   return max(max(a, b), max(c, d));
 }
 
-__global__ void __launch_bounds__(256) composite_bwd_kernel(const float* __restrict__ splat,
-                                                            const uint32_t* __restrict__ vals,
-                                                            const uint32_t* __restrict__ ranges,
-                                                            const uint32_t* __restrict__ order, uint32_t* queue,
-                                                            const glam_view_info* views, int n_views, int n_tiles,
-                                                            const float* bg, const float* T_final,
-                                                            const int32_t* n_contrib, const float* dimage,
-                                                            float* g2d, uint32_t capacity, uint32_t n_gauss) {
-  __shared__ WaveLds lds[kWaves];
-  const int lane = threadIdx.x & 63;
-  WaveLds& L = lds[threadIdx.x >> 6];
-  const int comp = reduce9_comp();
-  const uint32_t n_items = 4u * (uint32_t)n_tiles;
-  for (uint32_t item = next_item(queue + kQueueWords, lane); item < n_items;
-       item = next_item(queue + kQueueWords, lane)) {
-    const int tile = (int)min(order[item >> 2], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
-    const uint32_t e = min(ranges[2 * tile + 1], capacity);
-    const uint32_t s = min(ranges[2 * tile], e);
-    long_item_priority(e - s);
-    const float px = it.x + 0.5f, py = it.y + 0.5f;
-    float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    float B0 = bg ? bg[0] : 0.f, B1 = bg ? bg[1] : 0.f, B2 = bg ? bg[2] : 0.f;
-    int last = 0;
-    if (it.inside) {
-      const long long HW = (long long)it.W * it.H;
-      const long long p = (long long)it.y * it.W + it.x;
-      const float* di = dimage + 3 * it.pix_begin;
-      T = T_final[it.pix];
-      last = min(n_contrib[it.pix], (int32_t)(e - s));
-      g0 = di[p];
-      g1 = di[HW + p];
-      g2 = di[2 * HW + p];
+// Per-pixel state of the backward walk: transmittance in front of the current entry,
+// colour behind it, dL/dC and the pixel's last composited entry.
+struct BwdState {
+  float T, B0, B1, B2;
+  float g0, g1, g2;
+  int last;
+};
+
+// The reverse walk over range offsets [lo_end, hi) (from hi - 1 down), relative to the
+// range start s: per hit T_i = T_{i+1} / (1 - alpha_i), the nine gradient terms, one
+// reduction and one atomic per Gaussian, then the colour behind.
+__device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, int lo_end, int hi, uint32_t n_gauss,
+                         const Item& it, WaveLds& L, int lane, int comp, BwdState& st, float* g2d) {
+  if (!it.live || hi <= lo_end) return;
+  const float px = it.x + 0.5f, py = it.y + 0.5f;
+  Rec nxt;
+  uint32_t ngid = 0;
+  {
+    const int lo = max(lo_end, hi - 64);
+    if (lo + lane < hi) {
+      ngid = min(vals[s + lo + lane], n_gauss - 1);
+      nxt = load_rec(splat, ngid);
     }
-    const bool live = it.qx0 <= it.qx1 && it.qy0 <= it.qy1;
-    const int top = live ? wave_max(last) : 0;
-    // batches of 64 entries from the top down; the next lower batch is prefetched
-    Rec nxt;
-    uint32_t ngid = 0;
-    if (top > 0) {
-      const int lo = max(0, top - 64);
-      if (lo + lane < top) {
-        ngid = min(vals[s + lo + lane], n_gauss - 1);
+  }
+  for (int bh = hi; bh > lo_end; bh -= 64) {
+    const int lo = max(lo_end, bh - 64);
+    const Rec cur = nxt;
+    const uint32_t cgid = ngid;
+    const bool valid = lo + lane < bh;
+    if (lo > lo_end) {
+      const int lo2 = max(lo_end, lo - 64);
+      if (lo2 + lane < lo) {
+        ngid = min(vals[s + lo2 + lane], n_gauss - 1);
         nxt = load_rec(splat, ngid);
       }
     }
-    for (int hi = top; hi > 0; hi -= 64) {
-      const int lo = max(0, hi - 64);
-      const Rec cur = nxt;
-      const uint32_t cgid = ngid;
-      const bool valid = lo + lane < hi;
-      if (lo > 0) {
-        const int lo2 = max(0, lo - 64);
-        if (lo2 + lane < lo) {
-          ngid = min(vals[s + lo2 + lane], n_gauss - 1);
-          nxt = load_rec(splat, ngid);
-        }
-      }
-      const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
-      const uint64_t hm = __ballot(hit);
-      if (hit) {
-        const int pos = __popcll(hm & lanemask_lt(lane));
-        L.r0[pos] = cur.r0;
-        L.r1[pos] = cur.r1;
-        L.bx[pos] = make_float2(cur.r2.x, __uint_as_float(cgid));
-      }
-      __builtin_amdgcn_wave_barrier();
-      const int nhit = __popcll(hm);
-      // hits in reverse order; the entry offset of hit i is the position of the i-th
-      // set bit of the ballot mask
-      uint64_t rem = hm;
-      for (int i = nhit - 1; i >= 0; --i) {
-        const int bit = 63 - __clzll((unsigned long long)rem);
-        rem &= ~(1ull << bit);
-        const float4 r0 = L.r0[i], r1 = L.r1[i];
-        const float2 bx = L.bx[i];
-        float dx, dy, ep, raw;
-        const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
-        const bool contrib = lo + bit < last && alpha >= kAlphaMin;
-        if (__ballot(contrib) == 0) continue;
-        // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
-        T = contrib ? T * __builtin_amdgcn_rcpf(1.f - alpha) : T;
-        const float wgt = contrib ? alpha * T : 0.f;
-        const float cb = bx.x;
-        const float dal = contrib ? T * (g0 * (r1.z - B0) + g1 * (r1.w - B1) + g2 * (cb - B2)) : 0.f;
-        const float aB = contrib ? alpha : 0.f;
-        B0 = fmaf(aB, r1.z - B0, B0);
-        B1 = fmaf(aB, r1.w - B1, B1);
-        B2 = fmaf(aB, cb - B2, B2);
-        const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
-        const float dop = free_alpha ? dal * ep : 0.f;
-        const float dp = free_alpha ? dal * alpha : 0.f;
-        float v[9];
-        v[0] = -dp * (r0.z * dx + r0.w * dy);
-        v[1] = -dp * (r0.w * dx + r1.x * dy);
-        v[2] = -0.5f * dp * dx * dx;
-        v[3] = -dp * dx * dy;
-        v[4] = -0.5f * dp * dy * dy;
-        v[5] = dop;
-        v[6] = g0 * wgt;
-        v[7] = g1 * wgt;
-        v[8] = g2 * wgt;
-        const float tot = reduce9(v);
-        if (comp >= 0) atomicAdd(&g2d[(size_t)__float_as_uint(bx.y) * 9 + comp], tot);
-      }
-      __builtin_amdgcn_wave_barrier();
+    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
+    const uint64_t hm = __ballot(hit);
+    if (hit) {
+      const int pos = __popcll(hm & lanemask_lt(lane));
+      L.r0[pos] = cur.r0;
+      L.r1[pos] = cur.r1;
+      L.bx[pos] = make_float2(cur.r2.x, __uint_as_float(cgid));
     }
+    __builtin_amdgcn_wave_barrier();
+    const int nhit = __popcll(hm);
+    // hits in reverse order; the entry offset of hit i is the position of the i-th set
+    // bit of the ballot mask
+    uint64_t rem = hm;
+    for (int i = nhit - 1; i >= 0; --i) {
+      const int bit = 63 - __clzll((unsigned long long)rem);
+      rem &= ~(1ull << bit);
+      const float4 r0 = L.r0[i], r1 = L.r1[i];
+      const float2 bx = L.bx[i];
+      float dx, dy, ep, raw;
+      const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+      const bool contrib = lo + bit < st.last && alpha >= kAlphaMin;
+      if (__ballot(contrib) == 0) continue;
+      // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
+      st.T = contrib ? st.T * __builtin_amdgcn_rcpf(1.f - alpha) : st.T;
+      const float wgt = contrib ? alpha * st.T : 0.f;
+      const float cb = bx.x;
+      const float dal =
+          contrib ? st.T * (st.g0 * (r1.z - st.B0) + st.g1 * (r1.w - st.B1) + st.g2 * (cb - st.B2)) : 0.f;
+      const float aB = contrib ? alpha : 0.f;
+      st.B0 = fmaf(aB, r1.z - st.B0, st.B0);
+      st.B1 = fmaf(aB, r1.w - st.B1, st.B1);
+      st.B2 = fmaf(aB, cb - st.B2, st.B2);
+      const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
+      const float dop = free_alpha ? dal * ep : 0.f;
+      const float dp = free_alpha ? dal * alpha : 0.f;
+      float v[9];
+      v[0] = -dp * (r0.z * dx + r0.w * dy);
+      v[1] = -dp * (r0.w * dx + r1.x * dy);
+      v[2] = -0.5f * dp * dx * dx;
+      v[3] = -dp * dx * dy;
+      v[4] = -0.5f * dp * dy * dy;
+      v[5] = dop;
+      v[6] = st.g0 * wgt;
+      v[7] = st.g1 * wgt;
+      v[8] = st.g2 * wgt;
+      const float tot = reduce9(v);
+      if (comp >= 0) atomicAdd(&g2d[(size_t)__float_as_uint(bx.y) * 9 + comp], tot);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  leave_queue(queue + kQueueWords, gridDim.x * kWaves, lane);
+}
+
+// Local front-to-back compositing of range offsets [c0, c1) over the pixel's composited
+// entries (offset < last, alpha >= 1/255): the chunk's own colour L and transmittance P.
+__device__ void bwd_local(const float* splat, const uint32_t* vals, uint32_t s, int c0, int c1, uint32_t n_gauss,
+                          const Item& it, WaveLds& L, int lane, int last, float& P, float& L0, float& L1,
+                          float& L2) {
+  P = 1.f;
+  L0 = L1 = L2 = 0.f;
+  const float px = it.x + 0.5f, py = it.y + 0.5f;
+  walk_front(splat, vals, s + (uint32_t)c0, s + (uint32_t)c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
+    const int base = (int)(b0 - s);
+    for (int i = 0; i < nhit; i += kIlp) {
+      float4 r1[kIlp];
+      float2 bx[kIlp];
+      float alpha[kIlp];
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) {
+        const int j = min(i + k, nhit - 1);
+        r1[k] = L.r1[j];
+        bx[k] = L.bx[j];
+        alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kIlp; ++k) {
+        const bool take = base + __float_as_int(bx[k].y) < last && alpha[k] >= kAlphaMin;
+        const float wgt = take ? alpha[k] * P : 0.f;
+        L0 = fmaf(r1[k].z, wgt, L0);
+        L1 = fmaf(r1[k].w, wgt, L1);
+        L2 = fmaf(bx[k].x, wgt, L2);
+        P = take ? P * (1.f - alpha[k]) : P;
+      }
+    }
+    return false;
+  });
+}
+
+__device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const float* bgc, const float* T_final,
+                                              const int32_t* n_contrib, const float* dimage) {
+  BwdState st{1.f, bgc[0], bgc[1], bgc[2], 0.f, 0.f, 0.f, 0};
+  if (it.inside) {
+    const long long HW = (long long)it.W * it.H;
+    const long long p = (long long)it.y * it.W + it.x;
+    const float* di = dimage + 3 * it.pix_begin;
+    st.T = T_final[it.pix];
+    st.last = min(n_contrib[it.pix], (int32_t)n);
+    st.g0 = di[p];
+    st.g1 = di[HW + p];
+    st.g2 = di[2 * HW + p];
+  }
+  return st;
+}
+
+// A long tile's quadrant, by the whole workgroup in rounds of four chunks from the back.
+__device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t n_gauss, const Item& it,
+                         WaveLds& L, RoundLds& R, int w, int lane, int comp, BwdState st, float* g2d) {
+  const int top = it.live ? wave_max(st.last) : 0;  // the same in every wave
+  for (int hi = top; hi > 0; hi -= kWaves * kChunk) {
+    const int c1 = max(0, hi - w * kChunk), c0 = max(0, c1 - kChunk);
+    float P, L0, L1, L2;
+    bwd_local(splat, vals, s, c0, c1, n_gauss, it, L, lane, st.last, P, L0, L1, L2);
+    R.v[w][0][lane] = P;
+    R.v[w][1][lane] = L0;
+    R.v[w][2][lane] = L1;
+    R.v[w][3][lane] = L2;
+    __syncthreads();
+    // state behind this wave's chunk, from the chunks behind it in the round
+    BwdState cs = st;
+    for (int j = 0; j < w; ++j) {
+      const float Pj = R.v[j][0][lane];
+      cs.T = cs.T / Pj;
+      cs.B0 = fmaf(Pj, cs.B0, R.v[j][1][lane]);
+      cs.B1 = fmaf(Pj, cs.B1, R.v[j][2][lane]);
+      cs.B2 = fmaf(Pj, cs.B2, R.v[j][3][lane]);
+    }
+    bwd_walk(splat, vals, s, c0, c1, n_gauss, it, L, lane, comp, cs, g2d);
+    // state in front of the round (identical in every wave)
+    for (int j = 0; j < kWaves; ++j) {
+      const float Pj = R.v[j][0][lane];
+      st.T = st.T / Pj;
+      st.B0 = fmaf(Pj, st.B0, R.v[j][1][lane]);
+      st.B1 = fmaf(Pj, st.B1, R.v[j][2][lane]);
+      st.B2 = fmaf(Pj, st.B2, R.v[j][3][lane]);
+    }
+    __syncthreads();  // R is rewritten by the next round
+  }
+}
+
+__global__ void __launch_bounds__(256) composite_bwd_kernel(
+    const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
+    int n_views, int n_tiles, const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
+    float* g2d, uint32_t capacity, uint32_t n_gauss) {
+  __shared__ WaveLds lds[kWaves];
+  __shared__ RoundLds round;
+  __shared__ uint32_t s_item;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  WaveLds& L = lds[w];
+  const int comp = reduce9_comp();
+  const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
+  const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
+  uint32_t* q = queue + kQueueWords;
+  __builtin_amdgcn_s_setprio(2);
+  for (uint32_t li = next_long_item(q, &s_item); li < 4u * n_long; li = next_long_item(q, &s_item)) {
+    const int tile = (int)min(order[li >> 2], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(li & 3u), lane);
+    const uint32_t e = min(ranges[2 * tile + 1], capacity);
+    const uint32_t s = min(ranges[2 * tile], e);
+    bwd_long(splat, vals, s, n_gauss, it, L, round, w, lane, comp,
+             bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d);
+  }
+  __builtin_amdgcn_s_setprio(0);
+  const uint32_t n_items = 4u * ((uint32_t)n_tiles - n_long);
+  for (uint32_t item = next_item(q, lane); item < n_items; item = next_item(q, lane)) {
+    const int tile = (int)min(order[n_long + (item >> 2)], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
+    const uint32_t e = min(ranges[2 * tile + 1], capacity);
+    const uint32_t s = min(ranges[2 * tile], e);
+    BwdState st = bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage);
+    const int top = it.live ? wave_max(st.last) : 0;
+    bwd_walk(splat, vals, s, 0, top, n_gauss, it, L, lane, comp, st, g2d);
+  }
+  leave_queue(q, gridDim.x * kWaves, lane);
 }
 
 __global__ void background_kernel(const glam_view_info* views, int n_views, long long n_pix, const float* bg,
@@ -474,9 +735,9 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
     return launch_background(v, bg, image, T_final, n_contrib, n_eval, s);
   }
   hipLaunchKernelGGL(render_fwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBlocksPerCU)),
-                     dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.queue, v.dev, v.n,
-                     (int)v.n_tiles, bg, image, T_final, n_contrib, n_eval, (uint32_t)bins.capacity,
-                     (uint32_t)v.n_gauss);
+                     dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
+                     bins.queue, v.dev, v.n, (int)v.n_tiles, bg, image, T_final, n_contrib, n_eval,
+                     (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -487,9 +748,9 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
   if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g2d, n);
   if (v.n_tiles > 0 && v.n_gauss > 0)
     hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBlocksPerCU)),
-                       dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.queue, v.dev,
-                       v.n, (int)v.n_tiles, bg, T_final, n_contrib, dimage, g2d, (uint32_t)bins.capacity,
-                       (uint32_t)v.n_gauss);
+                       dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
+                       bins.queue, v.dev, v.n, (int)v.n_tiles, bg, T_final, n_contrib, dimage, g2d,
+                       (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
