@@ -43,7 +43,8 @@ namespace {
 
 constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
-constexpr int kBlocksPerCU = 8;  // persistent workgroups per CU
+constexpr int kFwdBlocksPerCU = 5;  // persistent workgroups per CU (register-limited occupancy)
+constexpr int kBwdBlocksPerCU = 6;
 constexpr int kChunk = 256;      // entries per wave and round of a long tile
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
@@ -379,7 +380,7 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
   if (w == 0) fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdBlocksPerCU)))
 render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
                   uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, const float* bg,
@@ -648,7 +649,7 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
   }
 }
 
-__global__ void __launch_bounds__(256) composite_bwd_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBlocksPerCU))) composite_bwd_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
     int n_views, int n_tiles, const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
@@ -734,7 +735,7 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
     // nothing to composite: background everywhere
     return launch_background(v, bg, image, T_final, n_contrib, n_eval, s);
   }
-  hipLaunchKernelGGL(render_fwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBlocksPerCU)),
+  hipLaunchKernelGGL(render_fwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kFwdBlocksPerCU)),
                      dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
                      bins.queue, v.dev, v.n, (int)v.n_tiles, bg, image, T_final, n_contrib, n_eval,
                      (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
@@ -747,7 +748,7 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
   const long long n = 9 * v.n_gauss;
   if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g2d, n);
   if (v.n_tiles > 0 && v.n_gauss > 0)
-    hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBlocksPerCU)),
+    hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBwdBlocksPerCU)),
                        dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
                        bins.queue, v.dev, v.n, (int)v.n_tiles, bg, T_final, n_contrib, dimage, g2d,
                        (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
