@@ -381,14 +381,18 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
       if (valid[i] && rank[i] == 0) s_cnt[i][w][dig[i]] = (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit (thread t = digit t): exclusive prefix over (item round, wave)
+    // per digit (thread t = digit t): exclusive prefix over (item round, wave); the 32
+    // counts are read before any is rewritten
+    constexpr int kSlots = kSortItems * (kSortThreads / 64);
+    uint32_t c[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) c[k] = s_cnt[k / (kSortThreads / 64)][k % (kSortThreads / 64)][t];
     uint32_t run = 0;
-    for (int i = 0; i < kSortItems; ++i)
-      for (int ww = 0; ww < kSortThreads / 64; ++ww) {
-        const uint32_t c = s_cnt[i][ww][t];
-        s_cnt[i][ww][t] = run;
-        run += c;
-      }
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      s_cnt[k / (kSortThreads / 64)][k % (kSortThreads / 64)][t] = run;
+      run += c[k];
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
