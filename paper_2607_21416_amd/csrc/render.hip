@@ -103,6 +103,32 @@ __device__ __forceinline__ bool box_meets(float bxf, float byf, const Item& it) 
   return x0 <= it.qx1 && x1 >= it.qx0 && y0 <= it.qy1 && y1 >= it.qy0;
 }
 
+// Whether the Gaussian's alpha can reach 1/255 at any pixel centre of the quadrant: the
+// minimum over the centres' rectangle of q = A dx^2 + 2 B dx dy + C dy^2 (the power is
+// -q/2) against 2 ln(255 opacity).  The minimum of this convex form over the rectangle
+// is 0 when the centre is inside, else it lies on an edge, where it is the clamped
+// one-dimensional minimum.  The test runs per batch entry (one entry per lane) and keeps
+// a margin, so it only drops entries whose alpha is below the threshold at every pixel
+// of the quadrant: the box test passes whole footprint boxes, the ellipse inside
+// can miss the quadrant.
+__device__ __forceinline__ float edge_min_q(float a, float b, float c, float dfix, float lo, float hi) {
+  // q along an edge where the first offset is fixed at dfix and the second runs over [lo, hi]
+  const float d = fminf(fmaxf(-b * dfix * __builtin_amdgcn_rcpf(c), lo), hi);
+  return fmaf(a * dfix, dfix, d * fmaf(c, d, 2.f * b * dfix));
+}
+
+__device__ __forceinline__ bool ellipse_meets(const float4& r0, const float4& r1, const Item& it) {
+  const float u = r0.x, v = r0.y, A = r0.z, B = r0.w, C = r1.x;
+  // offsets of the rectangle's edges from the centre
+  const float lx = it.qx0 + 0.5f - u, hx = it.qx1 + 0.5f - u;
+  const float ly = it.qy0 + 0.5f - v, hy = it.qy1 + 0.5f - v;
+  const bool inside = lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f;
+  const float q = fminf(fminf(edge_min_q(A, B, C, lx, ly, hy), edge_min_q(A, B, C, hx, ly, hy)),
+                        fminf(edge_min_q(C, B, A, ly, lx, hx), edge_min_q(C, B, A, hy, lx, hx)));
+  const float lim = 2.f * __logf(255.f * r1.y) + 0.01f;
+  return inside || q <= lim;
+}
+
 // Work queue.  Device-scope atomics are served at the memory side, so one counter would
 // serialise every grab; the longest-first tile list (after the long tiles) is dealt
 // round-robin over kQueues counters (one 128-byte line each), and workgroup b pulls
@@ -190,7 +216,7 @@ __device__ __forceinline__ void walk_front(const float* splat, const uint32_t* v
     const Rec cur = nxt;
     const bool valid = b0 + lane < c1;
     if (b0 + 64 + lane < c1) nxt = load_rec(splat, min(vals[b0 + 64 + lane], n_gauss - 1));
-    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
+    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
     const uint64_t hm = __ballot(hit);
     if (hit) {
       const int pos = __popcll(hm & lanemask_lt(lane));
@@ -511,7 +537,7 @@ __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, i
         nxt = load_rec(splat, ngid);
       }
     }
-    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it);
+    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
     const uint64_t hm = __ballot(hit);
     if (hit) {
       const int pos = __popcll(hm & lanemask_lt(lane));
