@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched-vs-plain comparison")
     ap.add_argument("--stage-iters", type=int, default=10)
+    ap.add_argument("--config5", action="store_true",
+                    help="also run config 5 (2 km path, 64 partitions x 8 views, mixed resolutions) once")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -267,6 +269,26 @@ def main():
                                    "plain_iterations_per_s": round(bp.vt.n * 1000.0 / tp, 1)}
         log(f"bench: batched {tb:.2f} ms, plain {tp:.2f} ms, speedup {tp / tb:.2f}")
         del bg, bp, plains
+
+    if args.config5:
+        log("bench: config 5 (2 km path, 64 partitions x 8 views)")
+        torch.cuda.reset_peak_memory_stats()
+        s5 = synth.config("C5")
+        p5 = Pipeline(s5, device=dev)
+        need5 = p5.fit_capacity()
+        p5.status.zero_()
+        for _ in range(2):
+            p5.step()
+        t5 = timed(torch, p5.step, 3, stream)
+        p5.check_status()
+        out["config5"] = {"workload": "config 5: 2 km path, 64 partitions (log-uniform 30k-300k Gaussians), "
+                                      "8 views each at 1226x370 / 1280x384 / 1280x960",
+                          "views": p5.vt.n, "view_gaussians": int(p5.vt.n_gauss), "pixels": int(p5.vt.n_pix),
+                          "pairs": int(need5), "step_ms": round(t5, 2),
+                          "view_iterations_per_s": round(p5.vt.n * 1000.0 / t5, 1), "launch": "eager",
+                          "peak_hbm_gib": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2)}
+        log(f"bench: config 5 step {t5:.2f} ms")
+        del p5, s5
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline (the 4 views of config 3, three times over)")
