@@ -237,8 +237,11 @@ glam_status glam_loss(const glam_views* views, const float* image, const float* 
 /* --- backward ------------------------------------------------------------------- */
 
 /* Gradients.  Intermediate buffers are required (the library allocates nothing):
-   g2d [n_gauss][9] = d(u, v, A, B, C, opacity, r, g, b) of each projected Gaussian
-   (nine consecutive floats per view-Gaussian, so one wave adds all nine at once),
+   g2d [n_gauss][9], nine consecutive floats per view-Gaussian (so one wave adds all nine
+   at once): the pixel sums of p dx, p dy, p dx^2, p dx dy, p dy^2 with p = dL/dpower
+   and (dx, dy) = (u, v) - pixel centre, then d(opacity, r, g, b).  The gradients of the
+   centre and conic follow as du = -(A m0 + B m1), dv = -(B m0 + C m1), dA = -m2/2,
+   dB = -m3, dC = -m4/2 (power = -(A dx^2 + C dy^2)/2 - B dx dy);
    dgauss: d(mean, scale, quat, opacity, rgb) per view-Gaussian (anchor mode) or of
    the plain parameters (plain mode: d(mean, log-scale, raw quat, logit, rgb), n = G).
    Anchor mode outputs dfeat [A][F], doffs [3][A*K], dlog_scale [A], dmlp [M][P]. */

@@ -162,13 +162,18 @@ __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, cons
   }
 }
 
-// Adjoint of the projection for one view-Gaussian; g2d[n][9] holds
-// d(u, v, A, B, C, opacity, r, g, b).  Writes d(mean, scale, quat, opacity, rgb) of the
-// activated parameters into d*.
+// Adjoint of the projection for one view-Gaussian.  g2d[n][9] holds, summed over the
+// pixels, the moments m = (p dx, p dy, p dx^2, p dx dy, p dy^2) of p = dL/dpower with
+// (dx, dy) = (u, v) - pixel centre, then d(opacity, r, g, b).  Since
+// power = -(A dx^2 + C dy^2)/2 - B dx dy, the centre and conic gradients are
+// du = -(A m0 + B m1), dv = -(B m0 + C m1), dA = -m2/2, dB = -m3, dC = -m4/2.
+// Writes d(mean, scale, quat) of the activated parameters into d*.
 __device__ __forceinline__ void project_adjoint(const glam_camera& cam, const GaussIn& g,
                                                 const ProjState& p, const float* gi,
                                                 float dmu[3], float ds[3], float dq[4]) {
-  const float du = gi[0], dv = gi[1], dA = gi[2], dB = gi[3], dC = gi[4];
+  const float cA = p.conic[0], cB = p.conic[1], cC = p.conic[2];
+  const float du = -(cA * gi[0] + cB * gi[1]), dv = -(cB * gi[0] + cC * gi[1]);
+  const float dA = -0.5f * gi[2], dB = -gi[3], dC = -0.5f * gi[4];
   const float a = p.a, b = p.b, c = p.c, id2 = p.inv_det * p.inv_det;
   const float da = (dA * (-c * c) + dB * (b * c) + dC * (-b * b)) * id2;
   const float db = (dA * (2.f * b * c) - dB * (a * c + b * b) + dC * (2.f * a * b)) * id2;

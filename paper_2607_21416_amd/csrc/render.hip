@@ -28,7 +28,9 @@
 // The backward walks the same ranges from the wave's last contributor down,
 // recovering T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance and
 // carrying the colour behind, B <- B + alpha_i (c_i - B).  Per Gaussian, the nine
-// gradient terms of the wave's pixels are summed with a reduce-scatter (two gfx950
+// accumulated terms (the opacity and colour gradients, and five moments of dL/dpower
+// from which the projection adjoint forms the centre and conic gradients) of the
+// wave's pixels are summed with a reduce-scatter (two gfx950
 // lane-swap stages, then DPP within 16-lane rows) and nine lanes add the totals to HBM
 // with one atomic instruction.  For long tiles the workgroup takes rounds of four
 // chunks from the back: each wave composites its chunk locally, and the state behind
@@ -573,11 +575,12 @@ __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, i
       const float dop = free_alpha ? dal * ep : 0.f;
       const float dp = free_alpha ? dal * alpha : 0.f;
       float v[9];
-      v[0] = -dp * (r0.z * dx + r0.w * dy);
-      v[1] = -dp * (r0.w * dx + r1.x * dy);
-      v[2] = -0.5f * dp * dx * dx;
-      v[3] = -dp * dx * dy;
-      v[4] = -0.5f * dp * dy * dy;
+      // moments of dL/dpower; the projection adjoint applies the conic
+      v[0] = dp * dx;
+      v[1] = dp * dy;
+      v[2] = v[0] * dx;
+      v[3] = v[0] * dy;
+      v[4] = v[1] * dy;
       v[5] = dop;
       v[6] = st.g0 * wgt;
       v[7] = st.g1 * wgt;

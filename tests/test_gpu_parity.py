@@ -59,6 +59,22 @@ def case(request):
     return request.param, scene, pipe, host(pipe)
 
 
+def g2d_gradients(g2d, conic):
+    """The 2-D gradients d(u, v, A, B, C, opacity, r, g, b) [9][n] from the kernel's
+    accumulators: moments m of dL/dpower and the conic (A, B, C), as the projection
+    adjoint forms them: du = -(A m0 + B m1), dv = -(B m0 + C m1), dA = -m2/2, dB = -m3,
+    dC = -m4/2."""
+    m = g2d.T.astype(np.float64)
+    A, B, C = conic.astype(np.float64)
+    out = m.copy()
+    out[0] = -(A * m[0] + B * m[1])
+    out[1] = -(B * m[0] + C * m[1])
+    out[2] = -0.5 * m[2]
+    out[3] = -m[3]
+    out[4] = -0.5 * m[4]
+    return out
+
+
 def oracle_gauss(scene, v):
     return oracle.view_gaussians(scene, v)
 
@@ -190,7 +206,7 @@ def test_backward_stagewise(case):
         vals = h["vals"].astype(np.int64) - sl["g0"]
         ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
         g2d = oracle.render_bwd(pr, gs, vals, ranges, scene["cams"][v], dims[v])
-        got = hb["g2d"][sl["g0"]:sl["g1"]].T
+        got = g2d_gradients(hb["g2d"][sl["g0"]:sl["g1"]], h["conic"][:, sl["g0"]:sl["g1"]])
         for k, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
             grad_close(got[k], g2d[k], name=f"{name} view {v} d{nm}")
         # projection adjoint fed the GPU's 2-D gradients and (anchor mode) decoded Gaussians
