@@ -314,21 +314,31 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
 constexpr int kBwdWaves = 4;
 constexpr int kBwdBlocksPerCU = 2;  // workgroups resident per CU (registers: two waves per SIMD)
 
+constexpr int align4(int x) { return (x + 3) & ~3; }
+
+// LDS layout of one MLP's adjoint.  Operands of the MFMAs are read four K-steps at a
+// time (one 16-byte LDS read): the K order of each product is chosen so that a lane's
+// four consecutive K-steps are four consecutive words, with transposed copies where a
+// product runs over the other index (W2^T, W1^T; Y and H are kept output-major).  Row
+// strides are multiples of four words whose 16 rows fall in distinct banks.
 template <int F, int K, int ML>
 struct MCfg {
   static constexpr int NIN = F + 4;
   static constexpr int OUT = ML == 0 ? K : (ML == 1 ? 3 * K : 7 * K);
-  static constexpr int OT = (OUT + 15) / 16;   // 16-row tiles of the outputs
-  static constexpr int KS1 = NIN / 4;          // K-steps of layer 1
-  static constexpr int KS2 = (OUT + 3) / 4;    // K-steps over the outputs
+  static constexpr int OUTP = (OUT + 15) / 16 * 16;  // outputs padded to 16-row tiles
+  static constexpr int OT = OUTP / 16;
+  static constexpr int KF = F / 4;             // feature columns per lane group in layer 1
   static constexpr int NC1 = (NIN + 15) / 16;  // 16-column tiles of W1
-  static constexpr int W1S = NIN + 1, W2S = kHid + 1;  // padded LDS rows
-  static constexpr int LW1 = 0, LB1 = kHid * W1S, LW2 = LB1 + kHid, LB2 = LW2 + OUT * W2S;
-  static constexpr int PW = (LB2 + OUT + 3) & ~3;
+  static constexpr int W1S = NIN, W2S = kHid + 4, W2TS = OUTP + 4, W1TS = kHid + 4;
+  static constexpr int LW1 = 0, LB1 = kHid * W1S, LW2 = align4(LB1 + kHid), LB2 = LW2 + OUT * W2S;
+  static constexpr int LW2T = align4(LB2 + OUT), LW1T = LW2T + kHid * W2TS;
+  static constexpr int PW = align4(LW1T + F * W1TS);
   static constexpr int PM = kHid * NIN + kHid + OUT * kHid + OUT;  // packed parameters
-  static constexpr int ZS = NIN + 1, YS = OUT + 1, HS = kHid + 1;
-  static constexpr int WAVE_WORDS = 16 * (ZS + YS + HS) + 16;
+  static constexpr int ZS = NIN, YTS = 20, HTS = 20;
+  // per wave: Z [16][NIN] anchor-major; Y^T [OUTP][20] and H^T [32][20] output-major
+  static constexpr int WAVE_WORDS = align4(16 * ZS + OUTP * YTS + kHid * HTS + 16);
   static constexpr int SMEM = PW + kBwdWaves * WAVE_WORDS;
+  static_assert(NIN % 4 == 0 && F % 16 == 0, "layout");
 };
 
 template <int F, int K>
@@ -337,8 +347,14 @@ constexpr int bwd_smem_words() {
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-// In the adjoint, gridDim.y = 4 selects the MLP: 0 opacity, 1 colour, 2 and 3 the two
-// halves of the covariance MLP.
+__device__ __forceinline__ float4 lds4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+__device__ __forceinline__ f4 mfma4(const float4& a, const float4& b, f4 acc) {
+  acc = mfma(a.x, b.x, acc);
+  acc = mfma(a.y, b.y, acc);
+  acc = mfma(a.z, b.z, acc);
+  return mfma(a.w, b.w, acc);
+}
 
 template <int F, int K, int ML>
 __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__ mlp,
@@ -359,23 +375,37 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
   float* s_p = smem;
   float* s_z = smem + C::PW + w * C::WAVE_WORDS;
-  float* s_y = s_z + 16 * C::ZS;
-  float* s_h = s_y + 16 * C::YS;
-  float* s_ds = s_h + 16 * C::HS;
-  {  // this MLP's weights, padded rows
+  float* s_yt = s_z + 16 * C::ZS;
+  float* s_ht = s_yt + C::OUTP * C::YTS;
+  float* s_ds = s_ht + kHid * C::HTS;
+  {  // this MLP's weights: W1, b1, W2 (rows padded to 36), b2, and the transposes W2^T, W1^T
     const float* pm = mlp + (size_t)lead.cam.partition * O.total + O.w1[ML];
     for (int i = t; i < C::PM; i += 64 * kBwdWaves) {
-      int dst;
-      if (i < kHid * C::NIN) dst = C::LW1 + (i / C::NIN) * C::W1S + i % C::NIN;
-      else if (i < kHid * C::NIN + kHid) dst = C::LB1 + (i - kHid * C::NIN);
-      else if (i < kHid * C::NIN + kHid + OUT * kHid) {
-        const int j = i - kHid * C::NIN - kHid;
-        dst = C::LW2 + (j / kHid) * C::W2S + j % kHid;
-      } else dst = C::LB2 + (i - kHid * C::NIN - kHid - OUT * kHid);
-      s_p[dst] = pm[i];
+      const float v = pm[i];
+      if (i < kHid * C::NIN) {
+        const int h = i / C::NIN, c = i % C::NIN;
+        s_p[C::LW1 + h * C::W1S + c] = v;
+        if (c < F) s_p[C::LW1T + c * C::W1TS + h] = v;
+      } else if (i < kHid * C::NIN + kHid) {
+        s_p[C::LB1 + (i - kHid * C::NIN)] = v;
+      } else if (i < kHid * C::NIN + kHid + OUT * kHid) {
+        const int j = i - kHid * C::NIN - kHid, o = j / kHid, h = j % kHid;
+        s_p[C::LW2 + o * C::W2S + h] = v;
+        s_p[C::LW2T + h * C::W2TS + o] = v;
+      } else {
+        s_p[C::LB2 + (i - kHid * C::NIN - kHid - OUT * kHid)] = v;
+      }
     }
+    for (int i = t; i < kHid * (C::OUTP - OUT); i += 64 * kBwdWaves)
+      s_p[C::LW2T + (i / (C::OUTP - OUT)) * C::W2TS + OUT + i % (C::OUTP - OUT)] = 0.f;
+    // padded output rows of this wave's Y^T stay zero
+    for (int i = l; i < (C::OUTP - OUT) * C::YTS; i += 64) s_yt[OUT * C::YTS + i] = 0.f;
   }
   __syncthreads();
+  const float* W1 = s_p + C::LW1;
+  const float* W2 = s_p + C::LW2;
+  const float* W2T = s_p + C::LW2T;
+  const float* W1T = s_p + C::LW1T;
   f4 dW2[2 * C::OT];
   f4 dW1[2 * C::NC1];
   float db2[(OUT + 63) / 64];
@@ -422,14 +452,15 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
       }
     }
     wave_sync();
-    // the features' share of layer 1 (all K-steps but the last, which holds d and delta)
+    // the features' share of layer 1 (lane group g takes feature columns [g KF, g KF + KF))
     f4 PF[2], dPsum[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-      const float* W1 = s_p + C::LW1 + (mt * 16 + li) * C::W1S;
+      const float* wr = W1 + (mt * 16 + li) * C::W1S + C::KF * lg;
+      const float* zr = s_z + li * C::ZS + C::KF * lg;
       f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < C::KS1 - 1; ++ks) acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], acc);
+      for (int q4 = 0; q4 < C::KF / 4; ++q4) acc = mfma4(lds4(wr + 4 * q4), lds4(zr + 4 * q4), acc);
       PF[mt] = acc;
       dPsum[mt] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -475,40 +506,36 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         s_z[l * C::ZS + F + 3] = delta;
       }
       wave_sync();
-      // layer 1, this MLP's 32 hidden rows: H^T tiles in the MFMA output layout
+      // layer 1 completed with the d, delta columns (lane group g: column F + g)
       f4 H[2];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        const float* W1 = s_p + C::LW1 + (mt * 16 + li) * C::W1S;
-        constexpr int ks = C::KS1 - 1;
-        f4 acc = mfma(W1[ks * 4 + lg], s_z[li * C::ZS + ks * 4 + lg], PF[mt]);
+        f4 acc = mfma(W1[(mt * 16 + li) * C::W1S + F + lg], s_z[li * C::ZS + F + lg], PF[mt]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = fmaxf(acc[r] + s_p[C::LB1 + mt * 16 + 4 * lg + r], 0.f);
         H[mt] = acc;
       }
-      // layer 2 into LDS (Y^T tiles from the H^T registers, permuted K)
+      // layer 2 into Y^T (K-step (t2, r) of lane group g: hidden row 16 t2 + 4 g + r)
 #pragma unroll
       for (int ot = 0; ot < C::OT; ++ot) {
         const int o = ot * 16 + li;
         f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t2 = 0; t2 < 2; ++t2)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float a = o < OUT ? s_p[C::LW2 + o * C::W2S + t2 * 16 + 4 * lg + r] : 0.f;
-            acc = mfma(a, H[t2][r], acc);
-          }
+        for (int t2 = 0; t2 < 2; ++t2) {
+          const float4 a = o < OUT ? lds4(W2 + o * C::W2S + t2 * 16 + 4 * lg) : make_float4(0.f, 0.f, 0.f, 0.f);
+          acc = mfma4(a, make_float4(H[t2][0], H[t2][1], H[t2][2], H[t2][3]), acc);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int orow = ot * 16 + 4 * lg + r;
-          if (orow < OUT) s_y[li * C::YS + orow] = acc[r] + s_p[C::LB2 + orow];
+          if (orow < OUT) s_yt[orow * C::YTS + li] = acc[r] + s_p[C::LB2 + orow];
         }
       }
-      // H to LDS, anchor-major, for dW2
+      // H^T for dW2
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = H[mt][r];
+        for (int r = 0; r < 4; ++r) s_ht[(mt * 16 + 4 * lg + r) * C::HTS + li] = H[mt][r];
       wave_sync();
       // activation adjoints, one lane per Gaussian; dY overwrites Y in place
 #pragma unroll
@@ -516,24 +543,25 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         const int gi = l + 64 * q;
         if (gi >= 16 * K) break;
         const int ai = gi / K, j = gi % K, a = a0 + ai;
-        float* y = s_y + ai * C::YS;
+        float* y = s_yt + ai;  // output o of this anchor at y[o * YTS]
+        constexpr int S = C::YTS;
         if (a >= A) {
-          if (ML == 0) y[j] = 0.f;
+          if (ML == 0) y[j * S] = 0.f;
           if (ML == 1)
-            for (int c = 0; c < 3; ++c) y[3 * j + c] = 0.f;
+            for (int c = 0; c < 3; ++c) y[(3 * j + c) * S] = 0.f;
           if (ML == 2)
-            for (int k = 0; k < 7; ++k) y[7 * j + k] = 0.f;
+            for (int k = 0; k < 7; ++k) y[(7 * j + k) * S] = 0.f;
           continue;
         }
         if (ML == 0) {
-          const float yo = y[j];
+          const float yo = y[j * S];
           const float dop = pg[q][0];
           if (sigmoid_op) {
             const float al = sigmoid(yo);
-            y[j] = dop * al * (1.f - al);
+            y[j * S] = dop * al * (1.f - al);
           } else {
             const float al = tanhf(yo);
-            y[j] = al > 0.f ? dop * (1.f - al * al) : 0.f;
+            y[j * S] = al > 0.f ? dop * (1.f - al * al) : 0.f;
           }
           // the mean is x_a + e^{s_a} o: offsets and log-scale
           float ds = 0.f;
@@ -545,38 +573,40 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
           atomicAdd(&s_ds[ai], ds);
         } else if (ML == 1) {
           for (int c = 0; c < 3; ++c) {
-            const float col = sigmoid(y[3 * j + c]);
-            y[3 * j + c] = pg[q][c] * col * (1.f - col);
+            const float col = sigmoid(y[(3 * j + c) * S]);
+            y[(3 * j + c) * S] = pg[q][c] * col * (1.f - col);
           }
         } else {
-          float* yc = y + 7 * j;
+          float yc[7];
+          for (int k = 0; k < 7; ++k) yc[k] = y[(7 * j + k) * S];
           float ds = 0.f;
           for (int k = 0; k < 3; ++k) {
             const float sg = sigmoid(yc[k]);
             const float dsc = pg[q][k];
-            yc[k] = dsc * es[q] * sg * (1.f - sg);
+            y[(7 * j + k) * S] = dsc * es[q] * sg * (1.f - sg);
             ds = fmaf(dsc, es[q] * sg, ds);
           }
           const float nr = sqrtf(yc[3] * yc[3] + yc[4] * yc[4] + yc[5] * yc[5] + yc[6] * yc[6] + 1e-24f);
           const float inv = 1.f / nr;
           float qd = 0.f;
           for (int k = 0; k < 4; ++k) qd = fmaf(yc[3 + k] * inv, pg[q][3 + k], qd);
-          for (int k = 0; k < 4; ++k) yc[3 + k] = (pg[q][3 + k] - yc[3 + k] * inv * qd) * inv;
+          for (int k = 0; k < 4; ++k) y[(7 * j + 3 + k) * S] = (pg[q][3 + k] - yc[3 + k] * inv * qd) * inv;
           atomicAdd(&s_ds[ai], ds);
         }
       }
       wave_sync();
-      // dH^T = W2^T dY^T, masked by the ReLU (H > 0 exactly where the pre-activation is)
+      // dH^T = W2^T dY^T (K-step (m, r) of lane group g: output 16 m + 4 g + r), masked
+      // by the ReLU (H > 0 exactly where the pre-activation is)
       f4 dP[2];
 #pragma unroll
       for (int ht = 0; ht < 2; ++ht) {
         f4 acc = {0.f, 0.f, 0.f, 0.f};
+        const float* wr = W2T + (ht * 16 + li) * C::W2TS + 4 * lg;
 #pragma unroll
-        for (int ks = 0; ks < C::KS2; ++ks) {
-          const int o = ks * 4 + lg;
-          const float a = o < OUT ? s_p[C::LW2 + o * C::W2S + ht * 16 + li] : 0.f;
-          const float b = o < OUT ? s_y[li * C::YS + o] : 0.f;
-          acc = mfma(a, b, acc);
+        for (int mo = 0; mo < C::OT; ++mo) {
+          const float* yr = s_yt + (16 * mo + 4 * lg) * C::YTS + li;
+          acc = mfma4(lds4(wr + 16 * mo),
+                      make_float4(yr[0], yr[C::YTS], yr[2 * C::YTS], yr[3 * C::YTS]), acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = H[ht][r] > 0.f ? acc[r] : 0.f;
@@ -585,48 +615,43 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
       // the features' gradients and weight gradients are linear in dPre: sum it over views
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) dPsum[mt] += dP[mt];
-      // dW2 += dY^T H over the chunk's 16 anchors, db2 += sum of dY
+      // dW2 += dY^T H over the chunk's 16 anchors (K-step k of lane group g: anchor 4 g + k)
 #pragma unroll
       for (int ot = 0; ot < C::OT; ++ot) {
-        const int o = ot * 16 + li;
+        const float4 a = lds4(s_yt + (ot * 16 + li) * C::YTS + 4 * lg);
 #pragma unroll
-        for (int ht = 0; ht < 2; ++ht) {
-          f4 acc = dW2[ot * 2 + ht];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int an_ = ks * 4 + lg;
-            const float a = o < OUT ? s_y[an_ * C::YS + o] : 0.f;
-            acc = mfma(a, s_h[an_ * C::HS + ht * 16 + li], acc);
-          }
-          dW2[ot * 2 + ht] = acc;
-        }
+        for (int ht = 0; ht < 2; ++ht)
+          dW2[ot * 2 + ht] = mfma4(a, lds4(s_ht + (ht * 16 + li) * C::HTS + 4 * lg), dW2[ot * 2 + ht]);
       }
 #pragma unroll
       for (int i = 0; i < (OUT + 63) / 64; ++i) {
         const int o = l + 64 * i;
-        if (o < OUT)
-          for (int an_ = 0; an_ < 16; ++an_) db2[i] += s_y[an_ * C::YS + o];
+        if (o < OUT) {
+          const float* yr = s_yt + o * C::YTS;
+          float acc = 0.f;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) {
+            const float4 y4 = lds4(yr + 4 * q4);
+            acc += (y4.x + y4.y) + (y4.z + y4.w);
+          }
+          db2[i] += acc;
+        }
       }
       wave_sync();
-      // dPre to LDS (reusing the H rows) for dW1 += dPre^T Z, db1 += sum of dPre
+      // dPre^T (reusing the H^T rows) for the d, delta columns of dW1, this view
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dP[mt][r];
+        for (int r = 0; r < 4; ++r) s_ht[(mt * 16 + 4 * lg + r) * C::HTS + li] = dP[mt][r];
       wave_sync();
-      // dW1 columns of d and delta (the last column tile), this view
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
         constexpr int ct = F / 16;
-        f4 acc = dW1[mt * C::NC1 + ct];
         const int col = ct * 16 + li;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int an_ = ks * 4 + lg;
-          const float b = col < C::NIN ? s_z[an_ * C::ZS + col] : 0.f;
-          acc = mfma(s_h[an_ * C::HS + mt * 16 + li], b, acc);
-        }
-        dW1[mt * C::NC1 + ct] = acc;
+        const float* zc = s_z + 4 * lg * C::ZS + col;
+        const float4 b = col < C::NIN ? make_float4(zc[0], zc[C::ZS], zc[2 * C::ZS], zc[3 * C::ZS])
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        dW1[mt * C::NC1 + ct] = mfma4(lds4(s_ht + (mt * 16 + li) * C::HTS + 4 * lg), b, dW1[mt * C::NC1 + ct]);
       }
       wave_sync();
     }
@@ -635,32 +660,33 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) s_h[li * C::HS + mt * 16 + 4 * lg + r] = dPsum[mt][r];
+      for (int r = 0; r < 4; ++r) s_ht[(mt * 16 + 4 * lg + r) * C::HTS + li] = dPsum[mt][r];
     wave_sync();
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < 2; ++mt) {
+      const float4 a = lds4(s_ht + (mt * 16 + li) * C::HTS + 4 * lg);
 #pragma unroll
       for (int ct = 0; ct < F / 16; ++ct) {
-        f4 acc = dW1[mt * C::NC1 + ct];
-        const int col = ct * 16 + li;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int an_ = ks * 4 + lg;
-          acc = mfma(s_h[an_ * C::HS + mt * 16 + li], s_z[an_ * C::ZS + col], acc);
-        }
-        dW1[mt * C::NC1 + ct] = acc;
+        const float* zc = s_z + 4 * lg * C::ZS + ct * 16 + li;
+        dW1[mt * C::NC1 + ct] =
+            mfma4(a, make_float4(zc[0], zc[C::ZS], zc[2 * C::ZS], zc[3 * C::ZS]), dW1[mt * C::NC1 + ct]);
       }
-    if (l < kHid)
-      for (int an_ = 0; an_ < 16; ++an_) db1 += s_h[an_ * C::HS + l];
+    }
+    if (l < kHid) {
+      const float* hr = s_ht + l * C::HTS;
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const float4 h4 = lds4(hr + 4 * q4);
+        db1 += (h4.x + h4.y) + (h4.z + h4.w);
+      }
+    }
     f4 dZ[F / 16];
 #pragma unroll
     for (int ft = 0; ft < F / 16; ++ft) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
+      const float* wr = W1T + (ft * 16 + li) * C::W1TS + 4 * lg;
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc = mfma(s_p[C::LW1 + (mt * 16 + 4 * lg + r) * C::W1S + ft * 16 + li], dPsum[mt][r], acc);
+      for (int mt = 0; mt < 2; ++mt) acc = mfma4(lds4(wr + 16 * mt), make_float4(dPsum[mt][0], dPsum[mt][1], dPsum[mt][2], dPsum[mt][3]), acc);
       dZ[ft] = acc;
     }
     // this MLP's share of the anchor gradients (all views summed)
@@ -720,7 +746,8 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
 }
 
 template <int F, int K>
-__global__ void __launch_bounds__(64 * kBwdWaves) decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
+__global__ void __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(kBwdBlocksPerCU)))
+decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
                                                                     const glam_view_info* views, int sigmoid_op,
                                                                     glam_gaussians dg, BwdGrid grid, float* doffs,
                                                                     float* dfeat_part, float* dls_part,
