@@ -236,14 +236,15 @@ class Pipeline:
             raise B.GlamError("device status", int(st[0]))
 
     def fit_capacity(self, slack: float = 1.25):
-        """Runs the forward up to the sort once and grows the pair buffers to the
-        required count times `slack` (one synchronising sizing pass)."""
+        """Runs the forward up to the sort once and sizes the pair buffers to the
+        required count times `slack` (one synchronising sizing pass; buffers more than
+        twice that size are shrunk, since the sort's grids scale with the capacity)."""
         self.decode()
         self.project()
         self.bin_sort()
         torch.cuda.synchronize(self.device)
         need = self.pair_count()
-        if need > self.capacity or self.capacity > 4 * max(need, 1024):
+        if need > self.capacity or self.capacity > 2 * slack * max(need, 1024):
             self.status.zero_()
             self._alloc_bins(max(1024, int(need * slack)))
         return need
