@@ -9,7 +9,7 @@
 //  4. radix passes     LSD, reduce-then-scan (no inter-block waiting): upsweep digit
 //                      histogram per block, per-digit scan across blocks, downsweep
 //                      scatter with a stable in-block rank from wave ballots
-//  5. ranges           [start, end) of every tile
+//  5. ranges           [start, end) of every tile (cleared by the plan kernel)
 //
 // Every kernel reads P and the key layout from the device-side plan, so the whole
 // sequence runs without a host round trip (and can be captured in a graph).  Passes
@@ -81,13 +81,18 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t
   __syncthreads();
   const long long base = (long long)blockIdx.x * kScanBlock;
   uint32_t sum = 0, mx = 0;
-  for (int i = 0; i < kScanItems; ++i) {
+  int32_t nt[kScanItems];
+  uint32_t db[kScanItems];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {  // all loads in flight first
     const long long g = base + (long long)i * kScanThreads + threadIdx.x;
-    if (g < n) {
-      const int32_t nt = ntiles[g];
-      sum += (uint32_t)nt;
-      if (nt > 0) mx = max(mx, __float_as_uint(depth[g]));
-    }
+    nt[i] = g < n ? ntiles[g] : 0;
+    db[i] = g < n ? __float_as_uint(depth[g]) : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    sum += (uint32_t)nt[i];
+    if (nt[i] > 0) mx = max(mx, db[i]);
   }
   atomicAdd(&s_sum, sum);
   atomicMax(&s_max, mx);
@@ -96,12 +101,16 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t
 }
 
 // One block of 1024 threads: exclusive scan of the block sums in place, and the plan.
+// Also clears the tile ranges and the longest-first counters for this call.
 __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const uint32_t* pmax, int nb,
                                                          long long capacity, long long n_tiles, int n_sort_blocks,
-                                                         Plan* plan, int32_t* status) {
+                                                         Plan* plan, int32_t* status, uint32_t* ranges,
+                                                         uint32_t* lpt) {
   __shared__ unsigned long long s_part[1024];
   __shared__ uint32_t s_max[1024];
   const int t = threadIdx.x;
+  for (long long i = t; i < 2 * n_tiles; i += 1024) ranges[i] = 0u;
+  if (t < 2 * kLptBuckets) lpt[t] = 0u;
   const int per = (nb + 1023) / 1024;
   const int lo = min(nb, t * per), hi = min(nb, lo + per);
   unsigned long long local = 0;
@@ -409,12 +418,6 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
   }
 }
 
-__global__ void ranges_clear_kernel(uint32_t* ranges, long long n, uint32_t* lpt) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) ranges[i] = 0u;
-  if (i < 2 * kLptBuckets) lpt[i] = 0u;
-}
-
 // Work order of the compositing queue: tiles by power-of-two class of their range
 // length, longest first (empty tiles last).  Counting sort over 32 classes; the order
 // inside a class is arbitrary (it only schedules work).
@@ -496,8 +499,10 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
   const long long n = v.n_gauss;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.depth,
                      n, psum, pmax);
+  uint32_t* lpt = reinterpret_cast<uint32_t*>(w + L.lpt);
   hipLaunchKernelGGL(scan_plan_kernel, dim3(1), dim3(1024), 0, s, psum, pmax, L.n_scan_blocks,
-                     (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status);
+                     (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status,
+                     bins.ranges, lpt);
   hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
                      n, v.dev, v.n, psum, plan, bins.keys, bins.vals, keys_alt, vals_alt);
   // host bound on the passes: tile bits are known, depth keys take at most 31 bits
@@ -510,9 +515,6 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
     hipLaunchKernelGGL(radix_downsweep_kernel, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
                        L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
   }
-  const long long nr = 2 * v.n_tiles;
-  uint32_t* lpt = reinterpret_cast<uint32_t*>(w + L.lpt);
-  hipLaunchKernelGGL(ranges_clear_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, bins.ranges, nr, lpt);
   if (bins.capacity > 0)
     hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,
                        bins.keys, bins.ranges, (long long)v.n_tiles);
