@@ -25,6 +25,15 @@ def plain_ragged():
     return synth.plain_scene(1011, 2000, 70, 45)
 
 
+def plain_dense():
+    # 20k faint Gaussians on 64x48: every tile's range holds 1000-4000 entries (the
+    # workgroup path for long tiles) and about 40% of the pixels stop between entries
+    # 1400 and 2400, i.e. inside its chunks and rounds
+    s = synth.plain_scene(1015, 20000, 64, 48)
+    s["logit"] = (s["logit"] - 1.8).astype(np.float32)
+    return s
+
+
 def anchor_small():
     # two partitions with uneven anchor counts, two views each, ragged 200x120 tiles
     return synth.anchor_scene(1012, [1500, 800], 2, W=200, H=120, fx=140.0, ssim_weight=0.2, bias_std=0.2)
@@ -46,7 +55,8 @@ def partition_without_views():
 
 # full-size workloads: config 2 (20k anchors, one 1226x370 view) and config 3 (50k
 # anchors, four views, the benchmark's workload)
-SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "anchor_small": anchor_small,
+SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "plain_dense": plain_dense,
+          "anchor_small": anchor_small,
           "empty_partition": partition_without_anchors, "viewless_partition": partition_without_views,
           "C2": lambda: synth.config("C2"),
           "C3": lambda: synth.config("C3")}
@@ -143,6 +153,13 @@ def test_bin_sort_bit_exact(case):
     want = h["depth"][h["vals"]].view(np.uint32).astype(np.uint64) - np.uint64(0x3E4CCCCD)
     assert np.array_equal(dk, want)
     assert np.array_equal(h["ranges"], ref["ranges"])
+    # the long tiles (ranges of 1024+ entries) are counted and listed first in the order
+    lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    n_long = int((lens >= 1024).sum())
+    assert int(pipe.status.cpu().numpy()[7]) == n_long
+    order = pipe.order.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(len(lens)))
+    assert (lens[order[:n_long]] >= 1024).all() and (lens[order[n_long:]] < 1024).all()
 
 
 def test_render_fwd_stagewise(case):
