@@ -47,7 +47,7 @@ constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
 constexpr int kFwdBlocksPerCU = 5;  // persistent workgroups per CU (register-limited occupancy)
 constexpr int kBwdBlocksPerCU = 6;
-constexpr int kChunk = 256;      // entries per wave and round of a long tile
+constexpr int kChunk = 64;       // entries per wave and round of a long tile
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
 // skip and stop decisions are bit-identical.
