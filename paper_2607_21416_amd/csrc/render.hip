@@ -203,6 +203,32 @@ struct RoundLds {
   float v[kWaves][8][64];
 };
 
+// Gathers the records of entries [c0, c1) (absolute positions in vals, at most 64),
+// one entry per lane, into registers; lanes past the end keep their old values.
+__device__ __forceinline__ void fetch_batch(const float* splat, const uint32_t* vals, uint32_t c0, uint32_t c1,
+                                            uint32_t n_gauss, int lane, Rec& rec, uint32_t& gid) {
+  if (c0 + lane < c1) {
+    gid = min(vals[c0 + lane], n_gauss - 1);
+    rec = load_rec(splat, gid);
+  }
+}
+
+// Compacts the hits among one gathered batch into L in entry order (bx.y takes `tag`)
+// and returns the hit mask: bit l is the batch's entry l.
+__device__ __forceinline__ uint64_t compact_hits(const Rec& cur, bool valid, float tag, const Item& it, WaveLds& L,
+                                                 int lane) {
+  const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
+  const uint64_t hm = __ballot(hit);
+  if (hit) {
+    const int pos = __popcll(hm & lanemask_lt(lane));
+    L.r0[pos] = cur.r0;
+    L.r1[pos] = cur.r1;
+    L.bx[pos] = make_float2(cur.r2.x, tag);
+  }
+  __builtin_amdgcn_wave_barrier();
+  return hm;
+}
+
 // Walks entries [c0, c1) (absolute positions in vals) front to back in batches of 64
 // with a register prefetch of the next batch; the hits of each batch are compacted into
 // L (tag: the entry's offset within the batch) and on_batch(nhit, b0) is called; it
@@ -213,20 +239,13 @@ __device__ __forceinline__ void walk_front(const float* splat, const uint32_t* v
                                            OnBatch on_batch) {
   if (!it.live || c0 >= c1) return;
   Rec nxt;
-  if (c0 + lane < c1) nxt = load_rec(splat, min(vals[c0 + lane], n_gauss - 1));
+  uint32_t gid;
+  fetch_batch(splat, vals, c0, c1, n_gauss, lane, nxt, gid);
   for (uint32_t b0 = c0; b0 < c1; b0 += 64) {
     const Rec cur = nxt;
     const bool valid = b0 + lane < c1;
-    if (b0 + 64 + lane < c1) nxt = load_rec(splat, min(vals[b0 + 64 + lane], n_gauss - 1));
-    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
-    const uint64_t hm = __ballot(hit);
-    if (hit) {
-      const int pos = __popcll(hm & lanemask_lt(lane));
-      L.r0[pos] = cur.r0;
-      L.r1[pos] = cur.r1;
-      L.bx[pos] = make_float2(cur.r2.x, __int_as_float(lane));
-    }
-    __builtin_amdgcn_wave_barrier();
+    if (b0 + 64 < c1) fetch_batch(splat, vals, b0 + 64, c1, n_gauss, lane, nxt, gid);
+    const uint64_t hm = compact_hits(cur, valid, __int_as_float(lane), it, L, lane);
     const bool end = on_batch(__popcll(hm), b0);
     __builtin_amdgcn_wave_barrier();
     if (end) break;
@@ -261,77 +280,77 @@ __device__ __forceinline__ void fwd_apply(FwdState& st, float alpha, const float
   st.done = st.done || halt;
 }
 
-// The exact walk of Eq. 1 over entries [c0, c1) of the range starting at s.  Groups of
-// kIlp hits evaluate their alphas side by side; only the updates run in sequence.
+// The exact walk of Eq. 1 over the nhit compacted hits in L, whose batch starts at
+// entry number `base` (tags: offsets within the batch).  Groups of kIlp hits evaluate
+// their alphas side by side; only the updates run in sequence.  Returns true once every
+// pixel has stopped.
+__device__ __forceinline__ bool fwd_exact_hits(const WaveLds& L, int nhit, int base, float px, float py,
+                                               FwdState& st) {
+  int i = 0;
+  for (; i + kIlp <= nhit; i += kIlp) {
+    float4 r0[kIlp], r1[kIlp];
+    float2 bx[kIlp];
+    float alpha[kIlp];
+#pragma unroll
+    for (int k = 0; k < kIlp; ++k) {
+      r0[k] = L.r0[i + k];
+      r1[k] = L.r1[i + k];
+      bx[k] = L.bx[i + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kIlp; ++k) alpha[k] = splat_alpha(r0[k], r1[k], px, py);
+#pragma unroll
+    for (int k = 0; k < kIlp; ++k) fwd_apply(st, alpha[k], r1[k], bx[k], base + __float_as_int(bx[k].y));
+    if (__ballot(!st.done) == 0) return true;
+  }
+  for (; i < nhit; ++i) {
+    const float4 r0 = L.r0[i], r1 = L.r1[i];
+    const float2 bx = L.bx[i];
+    fwd_apply(st, splat_alpha(r0, r1, px, py), r1, bx, base + __float_as_int(bx.y));
+    if (__ballot(!st.done) == 0) return true;
+  }
+  return false;
+}
+
+// The exact walk of Eq. 1 over entries [c0, c1) of the range starting at s.
 __device__ void fwd_exact(const float* splat, const uint32_t* vals, uint32_t s, uint32_t c0, uint32_t c1,
                           uint32_t n_gauss, const Item& it, WaveLds& L, int lane, float px, float py, FwdState& st) {
   if (__ballot(!st.done) == 0) return;
   walk_front(splat, vals, c0, c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
-    const int base = (int)(b0 - s) + 1;
-    int i = 0;
-    for (; i + kIlp <= nhit; i += kIlp) {
-      float4 r0[kIlp], r1[kIlp];
-      float2 bx[kIlp];
-      float alpha[kIlp];
-#pragma unroll
-      for (int k = 0; k < kIlp; ++k) {
-        r0[k] = L.r0[i + k];
-        r1[k] = L.r1[i + k];
-        bx[k] = L.bx[i + k];
-      }
-#pragma unroll
-      for (int k = 0; k < kIlp; ++k) alpha[k] = splat_alpha(r0[k], r1[k], px, py);
-#pragma unroll
-      for (int k = 0; k < kIlp; ++k) fwd_apply(st, alpha[k], r1[k], bx[k], base + __float_as_int(bx[k].y));
-      if (__ballot(!st.done) == 0) return true;
-    }
-    for (; i < nhit; ++i) {
-      const float4 r0 = L.r0[i], r1 = L.r1[i];
-      const float2 bx = L.bx[i];
-      fwd_apply(st, splat_alpha(r0, r1, px, py), r1, bx, base + __float_as_int(bx.y));
-      if (__ballot(!st.done) == 0) return true;
-    }
-    return false;
+    return fwd_exact_hits(L, nhit, (int)(b0 - s) + 1, px, py, st);
   });
 }
 
-// Local compositing of entries [c0, c1) from T = 1 without the stop rule (pixels with
-// `dead` set take no part): the chunk's own colour L, transmittance P and last
-// composited entry.  Ends early once every live pixel's P is below the stop threshold
-// (such a pixel stops inside this chunk whatever lies in front of it).
-__device__ void fwd_local(const float* splat, const uint32_t* vals, uint32_t s, uint32_t c0, uint32_t c1,
-                          uint32_t n_gauss, const Item& it, WaveLds& L, int lane, float px, float py, bool dead,
-                          float& P, float& L0, float& L1, float& L2, int& last) {
+// Local compositing of the nhit compacted hits in L (batch starting at entry number
+// `base`) from T = 1 without the stop rule (pixels with `dead` set take no part): the
+// chunk's own colour L, transmittance P and last composited entry.
+__device__ __forceinline__ void fwd_local_hits(const WaveLds& L, int nhit, int base, float px, float py, bool dead,
+                                               float& P, float& L0, float& L1, float& L2, int& last) {
   P = 1.f;
   L0 = L1 = L2 = 0.f;
   last = 0;
-  if (__ballot(!dead) == 0) return;
-  walk_front(splat, vals, c0, c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
-    const int base = (int)(b0 - s) + 1;
-    for (int i = 0; i < nhit; i += kIlp) {
-      float4 r1[kIlp];
-      float2 bx[kIlp];
-      float alpha[kIlp];
+  for (int i = 0; i < nhit; i += kIlp) {
+    float4 r1[kIlp];
+    float2 bx[kIlp];
+    float alpha[kIlp];
 #pragma unroll
-      for (int k = 0; k < kIlp; ++k) {
-        const int j = min(i + k, nhit - 1);
-        r1[k] = L.r1[j];
-        bx[k] = L.bx[j];
-        alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
-      }
-#pragma unroll
-      for (int k = 0; k < kIlp; ++k) {
-        const bool take = !dead && alpha[k] >= kAlphaMin;
-        const float wgt = take ? alpha[k] * P : 0.f;
-        L0 = fmaf(r1[k].z, wgt, L0);
-        L1 = fmaf(r1[k].w, wgt, L1);
-        L2 = fmaf(bx[k].x, wgt, L2);
-        P = take ? P * (1.f - alpha[k]) : P;
-        last = take ? base + __float_as_int(bx[k].y) : last;
-      }
+    for (int k = 0; k < kIlp; ++k) {
+      const int j = min(i + k, nhit - 1);
+      r1[k] = L.r1[j];
+      bx[k] = L.bx[j];
+      alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
     }
-    return __ballot(!dead && !(P < kTMin)) == 0;
-  });
+#pragma unroll
+    for (int k = 0; k < kIlp; ++k) {
+      const bool take = !dead && alpha[k] >= kAlphaMin;
+      const float wgt = take ? alpha[k] * P : 0.f;
+      L0 = fmaf(r1[k].z, wgt, L0);
+      L1 = fmaf(r1[k].w, wgt, L1);
+      L2 = fmaf(bx[k].x, wgt, L2);
+      P = take ? P * (1.f - alpha[k]) : P;
+      last = take ? base + __float_as_int(bx[k].y) : last;
+    }
+  }
 }
 
 __device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, const float* bgc, float* image,
@@ -349,18 +368,34 @@ __device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, co
 }
 
 // A long tile's quadrant, composited by the whole workgroup in rounds of four chunks.
+// A chunk is one gathered batch: its hits stay in L for the exact pass, and the next
+// round's records are fetched while the current round is composited.
+static_assert(kChunk == 64, "a long-tile chunk is one gathered batch");
 __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
                          const Item& it, WaveLds& L, RoundLds& R, int w, int lane, const float* bgc, float* image,
                          float* T_final, int32_t* n_contrib, int32_t* n_eval) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int n = (int)(e - s);
   FwdState st{1.f, 0.f, 0.f, 0.f, 0, n, !it.inside};
+  Rec nxt;
+  uint32_t gid;
+  {
+    const uint32_t c0 = s + min((uint32_t)n, (uint32_t)(w * kChunk));
+    fetch_batch(splat, vals, c0, min(c0 + kChunk, e), n_gauss, lane, nxt, gid);
+  }
   for (uint32_t r0 = s; r0 < e; r0 += kWaves * kChunk) {
-    const uint32_t c0 = min(r0 + (uint32_t)w * kChunk, e), c1 = min(c0 + kChunk, e);
-    // 1. this wave's chunk, locally
+    const uint32_t c0 = r0 + min(e - r0, (uint32_t)(w * kChunk)), c1 = min(c0 + kChunk, e);
+    const Rec cur = nxt;
+    if (e - r0 > (uint32_t)(kWaves * kChunk)) {
+      const uint32_t n0 = r0 + min(e - r0, (uint32_t)((kWaves + w) * kChunk));
+      fetch_batch(splat, vals, n0, min(n0 + kChunk, e), n_gauss, lane, nxt, gid);
+    }
+    // 1. this wave's chunk, locally (st.done is the same in every wave)
+    const uint64_t hm = __ballot(!st.done) ? compact_hits(cur, c0 + lane < c1, __int_as_float(lane), it, L, lane) : 0ull;
+    const int nhit = __popcll(hm), base = (int)(c0 - s) + 1;
     float P, L0, L1, L2;
     int llast;
-    fwd_local(splat, vals, s, c0, c1, n_gauss, it, L, lane, px, py, st.done, P, L0, L1, L2, llast);
+    fwd_local_hits(L, nhit, base, px, py, st.done, P, L0, L1, L2, llast);
     R.v[w][0][lane] = P;
     __syncthreads();
     // 2. transmittance in front of the chunk; the chunk where the pixel stops is redone
@@ -376,7 +411,7 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
     }
     const bool here = !before && Tin * P < kTMin;
     FwdState ex{Tin, 0.f, 0.f, 0.f, 0, n, !here};
-    fwd_exact(splat, vals, s, c0, c1, n_gauss, it, L, lane, px, py, ex);
+    if (__ballot(here)) fwd_exact_hits(L, nhit, base, px, py, ex);
     __syncthreads();  // every wave has read the P values
     const int state = before ? 0 : (here ? 2 : 1);
     R.v[w][0][lane] = here ? ex.T : Tin * P;
@@ -511,120 +546,106 @@ struct BwdState {
   int last;
 };
 
+// The hits of one batch (mask hm over the batch's entries, the first at range offset
+// lo; compacted into L with the Gaussian's index as tag) in reverse order: per hit
+// T_i = T_{i+1} / (1 - alpha_i), the nine gradient terms, one reduction and one atomic
+// per Gaussian, then the colour behind.
+__device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, float px, float py, int comp,
+                                         BwdState& st, float* g2d) {
+  const int nhit = __popcll(hm);
+  // the entry offset of hit i is the position of the i-th set bit of the mask
+  uint64_t rem = hm;
+  for (int i = nhit - 1; i >= 0; --i) {
+    const int bit = 63 - __clzll((unsigned long long)rem);
+    rem &= ~(1ull << bit);
+    const float4 r0 = L.r0[i], r1 = L.r1[i];
+    const float2 bx = L.bx[i];
+    float dx, dy, ep, raw;
+    const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
+    const bool contrib = lo + bit < st.last && alpha >= kAlphaMin;
+    if (__ballot(contrib) == 0) continue;
+    // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
+    st.T = contrib ? st.T * __builtin_amdgcn_rcpf(1.f - alpha) : st.T;
+    const float wgt = contrib ? alpha * st.T : 0.f;
+    const float cb = bx.x;
+    const float dal =
+        contrib ? st.T * (st.g0 * (r1.z - st.B0) + st.g1 * (r1.w - st.B1) + st.g2 * (cb - st.B2)) : 0.f;
+    const float aB = contrib ? alpha : 0.f;
+    st.B0 = fmaf(aB, r1.z - st.B0, st.B0);
+    st.B1 = fmaf(aB, r1.w - st.B1, st.B1);
+    st.B2 = fmaf(aB, cb - st.B2, st.B2);
+    const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
+    const float dop = free_alpha ? dal * ep : 0.f;
+    const float dp = free_alpha ? dal * alpha : 0.f;
+    float v[9];
+    // moments of dL/dpower; the projection adjoint applies the conic
+    v[0] = dp * dx;
+    v[1] = dp * dy;
+    v[2] = v[0] * dx;
+    v[3] = v[0] * dy;
+    v[4] = v[1] * dy;
+    v[5] = dop;
+    v[6] = st.g0 * wgt;
+    v[7] = st.g1 * wgt;
+    v[8] = st.g2 * wgt;
+    const float tot = reduce9(v);
+    if (comp >= 0) atomicAdd(&g2d[(size_t)__float_as_uint(bx.y) * 9 + comp], tot);
+  }
+}
+
 // The reverse walk over range offsets [lo_end, hi) (from hi - 1 down), relative to the
-// range start s: per hit T_i = T_{i+1} / (1 - alpha_i), the nine gradient terms, one
-// reduction and one atomic per Gaussian, then the colour behind.
+// range start s, in batches of 64 with a register prefetch of the next batch.
 __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, int lo_end, int hi, uint32_t n_gauss,
                          const Item& it, WaveLds& L, int lane, int comp, BwdState& st, float* g2d) {
   if (!it.live || hi <= lo_end) return;
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   Rec nxt;
   uint32_t ngid = 0;
-  {
-    const int lo = max(lo_end, hi - 64);
-    if (lo + lane < hi) {
-      ngid = min(vals[s + lo + lane], n_gauss - 1);
-      nxt = load_rec(splat, ngid);
-    }
-  }
+  fetch_batch(splat, vals, s + max(lo_end, hi - 64), s + hi, n_gauss, lane, nxt, ngid);
   for (int bh = hi; bh > lo_end; bh -= 64) {
     const int lo = max(lo_end, bh - 64);
     const Rec cur = nxt;
     const uint32_t cgid = ngid;
-    const bool valid = lo + lane < bh;
-    if (lo > lo_end) {
-      const int lo2 = max(lo_end, lo - 64);
-      if (lo2 + lane < lo) {
-        ngid = min(vals[s + lo2 + lane], n_gauss - 1);
-        nxt = load_rec(splat, ngid);
-      }
-    }
-    const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
-    const uint64_t hm = __ballot(hit);
-    if (hit) {
-      const int pos = __popcll(hm & lanemask_lt(lane));
-      L.r0[pos] = cur.r0;
-      L.r1[pos] = cur.r1;
-      L.bx[pos] = make_float2(cur.r2.x, __uint_as_float(cgid));
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int nhit = __popcll(hm);
-    // hits in reverse order; the entry offset of hit i is the position of the i-th set
-    // bit of the ballot mask
-    uint64_t rem = hm;
-    for (int i = nhit - 1; i >= 0; --i) {
-      const int bit = 63 - __clzll((unsigned long long)rem);
-      rem &= ~(1ull << bit);
-      const float4 r0 = L.r0[i], r1 = L.r1[i];
-      const float2 bx = L.bx[i];
-      float dx, dy, ep, raw;
-      const float alpha = splat_alpha(r0, r1, px, py, dx, dy, ep, raw);
-      const bool contrib = lo + bit < st.last && alpha >= kAlphaMin;
-      if (__ballot(contrib) == 0) continue;
-      // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
-      st.T = contrib ? st.T * __builtin_amdgcn_rcpf(1.f - alpha) : st.T;
-      const float wgt = contrib ? alpha * st.T : 0.f;
-      const float cb = bx.x;
-      const float dal =
-          contrib ? st.T * (st.g0 * (r1.z - st.B0) + st.g1 * (r1.w - st.B1) + st.g2 * (cb - st.B2)) : 0.f;
-      const float aB = contrib ? alpha : 0.f;
-      st.B0 = fmaf(aB, r1.z - st.B0, st.B0);
-      st.B1 = fmaf(aB, r1.w - st.B1, st.B1);
-      st.B2 = fmaf(aB, cb - st.B2, st.B2);
-      const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
-      const float dop = free_alpha ? dal * ep : 0.f;
-      const float dp = free_alpha ? dal * alpha : 0.f;
-      float v[9];
-      // moments of dL/dpower; the projection adjoint applies the conic
-      v[0] = dp * dx;
-      v[1] = dp * dy;
-      v[2] = v[0] * dx;
-      v[3] = v[0] * dy;
-      v[4] = v[1] * dy;
-      v[5] = dop;
-      v[6] = st.g0 * wgt;
-      v[7] = st.g1 * wgt;
-      v[8] = st.g2 * wgt;
-      const float tot = reduce9(v);
-      if (comp >= 0) atomicAdd(&g2d[(size_t)__float_as_uint(bx.y) * 9 + comp], tot);
-    }
+    if (lo > lo_end) fetch_batch(splat, vals, s + max(lo_end, lo - 64), s + lo, n_gauss, lane, nxt, ngid);
+    const uint64_t hm = compact_hits(cur, lo + lane < bh, __uint_as_float(cgid), it, L, lane);
+    bwd_hits(L, hm, lo, px, py, comp, st, g2d);
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-// Local front-to-back compositing of range offsets [c0, c1) over the pixel's composited
-// entries (offset < last, alpha >= 1/255): the chunk's own colour L and transmittance P.
-__device__ void bwd_local(const float* splat, const uint32_t* vals, uint32_t s, int c0, int c1, uint32_t n_gauss,
-                          const Item& it, WaveLds& L, int lane, int last, float& P, float& L0, float& L1,
-                          float& L2) {
+// Local front-to-back compositing of one batch's hits (mask hm, the first entry at
+// range offset lo, compacted in L) over the pixel's composited entries (offset < last,
+// alpha >= 1/255): the batch's own colour L and transmittance P.
+__device__ __forceinline__ void bwd_local_hits(const WaveLds& L, uint64_t hm, int lo, int last, float px, float py,
+                                               float& P, float& L0, float& L1, float& L2) {
   P = 1.f;
   L0 = L1 = L2 = 0.f;
-  const float px = it.x + 0.5f, py = it.y + 0.5f;
-  walk_front(splat, vals, s + (uint32_t)c0, s + (uint32_t)c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
-    const int base = (int)(b0 - s);
-    for (int i = 0; i < nhit; i += kIlp) {
-      float4 r1[kIlp];
-      float2 bx[kIlp];
-      float alpha[kIlp];
+  const int nhit = __popcll(hm);
+  uint64_t rem = hm;
+  for (int i = 0; i < nhit; i += kIlp) {
+    float4 r1[kIlp];
+    float2 bx[kIlp];
+    float alpha[kIlp];
+    int off[kIlp];
 #pragma unroll
-      for (int k = 0; k < kIlp; ++k) {
-        const int j = min(i + k, nhit - 1);
-        r1[k] = L.r1[j];
-        bx[k] = L.bx[j];
-        alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
-      }
-#pragma unroll
-      for (int k = 0; k < kIlp; ++k) {
-        const bool take = base + __float_as_int(bx[k].y) < last && alpha[k] >= kAlphaMin;
-        const float wgt = take ? alpha[k] * P : 0.f;
-        L0 = fmaf(r1[k].z, wgt, L0);
-        L1 = fmaf(r1[k].w, wgt, L1);
-        L2 = fmaf(bx[k].x, wgt, L2);
-        P = take ? P * (1.f - alpha[k]) : P;
-      }
+    for (int k = 0; k < kIlp; ++k) {
+      const int j = min(i + k, nhit - 1);
+      r1[k] = L.r1[j];
+      bx[k] = L.bx[j];
+      alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
+      off[k] = rem ? __builtin_ctzll(rem) : 0;  // offset of hit i + k (unused past the last hit)
+      rem &= rem - 1;
     }
-    return false;
-  });
+#pragma unroll
+    for (int k = 0; k < kIlp; ++k) {
+      const bool take = lo + off[k] < last && alpha[k] >= kAlphaMin;
+      const float wgt = take ? alpha[k] * P : 0.f;
+      L0 = fmaf(r1[k].z, wgt, L0);
+      L1 = fmaf(r1[k].w, wgt, L1);
+      L2 = fmaf(bx[k].x, wgt, L2);
+      P = take ? P * (1.f - alpha[k]) : P;
+    }
+  }
 }
 
 __device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const float* bgc, const float* T_final,
@@ -644,13 +665,29 @@ __device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const 
 }
 
 // A long tile's quadrant, by the whole workgroup in rounds of four chunks from the back.
+// A chunk is one gathered batch, compacted once for both passes; the next round's
+// records are fetched while the current round is walked.
 __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t n_gauss, const Item& it,
                          WaveLds& L, RoundLds& R, int w, int lane, int comp, BwdState st, float* g2d) {
+  const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int top = it.live ? wave_max(st.last) : 0;  // the same in every wave
+  Rec nxt;
+  uint32_t ngid = 0;
+  {
+    const int c1 = max(0, top - w * kChunk);
+    fetch_batch(splat, vals, s + max(0, c1 - kChunk), s + c1, n_gauss, lane, nxt, ngid);
+  }
   for (int hi = top; hi > 0; hi -= kWaves * kChunk) {
     const int c1 = max(0, hi - w * kChunk), c0 = max(0, c1 - kChunk);
+    const Rec cur = nxt;
+    const uint32_t cgid = ngid;
+    if (hi > kWaves * kChunk) {
+      const int n1 = max(0, hi - (kWaves + w) * kChunk);
+      fetch_batch(splat, vals, s + max(0, n1 - kChunk), s + n1, n_gauss, lane, nxt, ngid);
+    }
+    const uint64_t hm = compact_hits(cur, c0 + lane < c1, __uint_as_float(cgid), it, L, lane);
     float P, L0, L1, L2;
-    bwd_local(splat, vals, s, c0, c1, n_gauss, it, L, lane, st.last, P, L0, L1, L2);
+    bwd_local_hits(L, hm, c0, st.last, px, py, P, L0, L1, L2);
     R.v[w][0][lane] = P;
     R.v[w][1][lane] = L0;
     R.v[w][2][lane] = L1;
@@ -665,7 +702,7 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
       cs.B1 = fmaf(Pj, cs.B1, R.v[j][2][lane]);
       cs.B2 = fmaf(Pj, cs.B2, R.v[j][3][lane]);
     }
-    bwd_walk(splat, vals, s, c0, c1, n_gauss, it, L, lane, comp, cs, g2d);
+    bwd_hits(L, hm, c0, px, py, comp, cs, g2d);
     // state in front of the round (identical in every wave)
     for (int j = 0; j < kWaves; ++j) {
       const float Pj = R.v[j][0][lane];
