@@ -157,8 +157,10 @@ typedef struct {
   float* depth;     /* [n]    camera-space z                                        */
   float* ext;       /* [2][n] footprint half extents, -1 when culled                */
   int32_t* ntiles;  /* [n]    tiles touched, 0 when culled                          */
-  float* splat;     /* [n][12] packed render record (u, v, A, B, C, opacity, r, g, b,
-                       pixel box x0|x1<<16 and y0|y1<<16 as bits, depth)            */
+  float* splat;     /* [n][12] packed render record (u, v, a, b, c, opacity, r, g, b,
+                       pixel box x0|x1<<16 and y0|y1<<16 as bits, depth), where
+                       (a, b, c) = -log2(e) (A/2, B, C/2): the splat's alpha at
+                       offset (dx, dy) is opacity 2^(a dx^2 + b dx dy + c dy^2)      */
 } glam_projected;
 
 /* Words of the compositing work-queue buffer (two kernels x (16 counters on separate

@@ -156,8 +156,10 @@ __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, cons
   if (vis) {
     const uint32_t bx = (uint32_t)x0 | ((uint32_t)x1 << 16);
     const uint32_t by = (uint32_t)y0 | ((uint32_t)y1 << 16);
-    rec[0] = make_float4(p.u, p.v, p.conic[0], p.conic[1]);
-    rec[1] = make_float4(p.conic[2], g.op, g.rgb[0], g.rgb[1]);
+    // the conic as a base-2 exponent: -log2(e) (A/2, B, C/2)
+    constexpr float kLog2e = 1.4426950408889634f;
+    rec[0] = make_float4(p.u, p.v, -0.5f * kLog2e * p.conic[0], -kLog2e * p.conic[1]);
+    rec[1] = make_float4(-0.5f * kLog2e * p.conic[2], g.op, g.rgb[0], g.rgb[1]);
     rec[2] = make_float4(g.rgb[2], __uint_as_float(bx), __uint_as_float(by), p.t[2]);
   }
 }

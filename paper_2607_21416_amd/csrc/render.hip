@@ -50,14 +50,15 @@ constexpr int kBwdBlocksPerCU = 6;
 constexpr int kChunk = 64;       // entries per wave and round of a long tile
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
-// skip and stop decisions are bit-identical.
+// skip and stop decisions are bit-identical.  The record holds the conic as a base-2
+// exponent, (a, b, c) = -log2(e) (A/2, B, C/2): with (dx, dy) = centre - pixel,
+// alpha = min(0.99, opacity 2^(a dx^2 + b dx dy + c dy^2)); ep = 2^(...) = e^power.
 __device__ __forceinline__ float splat_alpha(const float4& r0, const float4& r1, float px, float py,
                                              float& dx, float& dy, float& ep, float& raw) {
   dx = r0.x - px;
   dy = r0.y - py;
-  const float q = fmaf(r0.z * dx, dx, (r1.x * dy) * dy);
-  const float power = fmaf(-0.5f, q, -((r0.w * dx) * dy));
-  ep = __expf(power);
+  const float e2 = fmaf(dx, fmaf(r0.z, dx, r0.w * dy), (r1.x * dy) * dy);
+  ep = __builtin_amdgcn_exp2f(e2);
   raw = r1.y * ep;
   return fminf(kAlphaMax, raw);
 }
@@ -106,29 +107,32 @@ __device__ __forceinline__ bool box_meets(float bxf, float byf, const Item& it) 
 }
 
 // Whether the Gaussian's alpha can reach 1/255 at any pixel centre of the quadrant: the
-// minimum over the centres' rectangle of q = A dx^2 + 2 B dx dy + C dy^2 (the power is
-// -q/2) against 2 ln(255 opacity).  The minimum of this convex form over the rectangle
-// is 0 when the centre is inside, else it lies on an edge, where it is the clamped
-// one-dimensional minimum.  The test runs per batch entry (one entry per lane) and keeps
+// largest value over the centres' rectangle of the record's exponent
+// Q = a dx^2 + b dx dy + c dy^2 (a negative definite form) against -log2(255 opacity).
+// The form peaks (Q = 0) at the centre, so over the rectangle it is 0 when the centre is
+// inside, else its largest value lies on an edge, where it is the clamped
+// one-dimensional maximum.  The test runs per batch entry (one entry per lane) and keeps
 // a margin, so it only drops entries whose alpha is below the threshold at every pixel
 // of the quadrant: the box test passes whole footprint boxes, the ellipse inside
 // can miss the quadrant.
-__device__ __forceinline__ float edge_min_q(float a, float b, float c, float dfix, float lo, float hi) {
-  // q along an edge where the first offset is fixed at dfix and the second runs over [lo, hi]
-  const float d = fminf(fmaxf(-b * dfix * __builtin_amdgcn_rcpf(c), lo), hi);
-  return fmaf(a * dfix, dfix, d * fmaf(c, d, 2.f * b * dfix));
+__device__ __forceinline__ float edge_max(float a, float b, float c, float f, float lo, float hi) {
+  // Q along an edge where one offset is fixed at f and the other, d, runs over [lo, hi]:
+  // a f^2 + d (c d + b f), largest at d = -b f / (2 c)
+  const float d = __builtin_amdgcn_fmed3f(-0.5f * b * f * __builtin_amdgcn_rcpf(c), lo, hi);
+  return fmaf(a * f, f, d * fmaf(c, d, b * f));
 }
 
 __device__ __forceinline__ bool ellipse_meets(const float4& r0, const float4& r1, const Item& it) {
-  const float u = r0.x, v = r0.y, A = r0.z, B = r0.w, C = r1.x;
+  const float u = r0.x, v = r0.y, a = r0.z, b = r0.w, c = r1.x;
   // offsets of the rectangle's edges from the centre
   const float lx = it.qx0 + 0.5f - u, hx = it.qx1 + 0.5f - u;
   const float ly = it.qy0 + 0.5f - v, hy = it.qy1 + 0.5f - v;
   const bool inside = lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f;
-  const float q = fminf(fminf(edge_min_q(A, B, C, lx, ly, hy), edge_min_q(A, B, C, hx, ly, hy)),
-                        fminf(edge_min_q(C, B, A, ly, lx, hx), edge_min_q(C, B, A, hy, lx, hx)));
-  const float lim = 2.f * __logf(255.f * r1.y) + 0.01f;
-  return inside || q <= lim;
+  const float q = fmaxf(fmaxf(edge_max(a, b, c, lx, ly, hy), edge_max(a, b, c, hx, ly, hy)),
+                        fmaxf(edge_max(c, b, a, ly, lx, hx), edge_max(c, b, a, hy, lx, hx)));
+  // opacity 2^Q >= 1/255, with a margin of 0.0073 in Q
+  const float lim = -__log2f(255.f * r1.y) - 0.0073f;
+  return inside || q >= lim;
 }
 
 // Work queue.  Device-scope atomics are served at the memory side, so one counter would
@@ -231,11 +235,11 @@ __device__ __forceinline__ uint64_t compact_hits(const Rec& cur, bool valid, flo
 
 // Walks entries [c0, c1) (absolute positions in vals) front to back in batches of 64
 // with a register prefetch of the next batch; the hits of each batch are compacted into
-// L (tag: the entry's offset within the batch) and on_batch(nhit, b0) is called; it
+// L (tag: the entry's number, first_tag for entry c0) and on_batch(nhit) is called; it
 // returns true to end the walk.
 template <class OnBatch>
 __device__ __forceinline__ void walk_front(const float* splat, const uint32_t* vals, uint32_t c0, uint32_t c1,
-                                           uint32_t n_gauss, const Item& it, WaveLds& L, int lane,
+                                           int first_tag, uint32_t n_gauss, const Item& it, WaveLds& L, int lane,
                                            OnBatch on_batch) {
   if (!it.live || c0 >= c1) return;
   Rec nxt;
@@ -245,8 +249,9 @@ __device__ __forceinline__ void walk_front(const float* splat, const uint32_t* v
     const Rec cur = nxt;
     const bool valid = b0 + lane < c1;
     if (b0 + 64 < c1) fetch_batch(splat, vals, b0 + 64, c1, n_gauss, lane, nxt, gid);
-    const uint64_t hm = compact_hits(cur, valid, __int_as_float(lane), it, L, lane);
-    const bool end = on_batch(__popcll(hm), b0);
+    const int tag = first_tag + (int)(b0 - c0) + lane;
+    const uint64_t hm = compact_hits(cur, valid, __int_as_float(tag), it, L, lane);
+    const bool end = on_batch(__popcll(hm));
     __builtin_amdgcn_wave_barrier();
     if (end) break;
   }
@@ -264,28 +269,29 @@ struct FwdState {
   bool done;
 };
 
-// One hit, in order: the skip and stop rules of Eq. 1 on this lane's pixel.
-__device__ __forceinline__ void fwd_apply(FwdState& st, float alpha, const float4& r1, const float2& bx, int entry) {
-  const float Tn = st.T * (1.f - alpha);
+// One hit, in order: the skip and stop rules of Eq. 1 on this lane's pixel (kStop: also
+// record the entry that stops the walk).
+template <bool kStop>
+__device__ __forceinline__ void fwd_apply(FwdState& st, float alpha, const float4& r1, const float2& bx) {
+  const float Tn = fmaf(-alpha, st.T, st.T);
   const bool ok = !st.done && alpha >= kAlphaMin;
   const bool halt = ok && Tn < kTMin;
-  const bool take = ok && !(Tn < kTMin);
-  const float wgt = take ? alpha * st.T : 0.f;
+  const bool take = ok && !halt;
+  const float wgt = (take ? alpha : 0.f) * st.T;
   st.C0 = fmaf(r1.z, wgt, st.C0);
   st.C1 = fmaf(r1.w, wgt, st.C1);
   st.C2 = fmaf(bx.x, wgt, st.C2);
   st.T = take ? Tn : st.T;
-  st.last = take ? entry : st.last;
-  st.stop = halt ? entry : st.stop;
+  st.last = take ? __float_as_int(bx.y) : st.last;
+  if (kStop) st.stop = halt ? __float_as_int(bx.y) : st.stop;
   st.done = st.done || halt;
 }
 
-// The exact walk of Eq. 1 over the nhit compacted hits in L, whose batch starts at
-// entry number `base` (tags: offsets within the batch).  Groups of kIlp hits evaluate
-// their alphas side by side; only the updates run in sequence.  Returns true once every
-// pixel has stopped.
-__device__ __forceinline__ bool fwd_exact_hits(const WaveLds& L, int nhit, int base, float px, float py,
-                                               FwdState& st) {
+// The exact walk of Eq. 1 over the nhit compacted hits in L (tags: entry numbers).
+// Groups of kIlp hits evaluate their alphas side by side; only the updates run in
+// sequence.  Returns true once every pixel has stopped.
+template <bool kStop>
+__device__ __forceinline__ bool fwd_exact_hits(const WaveLds& L, int nhit, float px, float py, FwdState& st) {
   int i = 0;
   for (; i + kIlp <= nhit; i += kIlp) {
     float4 r0[kIlp], r1[kIlp];
@@ -300,32 +306,32 @@ __device__ __forceinline__ bool fwd_exact_hits(const WaveLds& L, int nhit, int b
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) alpha[k] = splat_alpha(r0[k], r1[k], px, py);
 #pragma unroll
-    for (int k = 0; k < kIlp; ++k) fwd_apply(st, alpha[k], r1[k], bx[k], base + __float_as_int(bx[k].y));
+    for (int k = 0; k < kIlp; ++k) fwd_apply<kStop>(st, alpha[k], r1[k], bx[k]);
     if (__ballot(!st.done) == 0) return true;
   }
   for (; i < nhit; ++i) {
     const float4 r0 = L.r0[i], r1 = L.r1[i];
     const float2 bx = L.bx[i];
-    fwd_apply(st, splat_alpha(r0, r1, px, py), r1, bx, base + __float_as_int(bx.y));
+    fwd_apply<kStop>(st, splat_alpha(r0, r1, px, py), r1, bx);
     if (__ballot(!st.done) == 0) return true;
   }
   return false;
 }
 
 // The exact walk of Eq. 1 over entries [c0, c1) of the range starting at s.
+template <bool kStop>
 __device__ void fwd_exact(const float* splat, const uint32_t* vals, uint32_t s, uint32_t c0, uint32_t c1,
                           uint32_t n_gauss, const Item& it, WaveLds& L, int lane, float px, float py, FwdState& st) {
   if (__ballot(!st.done) == 0) return;
-  walk_front(splat, vals, c0, c1, n_gauss, it, L, lane, [&](int nhit, uint32_t b0) {
-    return fwd_exact_hits(L, nhit, (int)(b0 - s) + 1, px, py, st);
-  });
+  walk_front(splat, vals, c0, c1, (int)(c0 - s) + 1, n_gauss, it, L, lane,
+             [&](int nhit) { return fwd_exact_hits<kStop>(L, nhit, px, py, st); });
 }
 
-// Local compositing of the nhit compacted hits in L (batch starting at entry number
-// `base`) from T = 1 without the stop rule (pixels with `dead` set take no part): the
-// chunk's own colour L, transmittance P and last composited entry.
-__device__ __forceinline__ void fwd_local_hits(const WaveLds& L, int nhit, int base, float px, float py, bool dead,
-                                               float& P, float& L0, float& L1, float& L2, int& last) {
+// Local compositing of the nhit compacted hits in L (tags: entry numbers) from T = 1
+// without the stop rule (pixels with `dead` set take no part): the chunk's own colour
+// L, transmittance P and last composited entry.
+__device__ __forceinline__ void fwd_local_hits(const WaveLds& L, int nhit, float px, float py, bool dead, float& P,
+                                               float& L0, float& L1, float& L2, int& last) {
   P = 1.f;
   L0 = L1 = L2 = 0.f;
   last = 0;
@@ -343,12 +349,12 @@ __device__ __forceinline__ void fwd_local_hits(const WaveLds& L, int nhit, int b
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
       const bool take = !dead && alpha[k] >= kAlphaMin;
-      const float wgt = take ? alpha[k] * P : 0.f;
+      const float wgt = (take ? alpha[k] : 0.f) * P;
       L0 = fmaf(r1[k].z, wgt, L0);
       L1 = fmaf(r1[k].w, wgt, L1);
       L2 = fmaf(bx[k].x, wgt, L2);
-      P = take ? P * (1.f - alpha[k]) : P;
-      last = take ? base + __float_as_int(bx[k].y) : last;
+      P = take ? fmaf(-alpha[k], P, P) : P;
+      last = take ? __float_as_int(bx[k].y) : last;
     }
   }
 }
@@ -371,6 +377,7 @@ __device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, co
 // A chunk is one gathered batch: its hits stay in L for the exact pass, and the next
 // round's records are fetched while the current round is composited.
 static_assert(kChunk == 64, "a long-tile chunk is one gathered batch");
+template <bool kStop>
 __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
                          const Item& it, WaveLds& L, RoundLds& R, int w, int lane, const float* bgc, float* image,
                          float* T_final, int32_t* n_contrib, int32_t* n_eval) {
@@ -391,11 +398,12 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
       fetch_batch(splat, vals, n0, min(n0 + kChunk, e), n_gauss, lane, nxt, gid);
     }
     // 1. this wave's chunk, locally (st.done is the same in every wave)
-    const uint64_t hm = __ballot(!st.done) ? compact_hits(cur, c0 + lane < c1, __int_as_float(lane), it, L, lane) : 0ull;
-    const int nhit = __popcll(hm), base = (int)(c0 - s) + 1;
+    const int tag = (int)(c0 - s) + 1 + lane;  // entry number
+    const uint64_t hm = __ballot(!st.done) ? compact_hits(cur, c0 + lane < c1, __int_as_float(tag), it, L, lane) : 0ull;
+    const int nhit = __popcll(hm);
     float P, L0, L1, L2;
     int llast;
-    fwd_local_hits(L, nhit, base, px, py, st.done, P, L0, L1, L2, llast);
+    fwd_local_hits(L, nhit, px, py, st.done, P, L0, L1, L2, llast);
     R.v[w][0][lane] = P;
     __syncthreads();
     // 2. transmittance in front of the chunk; the chunk where the pixel stops is redone
@@ -411,7 +419,7 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
     }
     const bool here = !before && Tin * P < kTMin;
     FwdState ex{Tin, 0.f, 0.f, 0.f, 0, n, !here};
-    if (__ballot(here)) fwd_exact_hits(L, nhit, base, px, py, ex);
+    if (__ballot(here)) fwd_exact_hits<kStop>(L, nhit, px, py, ex);
     __syncthreads();  // every wave has read the P values
     const int state = before ? 0 : (here ? 2 : 1);
     R.v[w][0][lane] = here ? ex.T : Tin * P;
@@ -443,6 +451,8 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
   if (w == 0) fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
 }
 
+// kCount: also record per pixel the entry that stopped the walk (n_eval).
+template <bool kCount>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdBlocksPerCU)))
 render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
@@ -463,7 +473,7 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
     const Item it = make_item(views, n_views, tile, (int)(li & 3u), lane);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
-    fwd_long(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
+    fwd_long<kCount>(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
   }
   __builtin_amdgcn_s_setprio(0);
   // the other tiles, one quadrant per wave
@@ -474,7 +484,7 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     FwdState st{1.f, 0.f, 0.f, 0.f, 0, (int)(e - s), !it.inside};
-    fwd_exact(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
+    fwd_exact<kCount>(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
     fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
   }
   leave_queue(queue, gridDim.x * kWaves, lane);
@@ -498,34 +508,46 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-__device__ __forceinline__ float row_sum(float v) {
-  v += dpp<0xb1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4e>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x124>(v);  // row_ror:4
-  v += dpp<0x128>(v);  // row_ror:8
-  return v;
+// Two values folded at once within each 16-lane row: a DPP move with a bank mask (a bank
+// is four lanes of a row) writes only the enabled banks, so two moves and an add leave
+// a + a(partner) in banks BANKS and b + b(partner) in the others.
+template <int CTRL, int BANKS>
+__device__ __forceinline__ float pair_fold(float a, float b) {
+  const int t = __builtin_amdgcn_update_dpp(__float_as_int(b), __float_as_int(a), CTRL, 0xf, BANKS, false);
+  const int u = __builtin_amdgcn_update_dpp(__float_as_int(a), __float_as_int(b), CTRL, 0xf, 0xf ^ BANKS, false);
+  return __int_as_float(t) + __int_as_float(u);
 }
 
-// Component of the total that reduce9 leaves in this lane (lanes 16r + k, k < 3), or -1:
-// the swaps applied to the value tags.  Each swap moves whole rows or half-waves, so a
-// lane's two swap outputs always belong to one component, whatever half goes where.
+constexpr int kRowMirror = 0x140, kHalfMirror = 0x141, kQuadSwap2 = 0x4e, kQuadSwap1 = 0xb1;
+
+// Component of the total that reduce9 leaves in this lane, or -1: the swaps applied to
+// the value tags (each swap moves whole rows or half-waves, so a lane's two swap outputs
+// always belong to one component, whatever half goes where), then the row stage, which
+// leaves in the first lane of banks 0, 2 and 1 of a row its x0, x1 and x2.
 __device__ __forceinline__ int reduce9_comp() {
   const uint32_t none = 0xffffffffu;
   const uint32_t w0 = swap32_first(0, 1), w1 = swap32_first(2, 3), w2 = swap32_first(4, 5), w3 = swap32_first(6, 7),
                  w4 = swap32_first(8, none);
   const uint32_t x0 = swap16_first(w0, w1), x1 = swap16_first(w2, w3), x2 = swap16_first(w4, none);
-  const int k = threadIdx.x & 15;
-  return k == 0 ? (int)x0 : (k == 1 ? (int)x1 : (k == 2 ? (int)x2 : -1));
+  const int bank = (threadIdx.x >> 2) & 3;
+  if (threadIdx.x & 3) return -1;
+  return bank == 0 ? (int)x0 : (bank == 2 ? (int)x1 : (bank == 1 ? (int)x2 : -1));
 }
 
 // Sum of nine per-lane values over the wave, scattered so that nine lanes hold one total
-// each (reduce-scatter).  The wave must be fully active.
+// each (reduce-scatter): two lane-swap stages, then within each row x0 and x1 folded
+// across the row's halves together, and the three values across each half together.
+// The wave must be fully active.
 __device__ __forceinline__ float reduce9(const float v[9]) {
   const float w0 = swap32_sum(v[0], v[1]), w1 = swap32_sum(v[2], v[3]), w2 = swap32_sum(v[4], v[5]),
               w3 = swap32_sum(v[6], v[7]), w4 = swap32_sum(v[8], 0.f);
-  const float x0 = row_sum(swap16_sum(w0, w1)), x1 = row_sum(swap16_sum(w2, w3)), x2 = row_sum(swap16_sum(w4, 0.f));
-  const int k = threadIdx.x & 15;
-  return k == 0 ? x0 : (k == 1 ? x1 : x2);
+  const float x0 = swap16_sum(w0, w1), x1 = swap16_sum(w2, w3), x2 = swap16_sum(w4, 0.f);
+  const float y = pair_fold<kRowMirror, 0x3>(x0, x1);  // row lanes 0-7: x0, 8-15: x1
+  const float z = x2 + dpp<kRowMirror>(x2);
+  float t = pair_fold<kHalfMirror, 0x5>(y, z);  // banks 0, 2: x0, x1; banks 1, 3: x2
+  t += dpp<kQuadSwap2>(t);
+  t += dpp<kQuadSwap1>(t);
+  return t;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -565,18 +587,18 @@ __device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, 
     const bool contrib = lo + bit < st.last && alpha >= kAlphaMin;
     if (__ballot(contrib) == 0) continue;
     // T in front of this Gaussian: T_i = T_{i+1} / (1 - alpha_i)
-    st.T = contrib ? st.T * __builtin_amdgcn_rcpf(1.f - alpha) : st.T;
-    const float wgt = contrib ? alpha * st.T : 0.f;
-    const float cb = bx.x;
-    const float dal =
-        contrib ? st.T * (st.g0 * (r1.z - st.B0) + st.g1 * (r1.w - st.B1) + st.g2 * (cb - st.B2)) : 0.f;
+    const float Tc = st.T * __builtin_amdgcn_rcpf(1.f - alpha);
+    st.T = contrib ? Tc : st.T;
     const float aB = contrib ? alpha : 0.f;
-    st.B0 = fmaf(aB, r1.z - st.B0, st.B0);
-    st.B1 = fmaf(aB, r1.w - st.B1, st.B1);
-    st.B2 = fmaf(aB, cb - st.B2, st.B2);
-    const bool free_alpha = raw <= kAlphaMax;  // alpha not clamped: it depends on its inputs
-    const float dop = free_alpha ? dal * ep : 0.f;
-    const float dp = free_alpha ? dal * alpha : 0.f;
+    const float wgt = aB * st.T;  // alpha_i T_i, 0 off the contributors
+    const float d0 = r1.z - st.B0, d1 = r1.w - st.B1, d2 = bx.x - st.B2;
+    const float dal = st.T * fmaf(st.g0, d0, fmaf(st.g1, d1, st.g2 * d2));
+    st.B0 = fmaf(aB, d0, st.B0);
+    st.B1 = fmaf(aB, d1, st.B1);
+    st.B2 = fmaf(aB, d2, st.B2);
+    // dL/dalpha where alpha is not clamped (there it depends on its inputs)
+    const float df = contrib && raw <= kAlphaMax ? dal : 0.f;
+    const float dp = df * alpha;
     float v[9];
     // moments of dL/dpower; the projection adjoint applies the conic
     v[0] = dp * dx;
@@ -584,7 +606,7 @@ __device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, 
     v[2] = v[0] * dx;
     v[3] = v[0] * dy;
     v[4] = v[1] * dy;
-    v[5] = dop;
+    v[5] = df * ep;
     v[6] = st.g0 * wgt;
     v[7] = st.g1 * wgt;
     v[8] = st.g2 * wgt;
@@ -801,7 +823,8 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
     // nothing to composite: background everywhere
     return launch_background(v, bg, image, T_final, n_contrib, n_eval, s);
   }
-  hipLaunchKernelGGL(render_fwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kFwdBlocksPerCU)),
+  const auto kernel = n_eval ? render_fwd_kernel<true> : render_fwd_kernel<false>;
+  hipLaunchKernelGGL(kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kFwdBlocksPerCU)),
                      dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
                      bins.queue, v.dev, v.n, (int)v.n_tiles, bg, image, T_final, n_contrib, n_eval,
                      (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
