@@ -195,11 +195,13 @@ __device__ __forceinline__ Rec load_rec(const float* splat, uint32_t gid) {
   return o;
 }
 
-// Wave-private compacted batch: (u, v, A, B), (C, opacity, r, g), (b, tag as bits).
+// Wave-private compacted batch: (u, v, a, b), (c, opacity, r, g), (b, tag as bits); the
+// hits are followed by kIlp null records (opacity 0, so alpha 0), so that groups of kIlp
+// hits need no tail.
 struct WaveLds {
-  float4 r0[64];
-  float4 r1[64];
-  float2 bx[64];
+  float4 r0[64 + kIlp];
+  float4 r1[64 + kIlp];
+  float2 bx[64 + kIlp];
 };
 
 // Exchange of a long-tile round: per wave and lane, up to eight values.
@@ -217,8 +219,8 @@ __device__ __forceinline__ void fetch_batch(const float* splat, const uint32_t* 
   }
 }
 
-// Compacts the hits among one gathered batch into L in entry order (bx.y takes `tag`)
-// and returns the hit mask: bit l is the batch's entry l.
+// Compacts the hits among one gathered batch into L in entry order (bx.y takes `tag`),
+// pads them with null records and returns the hit mask: bit l is the batch's entry l.
 __device__ __forceinline__ uint64_t compact_hits(const Rec& cur, bool valid, float tag, const Item& it, WaveLds& L,
                                                  int lane) {
   const bool hit = valid && box_meets(cur.r2.y, cur.r2.z, it) && ellipse_meets(cur.r0, cur.r1, it);
@@ -228,6 +230,12 @@ __device__ __forceinline__ uint64_t compact_hits(const Rec& cur, bool valid, flo
     L.r0[pos] = cur.r0;
     L.r1[pos] = cur.r1;
     L.bx[pos] = make_float2(cur.r2.x, tag);
+  }
+  if (lane < kIlp) {
+    const int pos = __popcll(hm) + lane;
+    L.r0[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
+    L.r1[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
+    L.bx[pos] = make_float2(0.f, 0.f);
   }
   __builtin_amdgcn_wave_barrier();
   return hm;
@@ -292,27 +300,18 @@ __device__ __forceinline__ void fwd_apply(FwdState& st, float alpha, const float
 // sequence.  Returns true once every pixel has stopped.
 template <bool kStop>
 __device__ __forceinline__ bool fwd_exact_hits(const WaveLds& L, int nhit, float px, float py, FwdState& st) {
-  int i = 0;
-  for (; i + kIlp <= nhit; i += kIlp) {
-    float4 r0[kIlp], r1[kIlp];
+  for (int i = 0; i < nhit; i += kIlp) {
+    float4 r1[kIlp];
     float2 bx[kIlp];
     float alpha[kIlp];
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
-      r0[k] = L.r0[i + k];
       r1[k] = L.r1[i + k];
       bx[k] = L.bx[i + k];
+      alpha[k] = splat_alpha(L.r0[i + k], r1[k], px, py);
     }
 #pragma unroll
-    for (int k = 0; k < kIlp; ++k) alpha[k] = splat_alpha(r0[k], r1[k], px, py);
-#pragma unroll
     for (int k = 0; k < kIlp; ++k) fwd_apply<kStop>(st, alpha[k], r1[k], bx[k]);
-    if (__ballot(!st.done) == 0) return true;
-  }
-  for (; i < nhit; ++i) {
-    const float4 r0 = L.r0[i], r1 = L.r1[i];
-    const float2 bx = L.bx[i];
-    fwd_apply<kStop>(st, splat_alpha(r0, r1, px, py), r1, bx);
     if (__ballot(!st.done) == 0) return true;
   }
   return false;
@@ -341,10 +340,9 @@ __device__ __forceinline__ void fwd_local_hits(const WaveLds& L, int nhit, float
     float alpha[kIlp];
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
-      const int j = min(i + k, nhit - 1);
-      r1[k] = L.r1[j];
-      bx[k] = L.bx[j];
-      alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
+      r1[k] = L.r1[i + k];
+      bx[k] = L.bx[i + k];
+      alpha[k] = splat_alpha(L.r0[i + k], r1[k], px, py);
     }
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
@@ -651,21 +649,20 @@ __device__ __forceinline__ void bwd_local_hits(const WaveLds& L, uint64_t hm, in
     int off[kIlp];
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
-      const int j = min(i + k, nhit - 1);
-      r1[k] = L.r1[j];
-      bx[k] = L.bx[j];
-      alpha[k] = i + k < nhit ? splat_alpha(L.r0[j], r1[k], px, py) : 0.f;
+      r1[k] = L.r1[i + k];
+      bx[k] = L.bx[i + k];
+      alpha[k] = splat_alpha(L.r0[i + k], r1[k], px, py);  // 0 on the null records
       off[k] = rem ? __builtin_ctzll(rem) : 0;  // offset of hit i + k (unused past the last hit)
       rem &= rem - 1;
     }
 #pragma unroll
     for (int k = 0; k < kIlp; ++k) {
       const bool take = lo + off[k] < last && alpha[k] >= kAlphaMin;
-      const float wgt = take ? alpha[k] * P : 0.f;
+      const float wgt = (take ? alpha[k] : 0.f) * P;
       L0 = fmaf(r1[k].z, wgt, L0);
       L1 = fmaf(r1[k].w, wgt, L1);
       L2 = fmaf(bx[k].x, wgt, L2);
-      P = take ? P * (1.f - alpha[k]) : P;
+      P = take ? fmaf(-alpha[k], P, P) : P;
     }
   }
 }
