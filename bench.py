@@ -28,14 +28,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per Gaussian-pixel evaluation (FP32 operations of the method as built):
-#   forward:  offset 2, quadratic form 9, exp 2, opacity 1, clamp 1, threshold 1,
-#             transmittance 2, stop test 1, weight 1, colour 6            -> 26
-#   backward: the forward's alpha 16, T_i recovery 2, colour gradient 4, alpha gradient 9,
+# Algorithmic work per Gaussian-pixel evaluation (FP32 operations of the method as built,
+# an FMA counted as two, exp2 as one; the render record holds the conic pre-scaled to a
+# base-2 exponent):
+#   forward:  offset 2, exponent form 7, exp2 1, opacity 1, clamp 1, threshold 1,
+#             transmittance 2, stop test 1, weight 1, colour 6            -> 23
+#   backward: the forward's alpha 13, T_i recovery 2, colour gradient 4, alpha gradient 9,
 #             behind-colour update 6, opacity/power 2, the five moments of dL/dpower
-#             from which the centre and conic gradients follow 5         -> 44
-FLOP_FWD = 26
-FLOP_BWD = 44
+#             from which the centre and conic gradients follow 5         -> 41
+FLOP_FWD = 23
+FLOP_BWD = 41
 PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, scalar (non-packed) FP32
 PEAK_HBM_GBS = 8000.0
 
