@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--stage-iters", type=int, default=10)
     ap.add_argument("--config5", action="store_true",
                     help="also run config 5 (2 km path, 64 partitions x 8 views, mixed resolutions) once")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (built-in tile edge and compositing schedule)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -166,7 +168,7 @@ def main():
     import torch
 
     import synth
-    from paper_2607_21416_amd import binding
+    from paper_2607_21416_amd import binding, tuning
     from paper_2607_21416_amd.pipeline import Pipeline
 
     binding.load()
@@ -174,7 +176,14 @@ def main():
     torch.cuda.set_device(dev)
     log("bench: generating config 3 (50k anchors, 4 views 1226x370)")
     scene = synth.config("C3")
-    pipe = Pipeline(scene, device=dev)
+    if args.no_tune:
+        choice = dict(tuning.DEFAULT)
+    else:
+        log("bench: autotuning tile edge and compositing schedule (outside the timed region)")
+        choice = tuning.autotune(scene, device=dev, log=log)
+    log("bench: tile %d, long tiles >= 2^%d, grids %d/%d workgroups per CU" % (
+        choice["tile"], choice["long_log2"], choice["fwd_blocks_per_cu"], choice["bwd_blocks_per_cu"]))
+    pipe = Pipeline(scene, device=dev, tile=choice["tile"], tuning=tuning.schedule(choice))
     need = pipe.fit_capacity()
     pipe.status.zero_()
     log(f"bench: {pipe.vt.n_gauss} view-Gaussians, {need} pairs, capacity {pipe.capacity}")
@@ -198,12 +207,21 @@ def main():
     # per-stage times and evaluation counts (eager, outside the timed region)
     st = stage_times(torch, pipe, args.stage_iters)
     pipe.check_status()
-    pipe.count_evaluations()
-    pipe.render()
+    # evaluations are counted over 16x16 tile ranges (the workload's definition of the
+    # work, independent of the tile edge the tuner chose for the timed kernels)
+    ref = pipe if pipe.vt.tile == 16 else Pipeline(scene, device=dev)
+    if ref is not pipe:
+        ref.fit_capacity()
+        ref.status.zero_()
+        ref.forward()
+    ref.count_evaluations()
+    ref.render()
     torch.cuda.synchronize()
-    evals_fwd = int(pipe.n_eval.to(torch.int64).sum().item())
-    evals_bwd = int(pipe.n_contrib.to(torch.int64).sum().item())
-    pipe.count_evaluations(False)
+    evals_fwd = int(ref.n_eval.to(torch.int64).sum().item())
+    evals_bwd = int(ref.n_contrib.to(torch.int64).sum().item())
+    ref.count_evaluations(False)
+    ref.check_status()
+    del ref
     log("bench: stages " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
     dom = max(("render_fwd", "composite_bwd"), key=lambda k: st[k])
     flops = evals_fwd * FLOP_FWD if dom == "render_fwd" else evals_bwd * FLOP_BWD
@@ -229,18 +247,23 @@ def main():
         "config": {"workload": "config 3: 50k anchors x 10 offsets = 500k Gaussians, street corridor, "
                                "4 keyframe views 1226x370, L1 + 0.2 (1 - SSIM), fwd + bwd to anchors and MLPs",
                    "views_per_step": n_views, "view_gaussians": int(pipe.vt.n_gauss), "pairs": int(need),
-                   "launch": "hip graph" if graph else "eager"},
+                   "launch": "hip graph" if graph else "eager",
+                   "tile": choice["tile"], "schedule": tuning.schedule(choice),
+                   "autotuned": not args.no_tune},
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
         "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
                               "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
         "roofline": roofline,
     }
+    if "ms" in choice:
+        out["autotune_ms"] = choice["ms"]
     del graph
 
     if not args.no_batched:
         log("bench: config 4 (16 partitions x 4 views), batched vs plain")
         s4 = synth.config("C4")
-        bp = Pipeline(s4, device=dev)
+        c4 = dict(tuning.DEFAULT) if args.no_tune else tuning.autotune(s4, device=dev, log=log)
+        bp = Pipeline(s4, device=dev, tile=c4["tile"], tuning=tuning.schedule(c4))
         bp.fit_capacity()
         bp.status.zero_()
         for _ in range(2):
@@ -266,6 +289,7 @@ def main():
         out["batched_vs_plain"] = {"workload": "config 4: 16 partitions (log-uniform 20k-400k Gaussians) x 4 views "
                                                "1226x370, own MLPs",
                                    "views": bp.vt.n, "view_gaussians": int(bp.vt.n_gauss),
+                                   "batched_tile": c4["tile"], "batched_schedule": tuning.schedule(c4),
                                    "batched_ms": round(tb, 3), "plain_ms": round(tp, 3),
                                    "speedup": round(tp / tb, 3),
                                    "batched_iterations_per_s": round(bp.vt.n * 1000.0 / tb, 1),

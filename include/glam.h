@@ -7,7 +7,7 @@
  *                    one MLP set per spatial partition (Eq. 6)
  *   glam_project     3-D Gaussians -> projected 2-D Gaussians + footprint boxes
  *   glam_bin_sort    (tile, depth) pairs, device radix sort, per-tile ranges
- *   glam_render_fwd  front-to-back alpha compositing per 16x16 tile (Eq. 1)
+ *   glam_render_fwd  front-to-back alpha compositing per tile (Eq. 1)
  *   glam_loss        L1 + SSIM objective (Eq. 3) and its image gradient
  *   glam_render_bwd  reverse compositing, projection adjoint, decode adjoint
  *
@@ -102,7 +102,8 @@ typedef struct {
   const glam_view_info* host;   /* [n] host memory                                 */
   const glam_view_info* dev;    /* [n] device copy of the same bytes               */
   int32_t n;
-  int32_t tile_w, tile_h;       /* 16 x 16 (the only size built)                   */
+  int32_t tile_w, tile_h;       /* square tiles of 8, 16 or 32 pixels (binning
+                                   granularity; compositing works on 8x8 quadrants) */
   int32_t reserved;
   int64_t n_gauss;              /* total view-Gaussians                            */
   int64_t n_pix;                /* total pixels                                    */
@@ -112,7 +113,8 @@ typedef struct {
 /* Fills info[n_views] and the totals of *views (everything except the host/dev
    pointers).  Anchor mode: part_begin[n_parts+1] (host) delimits each partition's
    anchors, each view gets anchor_count*K Gaussians.  Plain mode (part_begin NULL):
-   every view gets plain_G Gaussians.  Pure host function. */
+   every view gets plain_G Gaussians.  tile_w == tile_h in {8, 16, 32}, else
+   GLAM_ERR_UNSUPPORTED.  Pure host function. */
 glam_status glam_views_build(const glam_camera* cams, int32_t n_views,
                              const int32_t* part_begin, int32_t n_parts, int32_t K,
                              int64_t plain_G, int32_t tile_w, int32_t tile_h,
@@ -167,6 +169,21 @@ typedef struct {
    128-byte lines + a line holding the exit count and the long-tile counter)). */
 #define GLAM_QUEUE_WORDS 1088
 
+/* Schedule of the compositing over a binning (all fields 0 = the built-in default;
+   the results never depend on them, only the time does):
+   long_log2         tiles whose range holds at least 2^long_log2 entries are listed
+                     first in the work order and composited by whole workgroups
+                     (default 10; 6..24)
+   fwd_blocks_per_cu persistent workgroups per CU of the forward compositing grid
+                     (default and maximum 5)
+   bwd_blocks_per_cu the same for the backward compositing grid (default and maximum 6) */
+typedef struct {
+  int32_t long_log2;
+  int32_t fwd_blocks_per_cu;
+  int32_t bwd_blocks_per_cu;
+  int32_t reserved;
+} glam_tuning;
+
 /* Sorted (tile, Gaussian) pairs, per-tile ranges and the compositing work order. */
 typedef struct {
   uint64_t* keys;   /* [capacity] sorted keys: tile << depth_bits | depth key        */
@@ -176,13 +193,14 @@ typedef struct {
   int32_t* status;  /* [8] device: [0] sticky status, [1] pair count (low word),
                        [2..3] required capacity (int64), [4] depth key bits,
                        [5] tile key bits, [6] radix passes, [7] long tiles (range
-                       of 1024 entries or more, listed first in order, composited
-                       by whole workgroups); caller zeroes [0] once                 */
+                       of 2^tuning.long_log2 entries or more, listed first in order,
+                       composited by whole workgroups); caller zeroes [0] once      */
   uint32_t* order;  /* [n_tiles] tiles by decreasing range length (power-of-two
                        classes), the order the compositing queue hands them out       */
   uint32_t* queue;  /* [GLAM_QUEUE_WORDS] device work-queue counters of the
                        compositing kernels; caller zeroes them once, every launch
                        leaves them zeroed                                             */
+  glam_tuning tuning; /* host: the compositing schedule (rejected when out of range)  */
 } glam_bins;
 
 /* Workspace bytes glam_bin_sort needs for this view table and pair capacity. */

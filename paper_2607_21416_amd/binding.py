@@ -66,9 +66,14 @@ class Projected(C.Structure):
                 ("ntiles", C.c_void_p), ("splat", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("long_log2", C.c_int32), ("fwd_blocks_per_cu", C.c_int32), ("bwd_blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class Bins(C.Structure):
     _fields_ = [("keys", C.c_void_p), ("vals", C.c_void_p), ("ranges", C.c_void_p), ("capacity", C.c_int64),
-                ("status", C.c_void_p), ("order", C.c_void_p), ("queue", C.c_void_p)]
+                ("status", C.c_void_p), ("order", C.c_void_p), ("queue", C.c_void_p), ("tuning", Tuning)]
 
 
 class Grads(C.Structure):

@@ -21,7 +21,7 @@ bool ok_ptr(const void* p) { return p != nullptr && aligned16(p); }
 
 bool views_ok(const glam_views* v) {
   if (!v || !v->host || !v->dev || v->n <= 0) return false;
-  if (v->tile_w != glam::kTileEdge() || v->tile_h != glam::kTileEdge()) return false;
+  if (v->tile_w != v->tile_h || !glam::tile_edge_supported(v->tile_w)) return false;
   if (v->n_gauss < 0 || v->n_pix <= 0 || v->n_tiles <= 0) return false;
   // totals must agree with the host table
   long long g = 0, p = 0, t = 0;
@@ -69,7 +69,7 @@ bool proj_ok(const glam_projected* p) {
 
 bool bins_ok(const glam_bins* b) {
   return b && ok_ptr(b->keys) && ok_ptr(b->vals) && ok_ptr(b->ranges) && ok_ptr(b->status) && ok_ptr(b->order) &&
-         ok_ptr(b->queue) && b->capacity > 0 && b->capacity < (1ll << 32);
+         ok_ptr(b->queue) && b->capacity > 0 && b->capacity < (1ll << 32) && glam::tuning_ok(b->tuning);
 }
 
 int max_partition(const glam_views* v) {
@@ -104,7 +104,7 @@ glam_status glam_views_build(const glam_camera* cams, int32_t n_views, const int
                              int32_t K, int64_t plain_G, int32_t tile_w, int32_t tile_h, glam_view_info* info,
                              glam_views* views) {
   if (!cams || !info || !views || n_views <= 0) return GLAM_ERR_INVALID_ARG;
-  if (tile_w != glam::kTileEdge() || tile_h != glam::kTileEdge()) return GLAM_ERR_UNSUPPORTED;
+  if (tile_w != tile_h || !glam::tile_edge_supported(tile_w)) return GLAM_ERR_UNSUPPORTED;
   if (part_begin && (n_parts <= 0 || K <= 0)) return GLAM_ERR_INVALID_ARG;
   if (!part_begin && plain_G <= 0) return GLAM_ERR_INVALID_ARG;
   long long g = 0, p = 0, t = 0;

@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
 // in the prefix, so every pair costs the same and the stores are coalesced.
 __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* ntiles, const float* splat,
                                                                  long long n, const glam_view_info* views,
-                                                                 int n_views, const uint32_t* psum,
+                                                                 int n_views, int tl, const uint32_t* psum,
                                                                  const Plan* plan, uint64_t* keys_out,
                                                                  uint32_t* vals_out, uint64_t* keys_alt,
                                                                  uint32_t* vals_alt) {
@@ -205,8 +205,8 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
       while (vi + 1 < n_views && views[vi + 1].g_begin <= g) ++vi;
       const glam_view_info& vw = views[vi];
       const uint32_t bx = __float_as_uint(rec[i].y), by = __float_as_uint(rec[i].z);
-      const int tx0 = (int)(bx & 0xffffu) / kTile, tx1 = (int)(bx >> 16) / kTile;
-      const int ty0 = (int)(by & 0xffffu) / kTile;
+      const int tx0 = (int)(bx & 0xffffu) >> tl, tx1 = (int)(bx >> 16) >> tl;  // tiles of edge 2^tl
+      const int ty0 = (int)(by & 0xffffu) >> tl;
       tile0 = (uint32_t)(vw.tile_begin + (long long)ty0 * vw.tiles_x + tx0);
       dim = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vw.tiles_x << 16);
       dkey = __float_as_uint(rec[i].w) - kDepthBase;
@@ -438,9 +438,9 @@ __global__ void __launch_bounds__(256) lpt_count_kernel(const uint32_t* ranges, 
 }
 
 // Also records in status[7] the number of long tiles (range length at least
-// 2^kLongTileLog2), which are exactly the first classes of the order.
+// 2^long_log2), which are exactly the first classes of the order.
 __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t* ranges, long long n_tiles, uint32_t* lpt,
-                                                          uint32_t* order, int32_t* status) {
+                                                          int long_log2, uint32_t* order, int32_t* status) {
   __shared__ uint32_t base[kLptBuckets], h[kLptBuckets], blk[kLptBuckets];
   if (threadIdx.x < kLptBuckets) h[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t* ranges
     for (int b = 0; b < kLptBuckets; ++b) {
       base[b] = run;
       run += lpt[b];
-      if (b == kLptBuckets - 1 - kLongTileLog2 && blockIdx.x == 0) status[7] = (int32_t)run;
+      if (b == kLptBuckets - 1 - long_log2 && blockIdx.x == 0) status[7] = (int32_t)run;
     }
   }
   __syncthreads();
@@ -504,7 +504,7 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                      (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status,
                      bins.ranges, lpt);
   hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
-                     n, v.dev, v.n, psum, plan, bins.keys, bins.vals, keys_alt, vals_alt);
+                     n, v.dev, v.n, tile_log2(v.tile_w), psum, plan, bins.keys, bins.vals, keys_alt, vals_alt);
   // host bound on the passes: tile bits are known, depth keys take at most 31 bits
   const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
   const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;
@@ -520,8 +520,9 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                        bins.keys, bins.ranges, (long long)v.n_tiles);
   const unsigned tb = (unsigned)((v.n_tiles + 255) / 256);
   hipLaunchKernelGGL(lpt_count_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt);
+  const int long_log2 = bins.tuning.long_log2 > 0 ? bins.tuning.long_log2 : kDefaultLongLog2;
   hipLaunchKernelGGL(lpt_scatter_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt,
-                     bins.order, bins.status);
+                     long_log2, bins.order, bins.status);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

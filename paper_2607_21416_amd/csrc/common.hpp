@@ -8,18 +8,12 @@
 
 namespace glam {
 
-constexpr int kTile = 16;             // tile edge in pixels
-constexpr int kTilePix = kTile * kTile;
 constexpr float kZNear = 0.2f;        // cull depth
 constexpr float kDilation = 0.3f;     // px^2 added to the 2-D covariance diagonal
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr int kSplatWords = 12;       // packed render record
-// Tiles whose depth-sorted range holds at least 2^kLongTileLog2 entries are composited
-// by whole workgroups (the range split across the waves); the bin sort lists them
-// first in its work order and counts them.
-constexpr int kLongTileLog2 = 10;
 
 // Index of the view whose [begin, next begin) holds `i`; views sorted by the field.
 template <class Get>

@@ -7,7 +7,19 @@
 
 namespace glam {
 
-constexpr int kTileEdge() { return 16; }
+// Tile edges the binning and compositing support (square tiles, multiples of the 8x8
+// compositing quadrant).
+inline bool tile_edge_supported(int e) { return e == 8 || e == 16 || e == 32; }
+inline int tile_log2(int e) { return e == 8 ? 3 : (e == 16 ? 4 : 5); }
+
+// Compositing schedule defaults and limits (glam_tuning).
+constexpr int kDefaultLongLog2 = 10;
+constexpr int kMaxFwdBlocksPerCU = 5, kMaxBwdBlocksPerCU = 6;
+inline bool tuning_ok(const glam_tuning& t) {
+  return (t.long_log2 == 0 || (t.long_log2 >= 6 && t.long_log2 <= 24)) && t.fwd_blocks_per_cu >= 0 &&
+         t.fwd_blocks_per_cu <= kMaxFwdBlocksPerCU && t.bwd_blocks_per_cu >= 0 &&
+         t.bwd_blocks_per_cu <= kMaxBwdBlocksPerCU;
+}
 
 // Compute units of the current device (256 if the runtime cannot say).
 int cu_count();

@@ -106,7 +106,7 @@ __device__ __forceinline__ void load_gauss(const glam_gaussians& g, long long i,
 }
 
 __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, const glam_view_info* views,
-                                                      int n_views, long long n_total, int plain,
+                                                      int n_views, long long n_total, int plain, int tl,
                                                       glam_projected out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_total) return;
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, cons
   } else {
     out.conic[i] = 0.f; out.conic[n + i] = 0.f; out.conic[2 * n + i] = 0.f;
   }
-  out.ntiles[i] = vis ? (x1 / kTile - x0 / kTile + 1) * (y1 / kTile - y0 / kTile + 1) : 0;
+  // tiles of edge 2^tl touched by the pixel box
+  out.ntiles[i] = vis ? ((x1 >> tl) - (x0 >> tl) + 1) * ((y1 >> tl) - (y0 >> tl) + 1) : 0;
   float4* rec = reinterpret_cast<float4*>(out.splat + i * kSplatWords);
   if (vis) {
     const uint32_t bx = (uint32_t)x0 | ((uint32_t)x1 << 16);
@@ -308,7 +309,8 @@ glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool pl
   const long long n = v.n_gauss;
   if (n == 0) return GLAM_OK;
   const unsigned blocks = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, s, g, v.dev, v.n, n, plain ? 1 : 0, out);
+  hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, s, g, v.dev, v.n, n, plain ? 1 : 0,
+                     tile_log2(v.tile_w), out);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

@@ -1,9 +1,10 @@
 // Front-to-back alpha compositing (Eq. 1) and its reverse-order adjoint.
 //
-// Work decomposition.  Gaussians are binned to 16x16 tiles; each tile is split into
-// four 8x8 quadrants, and one wave64 composites one quadrant (one pixel per lane).
-// The (tile, quadrant) items are pulled from a device work queue by a persistent grid
-// (a few workgroups per CU), in longest-range-first order.
+// Work decomposition.  Gaussians are binned to square tiles (8, 16 or 32 pixels, 16 by
+// default); each tile is split into 8x8 quadrants, and one wave64 composites one
+// quadrant (one pixel per lane).  The (tile, quadrant) items are pulled from a device
+// work queue by a persistent grid (a few workgroups per CU), in longest-range-first
+// order.
 //
 // Per item, a wave walks its tile's depth-sorted range in batches of 64: lane l
 // gathers the 48-byte record of entry b0+l from HBM (the next batch is prefetched into
@@ -45,8 +46,10 @@ namespace {
 
 constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
-constexpr int kFwdBlocksPerCU = 5;  // persistent workgroups per CU (register-limited occupancy)
-constexpr int kBwdBlocksPerCU = 6;
+// persistent workgroups per CU at most (the register-limited occupancy the kernels are
+// compiled for); the schedule may ask for fewer
+constexpr int kFwdBlocksPerCU = kMaxFwdBlocksPerCU;
+constexpr int kBwdBlocksPerCU = kMaxBwdBlocksPerCU;
 constexpr int kChunk = 64;       // entries per wave and round of a long tile
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
@@ -78,12 +81,16 @@ struct Item {
   long long pix;           // this lane's pixel in the batched per-pixel arrays
 };
 
-__device__ __forceinline__ Item make_item(const glam_view_info* views, int n_views, int tile, int quad, int lane) {
+// Item of quadrant `quad` of `tile` (tiles of edge 2^tl hold 2^(tl-3) x 2^(tl-3) quadrants).
+__device__ __forceinline__ Item make_item(const glam_view_info* views, int n_views, int tile, int quad, int lane,
+                                          int tl) {
   Item it;
   const int v = find_view(views, n_views, tile, [](const glam_view_info& w) { return (long long)w.tile_begin; });
   const glam_view_info& vw = views[v];
   const int lt = tile - vw.tile_begin;
-  const int qx = (lt % vw.tiles_x) * kTile + (quad & 1) * 8, qy = (lt / vw.tiles_x) * kTile + (quad >> 1) * 8;
+  const int qpr = tl - 3;  // log2 of the quadrants per tile row
+  const int qx = ((lt % vw.tiles_x) << tl) + (quad & ((1 << qpr) - 1)) * 8;
+  const int qy = ((lt / vw.tiles_x) << tl) + (quad >> qpr) * 8;
   it.W = vw.cam.width;
   it.H = vw.cam.height;
   it.x = qx + (lane & 7);
@@ -139,9 +146,10 @@ __device__ __forceinline__ bool ellipse_meets(const float4& r0, const float4& r1
 // serialise every grab; the longest-first tile list (after the long tiles) is dealt
 // round-robin over kQueues counters (one 128-byte line each), and workgroup b pulls
 // from counter b % kQueues.  Workgroups are dealt to the 8 XCDs round-robin, so all
-// workgroups of one counter sit on one XCD; the four quadrant items of a tile are
-// consecutive grabs of one counter, so the tile's records are fetched into that XCD's
-// L2 once and read there four times.  An item is 4 * (tile rank) + quadrant.
+// workgroups of one counter sit on one XCD; the quadrant items of a tile (2^ql of them:
+// 1, 4 or 16 for tiles of edge 8, 16 or 32) are consecutive grabs of one counter, so the
+// tile's records are fetched into that XCD's L2 once and read there 2^ql times.  An
+// item is 2^ql * (tile rank) + quadrant.
 // Words [0, kQueues*32) of a queue region hold the counters, word kQueues*32 the exit
 // count and word kQueues*32 + 1 the counter of the long-tile items (taken by whole
 // workgroups).  The last wave to leave resets all of them for the next launch.
@@ -150,13 +158,13 @@ constexpr int kQueueWords = kQueues * 32 + 32;
 constexpr int kExitWord = kQueues * 32, kLongWord = kQueues * 32 + 1;
 static_assert(2 * kQueueWords == GLAM_QUEUE_WORDS, "queue layout");
 
-__device__ __forceinline__ uint32_t next_item(uint32_t* q, int lane) {
+__device__ __forceinline__ uint32_t next_item(uint32_t* q, int lane, int ql) {
   const uint32_t nq = min((uint32_t)kQueues, gridDim.x);  // every counter in use has workgroups
   const uint32_t qi = blockIdx.x % nq;
   uint32_t v = 0;
   if (lane == 0) v = atomicAdd(&q[32 * qi], 1u);
   v = __builtin_amdgcn_readfirstlane(v);
-  return ((v >> 2) * nq + qi) * 4u + (v & 3u);
+  return (((v >> ql) * nq + qi) << ql) | (v & ((1u << ql) - 1u));
 }
 
 // Next long-tile item for the whole workgroup (every thread must call it).
@@ -454,9 +462,9 @@ template <bool kCount>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdBlocksPerCU)))
 render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
-                  uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, const float* bg,
-                  float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval, uint32_t capacity,
-                  uint32_t n_gauss) {
+                  uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, int tl,
+                  const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
+                  uint32_t capacity, uint32_t n_gauss) {
   __shared__ WaveLds lds[kWaves];
   __shared__ RoundLds round;
   __shared__ uint32_t s_item;
@@ -464,21 +472,22 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
   WaveLds& L = lds[w];
   const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
   const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
+  const int ql = 2 * (tl - 3);  // log2 of the quadrants per tile
   // long tiles first, one quadrant per workgroup
   __builtin_amdgcn_s_setprio(2);
-  for (uint32_t li = next_long_item(queue, &s_item); li < 4u * n_long; li = next_long_item(queue, &s_item)) {
-    const int tile = (int)min(order[li >> 2], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(li & 3u), lane);
+  for (uint32_t li = next_long_item(queue, &s_item); li < (n_long << ql); li = next_long_item(queue, &s_item)) {
+    const int tile = (int)min(order[li >> ql], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(li & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     fwd_long<kCount>(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
   }
   __builtin_amdgcn_s_setprio(0);
   // the other tiles, one quadrant per wave
-  const uint32_t n_items = 4u * ((uint32_t)n_tiles - n_long);
-  for (uint32_t item = next_item(queue, lane); item < n_items; item = next_item(queue, lane)) {
-    const int tile = (int)min(order[n_long + (item >> 2)], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
+  const uint32_t n_items = ((uint32_t)n_tiles - n_long) << ql;
+  for (uint32_t item = next_item(queue, lane, ql); item < n_items; item = next_item(queue, lane, ql)) {
+    const int tile = (int)min(order[n_long + (item >> ql)], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(item & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     FwdState st{1.f, 0.f, 0.f, 0.f, 0, (int)(e - s), !it.inside};
@@ -737,8 +746,8 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBlocksPerCU))) composite_bwd_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
-    int n_views, int n_tiles, const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
-    float* g2d, uint32_t capacity, uint32_t n_gauss) {
+    int n_views, int n_tiles, int tl, const float* bg, const float* T_final, const int32_t* n_contrib,
+    const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss) {
   __shared__ WaveLds lds[kWaves];
   __shared__ RoundLds round;
   __shared__ uint32_t s_item;
@@ -748,20 +757,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
   const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
   const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
   uint32_t* q = queue + kQueueWords;
+  const int ql = 2 * (tl - 3);  // log2 of the quadrants per tile
   __builtin_amdgcn_s_setprio(2);
-  for (uint32_t li = next_long_item(q, &s_item); li < 4u * n_long; li = next_long_item(q, &s_item)) {
-    const int tile = (int)min(order[li >> 2], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(li & 3u), lane);
+  for (uint32_t li = next_long_item(q, &s_item); li < (n_long << ql); li = next_long_item(q, &s_item)) {
+    const int tile = (int)min(order[li >> ql], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(li & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     bwd_long(splat, vals, s, n_gauss, it, L, round, w, lane, comp,
              bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d);
   }
   __builtin_amdgcn_s_setprio(0);
-  const uint32_t n_items = 4u * ((uint32_t)n_tiles - n_long);
-  for (uint32_t item = next_item(q, lane); item < n_items; item = next_item(q, lane)) {
-    const int tile = (int)min(order[n_long + (item >> 2)], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(item & 3u), lane);
+  const uint32_t n_items = ((uint32_t)n_tiles - n_long) << ql;
+  for (uint32_t item = next_item(q, lane, ql); item < n_items; item = next_item(q, lane, ql)) {
+    const int tile = (int)min(order[n_long + (item >> ql)], (uint32_t)n_tiles - 1);
+    const Item it = make_item(views, n_views, tile, (int)(item & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     BwdState st = bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage);
@@ -784,9 +794,17 @@ __global__ void background_kernel(const glam_view_info* views, int n_views, long
   if (n_eval) n_eval[i] = 0;
 }
 
-__global__ void zero_kernel(float* p, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.f;
+// Zero fill with 16-byte stores (the head up to 16-byte alignment and the tail scalar).
+__global__ void __launch_bounds__(256) zero_kernel(float* p, long long n) {
+  const long long head = min(n, (long long)((16 - ((uintptr_t)p & 15)) & 15) / 4);
+  const long long n4 = (n - head) / 4;
+  float4* q = reinterpret_cast<float4*>(p + head);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long i = i0; i < n4; i += stride) q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i0 < head) p[i0] = 0.f;
+  const long long t = head + 4 * n4 + i0;
+  if (t < n) p[t] = 0.f;
 }
 
 glam_status launch_background(const glam_views& v, const float* bg, float* image, float* T_final,
@@ -820,11 +838,14 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
     // nothing to composite: background everywhere
     return launch_background(v, bg, image, T_final, n_contrib, n_eval, s);
   }
+  const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
+  if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
+  const int bpc = bins.tuning.fwd_blocks_per_cu > 0 ? bins.tuning.fwd_blocks_per_cu : kFwdBlocksPerCU;
   const auto kernel = n_eval ? render_fwd_kernel<true> : render_fwd_kernel<false>;
-  hipLaunchKernelGGL(kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kFwdBlocksPerCU)),
-                     dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
-                     bins.queue, v.dev, v.n, (int)v.n_tiles, bg, image, T_final, n_contrib, n_eval,
-                     (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
+  hipLaunchKernelGGL(kernel, dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)), dim3(64 * kWaves), 0, s,
+                     proj.splat, bins.vals, bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n,
+                     (int)v.n_tiles, tl, bg, image, T_final, n_contrib, n_eval, (uint32_t)bins.capacity,
+                     (uint32_t)v.n_gauss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -832,11 +853,16 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
                                  const float* bg, const float* T_final, const int32_t* n_contrib,
                                  const float* dimage, float* g2d, hipStream_t s) {
   const long long n = 9 * v.n_gauss;
-  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g2d, n);
+  if (n > 0)
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
+                       g2d, n);
+  const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
+  if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
+  const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : kBwdBlocksPerCU;
   if (v.n_tiles > 0 && v.n_gauss > 0)
-    hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(4 * v.n_tiles, kWaves, kBwdBlocksPerCU)),
+    hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)),
                        dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
-                       bins.queue, v.dev, v.n, (int)v.n_tiles, bg, T_final, n_contrib, dimage, g2d,
+                       bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, T_final, n_contrib, dimage, g2d,
                        (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }

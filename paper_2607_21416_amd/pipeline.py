@@ -15,7 +15,7 @@ import torch
 
 from . import binding as B
 
-TILE = 16
+TILE = 16  # default tile edge (8, 16 and 32 are built)
 
 
 def camera_array(cams) -> "C.Array":
@@ -40,17 +40,18 @@ def _f32(a, dev):
 class ViewTable:
     """Host and device copies of the per-view offsets (glam_views_build)."""
 
-    def __init__(self, cams, device, part_begin=None, K=0, plain_G=0):
+    def __init__(self, cams, device, part_begin=None, K=0, plain_G=0, tile=TILE):
         self.cams = camera_array(cams)
+        self.tile = int(tile)
         n = len(cams)
         self.info = (B.ViewInfo * n)()
         self.views = B.Views()
         if part_begin is not None:
             pb = np.ascontiguousarray(part_begin, np.int32)
             self._pb = pb
-            B.glam_views_build(self.cams, n, pb, len(pb) - 1, K, 0, TILE, TILE, self.info, self.views)
+            B.glam_views_build(self.cams, n, pb, len(pb) - 1, K, 0, self.tile, self.tile, self.info, self.views)
         else:
-            B.glam_views_build(self.cams, n, None, 0, 0, plain_G, TILE, TILE, self.info, self.views)
+            B.glam_views_build(self.cams, n, None, 0, 0, plain_G, self.tile, self.tile, self.info, self.views)
         raw = np.frombuffer(bytes(self.info), dtype=np.uint8).copy()
         self.dev_bytes = torch.from_numpy(raw).to(device)
         self.views.host = C.cast(self.info, C.c_void_p)
@@ -78,10 +79,15 @@ class Pipeline:
     """Device buffers and launch sequence of one scene (see the synth module for the
     scene dictionaries)."""
 
-    def __init__(self, scene: dict, device="cuda", capacity: int | None = None, bg=(0.0, 0.0, 0.0)):
+    def __init__(self, scene: dict, device="cuda", capacity: int | None = None, bg=(0.0, 0.0, 0.0),
+                 tile: int = TILE, tuning: dict | None = None):
+        """tile: binning tile edge (8, 16 or 32); tuning: the compositing schedule
+        (long_log2, fwd_blocks_per_cu, bwd_blocks_per_cu; missing or 0 = default)."""
         self.device = torch.device(device)
         dev = self.device
         self.scene = scene
+        self.tuning = B.Tuning(*(int((tuning or {}).get(k, 0)) for k in ("long_log2", "fwd_blocks_per_cu",
+                                                                          "bwd_blocks_per_cu")), 0)
         self.plain = scene["kind"] == "plain"
         self.flags = B.GLAM_PLAIN if self.plain else 0
         if not self.plain and scene.get("opacity_mode", "tanh") == "sigmoid":
@@ -90,7 +96,7 @@ class Pipeline:
         cams = scene["cams"]
         if self.plain:
             G = scene["mean"].shape[1]
-            self.vt = ViewTable(cams, dev, plain_G=G)
+            self.vt = ViewTable(cams, dev, plain_G=G, tile=tile)
             self.params = {k: _f32(scene[k], dev) for k in ("mean", "log_scale", "quat", "logit", "rgb")}
             self.gauss = B.Gaussians(self.params["mean"].data_ptr(), self.params["log_scale"].data_ptr(),
                                      self.params["quat"].data_ptr(), self.params["logit"].data_ptr(),
@@ -98,7 +104,7 @@ class Pipeline:
             self.n_parts = 0
         else:
             F, K = scene["F"], scene["K"]
-            self.vt = ViewTable(cams, dev, part_begin=scene["part_begin"], K=K)
+            self.vt = ViewTable(cams, dev, part_begin=scene["part_begin"], K=K, tile=tile)
             self.params = {k: _f32(scene[k], dev) for k in ("pos", "feat", "log_scale", "offs", "mlp")}
             A = scene["feat"].shape[0]
             self.anchors = B.Anchors(self.params["pos"].data_ptr(), self.params["feat"].data_ptr(),
@@ -163,9 +169,15 @@ class Pipeline:
         self.order = torch.empty(self.vt.n_tiles, device=dev, dtype=torch.int32)
         self.queue = torch.zeros(B.GLAM_QUEUE_WORDS, device=dev, dtype=torch.int32)
         self.bins = B.Bins(self.keys.data_ptr(), self.vals.data_ptr(), self.ranges.data_ptr(), self.capacity,
-                           self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr())
+                           self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr(), self.tuning)
         nb = B.glam_bin_sort_workspace_bytes(self.vt.views, self.capacity)
         self.ws_sort = torch.empty(nb, device=dev, dtype=torch.uint8)
+
+    def set_tuning(self, tuning: dict | None):
+        """Changes the compositing schedule (takes effect from the next bin_sort)."""
+        self.tuning = B.Tuning(*(int((tuning or {}).get(k, 0)) for k in ("long_log2", "fwd_blocks_per_cu",
+                                                                          "bwd_blocks_per_cu")), 0)
+        self.bins.tuning = self.tuning
 
     def stream(self):
         return torch.cuda.current_stream(self.device)

@@ -13,8 +13,8 @@ AMB_VALUE = oracle.AMB_ALPHA | oracle.AMB_T | oracle.AMB_DEPTH
 AMB_STAGE = oracle.AMB_ALPHA | oracle.AMB_T
 
 
-def run(scene, steps=1):
-    pipe = Pipeline(scene, device="cuda")
+def run(scene, steps=1, tile=16, tuning=None):
+    pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning)
     pipe.count_evaluations()
     pipe.fit_capacity()
     pipe.status.zero_()

@@ -36,14 +36,42 @@ def test_param_count_matches_oracle():
     assert B.glam_mlp_param_count(16, 4, 32) == oracle.mlp_param_count(16, 4, 32)
 
 
-def _build(cams, part_begin=None, K=0, plain_G=0):
+def _build(cams, part_begin=None, K=0, plain_G=0, tile=(16, 16)):
     arr = camera_array(cams)
     info = (B.ViewInfo * len(cams))()
     views = B.Views()
     pb = None if part_begin is None else np.ascontiguousarray(part_begin, np.int32)
     st = B.load().glam_views_build(B.ref(arr), len(cams), B.ref(pb), 0 if pb is None else len(pb) - 1, K, plain_G,
-                                   16, 16, B.ref(info), B.ref(views))
+                                   tile[0], tile[1], B.ref(info), B.ref(views))
     return st, info, views
+
+
+def test_views_build_tile_edges():
+    cams = [synth.camera(np.eye(3), np.zeros(3), 50, 50, 10, 10, 70, 45)]
+    for t, grid in ((8, (9, 6)), (16, (5, 3)), (32, (3, 2))):
+        st, info, views = _build(cams, None, 0, 10, (t, t))
+        assert st == B.GLAM_OK and (info[0].tiles_x, info[0].tiles_y) == grid and views.n_tiles == grid[0] * grid[1]
+        assert views.tile_w == views.tile_h == t
+    for t in ((12, 12), (16, 32), (64, 64), (4, 4)):
+        assert _build(cams, None, 0, 10, t)[0] == B.GLAM_ERR_UNSUPPORTED
+
+
+def test_schedule_out_of_range_is_rejected():
+    lib = B.load()
+    s = synth.plain_scene(1, 10, 32, 32)
+    st, info, views = _build(s["cams"], None, 0, 10)
+    fake = 0x100000
+    views.host = C.cast(info, C.c_void_p)
+    views.dev = fake
+    proj = B.Projected(fake, fake, fake, fake, fake, fake)
+    need = lib.glam_bin_sort_workspace_bytes(B.ref(views), 1000)
+    for bad in (B.Tuning(5, 0, 0, 0), B.Tuning(25, 0, 0, 0), B.Tuning(0, 6, 0, 0), B.Tuning(0, 0, 7, 0),
+                B.Tuning(0, -1, 0, 0)):
+        bins = B.Bins(fake, fake, fake, 1000, fake, fake, fake, bad)
+        assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins), C.c_void_p(fake), need,
+                                 None) == B.GLAM_ERR_INVALID_ARG
+        assert lib.glam_render_fwd(B.ref(proj), B.ref(bins), B.ref(views), None, C.c_void_p(fake),
+                                   C.c_void_p(fake), C.c_void_p(fake), None, None) == B.GLAM_ERR_INVALID_ARG
 
 
 def test_views_build_offsets():
