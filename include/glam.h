@@ -10,6 +10,8 @@
  *   glam_render_fwd  front-to-back alpha compositing per tile (Eq. 1)
  *   glam_loss        L1 + SSIM objective (Eq. 3) and its image gradient
  *   glam_render_bwd  reverse compositing, projection adjoint, decode adjoint
+ *   glam_adam_step   the optimiser step of the mapping iteration (fused Adam)
+ *   glam_sample_keyframes  which keyframes an iteration renders (host)
  *
  * Conventions shared by every call:
  *  - Array arguments are DEVICE pointers owned by the caller; the library never
@@ -307,6 +309,49 @@ glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins,
                             const float* mlp, int32_t n_parts, uint32_t flags,
                             glam_grads* grads, void* workspace, size_t workspace_bytes,
                             hipStream_t stream);
+
+/* --- optimiser step ------------------------------------------------------------- */
+
+/* One parameter group of the Adam update: param, grad, m and v are [n] device arrays
+   (16-byte aligned; the caller zeroes m and v before step 1).  The learning rate is
+   periodic in the element index: element i takes lr[k] for the segment k of (i mod
+   period) in [seg_end[k-1], seg_end[k]) (seg_end[-1] = 0; 1 <= n_seg <= 4, seg_end
+   increasing, seg_end[n_seg-1] == period).  A plain array is period = n, one segment;
+   the packed MLP sets of all partitions are period = the parameters of one set, one
+   segment per MLP. */
+typedef struct {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t n;
+  int32_t period;
+  int32_t n_seg;
+  int32_t seg_end[4];
+  float lr[4];
+} glam_adam_group;
+
+#define GLAM_ADAM_MAX_GROUPS 16
+
+/* The mapping iteration's optimiser step (the update that follows the backward):
+   Adam (Kingma & Ba) over all groups in one launch, step t >= 1 (bias corrections
+   1 - beta^t), per element
+     m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+     param -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+   1 <= n_groups <= GLAM_ADAM_MAX_GROUPS; 0 <= beta1, beta2 < 1; eps > 0; learning
+   rates finite and >= 0; otherwise GLAM_ERR_INVALID_ARG before any launch. */
+glam_status glam_adam_step(const glam_adam_group* groups, int32_t n_groups, int32_t step,
+                           float beta1, float beta2, float eps, hipStream_t stream);
+
+/* Keyframe sampler of a mapping iteration: count keyframe indices drawn from n_keyframes
+   (0 = oldest): with probability p_recent uniformly among the k_recent most recent,
+   otherwise uniformly among the older ones (all keyframes are recent when n_keyframes
+   <= k_recent).  Draws come from Philox4x32-10 (Salmon et al., SC 2011) keyed by seed,
+   at counters counter, counter + 1, ... (one counter per draw: the first word decides
+   recent or old, the second picks the keyframe), so a draw is reproducible from
+   (seed, counter).  out: [count] host.  Pure host function. */
+glam_status glam_sample_keyframes(int32_t n_keyframes, int32_t k_recent, float p_recent,
+                                  int32_t count, uint64_t seed, uint64_t counter, int32_t* out);
 
 #ifdef __cplusplus
 }

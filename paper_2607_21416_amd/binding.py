@@ -23,8 +23,9 @@ EXPORTS = [
     "glam_status_string", "glam_mlp_param_count", "glam_views_build", "glam_bin_sort_workspace_bytes",
     "glam_decode", "glam_project", "glam_bin_sort", "glam_render_fwd", "glam_loss_workspace_bytes", "glam_loss",
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
-    "glam_render_bwd",
+    "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes",
 ]
+GLAM_ADAM_MAX_GROUPS = 16
 
 
 class GlamError(RuntimeError):
@@ -81,6 +82,12 @@ class Grads(C.Structure):
                 ("dlog_scale", C.c_void_p), ("dmlp", C.c_void_p)]
 
 
+class AdamGroup(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("period", C.c_int32), ("n_seg", C.c_int32), ("seg_end", C.c_int32 * 4),
+                ("lr", C.c_float * 4)]
+
+
 _lib = None
 
 
@@ -110,6 +117,8 @@ def load():
         "glam_decode_bwd_workspace_bytes": (SZ, [P, P, I32]),
         "glam_decode_bwd": (I32, [P, P, I32, P, U32, P, P, P, P, P, P, SZ, P]),
         "glam_render_bwd": (I32, [P, P, P, P, P, P, P, P, P, P, I32, U32, P, P, SZ, P]),
+        "glam_adam_step": (I32, [P, I32, I32, F32, F32, F32, P]),
+        "glam_sample_keyframes": (I32, [I32, I32, F32, I32, C.c_uint64, C.c_uint64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -226,3 +235,17 @@ def glam_render_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, gauss, an
                   load().glam_render_bwd(ref(proj), ref(bins), ref(views), ref(bg), ref(T_final), ref(n_contrib),
                                          ref(dimage), ref(gauss), ref(anchors), ref(mlp), n_parts, flags, ref(grads),
                                          ref(ws), ws_bytes, _stream(stream)))
+
+
+def glam_adam_step(groups, n_groups, step, beta1, beta2, eps, stream):
+    return _check("glam_adam_step", load().glam_adam_step(ref(groups), n_groups, step, float(beta1), float(beta2),
+                                                          float(eps), _stream(stream)))
+
+
+def glam_sample_keyframes(n_keyframes, k_recent, p_recent, count, seed, counter):
+    """Returns the count sampled keyframe indices (numpy int32)."""
+    out = np.zeros(max(count, 1), np.int32)
+    _check("glam_sample_keyframes", load().glam_sample_keyframes(n_keyframes, k_recent, float(p_recent), count,
+                                                                 C.c_uint64(seed), C.c_uint64(counter), ref(out)))
+    return out[:count]
+

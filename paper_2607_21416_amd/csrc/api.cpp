@@ -274,4 +274,21 @@ glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins, c
                          grads->dlog_scale, grads->dmlp, workspace, workspace_bytes, stream);
 }
 
+glam_status glam_adam_step(const glam_adam_group* groups, int32_t n_groups, int32_t step, float beta1, float beta2,
+                           float eps, hipStream_t stream) {
+  if (!glam::adam_groups_ok(groups, n_groups) || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return GLAM_ERR_INVALID_ARG;
+  return glam::launch_adam(groups, n_groups, step, beta1, beta2, eps, stream);
+}
+
+glam_status glam_sample_keyframes(int32_t n_keyframes, int32_t k_recent, float p_recent, int32_t count,
+                                  uint64_t seed, uint64_t counter, int32_t* out) {
+  if (n_keyframes <= 0 || k_recent <= 0 || count < 0 || (count > 0 && !out) || !(p_recent >= 0.f && p_recent <= 1.f))
+    return GLAM_ERR_INVALID_ARG;
+  glam::sample_keyframes(n_keyframes, k_recent, p_recent, count, seed, counter, out);
+  return GLAM_OK;
+}
+
 }  // extern "C"
+

@@ -51,4 +51,10 @@ glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_par
                               bool sigmoid_opacity, const glam_gaussians& dg, float* dfeat, float* doffs,
                               float* dlog_scale, float* dmlp, void* ws, hipStream_t s);
 
+bool adam_groups_ok(const glam_adam_group* groups, int n_groups);
+glam_status launch_adam(const glam_adam_group* groups, int n_groups, int step, float beta1, float beta2, float eps,
+                        hipStream_t s);
+void sample_keyframes(int n, int k_recent, float p_recent, int count, uint64_t seed, uint64_t counter,
+                      int32_t* out);
+
 }  // namespace glam

@@ -17,6 +17,13 @@ from . import binding as B
 
 TILE = 16  # default tile edge (8, 16 and 32 are built)
 
+# Adam settings of the optimiser step (the paper names none; these are the defaults of
+# the anchor-based Gaussian-splatting lineage it builds on): learning rates per
+# parameter group, the MLP sets per MLP (opacity, colour, covariance).
+ADAM = dict(beta1=0.9, beta2=0.999, eps=1e-15)
+ADAM_LR_ANCHOR = {"feat": 0.0075, "offs": 0.01, "log_scale": 0.007, "mlp": (0.002, 0.008, 0.004)}
+ADAM_LR_PLAIN = {"mean": 0.00016, "log_scale": 0.005, "quat": 0.001, "logit": 0.05, "rgb": 0.0025}
+
 
 def camera_array(cams) -> "C.Array":
     arr = (B.Camera * len(cams))()
@@ -172,6 +179,52 @@ class Pipeline:
                            self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr(), self.tuning)
         nb = B.glam_bin_sort_workspace_bytes(self.vt.views, self.capacity)
         self.ws_sort = torch.empty(nb, device=dev, dtype=torch.uint8)
+
+    # ------------------------------------------------------------------------------
+    def init_optimizer(self):
+        """Adam state (zeroed moments) and the parameter groups of glam_adam_step: the
+        anchors' features, offsets and log-scales and the MLP sets (one group, a segment
+        per MLP), or the plain Gaussians' parameters.  Anchor positions stay fixed."""
+        dev = self.device
+        if self.plain:
+            names, lrs = list(ADAM_LR_PLAIN), ADAM_LR_PLAIN
+            grads = {"mean": self.dg["mean"], "log_scale": self.dg["log_scale"], "quat": self.dg["quat"],
+                     "logit": self.dg["logit"], "rgb": self.dg["rgb"]}
+        else:
+            names, lrs = list(ADAM_LR_ANCHOR), ADAM_LR_ANCHOR
+            grads = self.pgrad
+        self.opt_m = {k: torch.zeros_like(self.params[k]) for k in names}
+        self.opt_v = {k: torch.zeros_like(self.params[k]) for k in names}
+        self.opt_t = 0
+        groups = (B.AdamGroup * len(names))()
+        for i, k in enumerate(names):
+            g = groups[i]
+            g.param, g.grad = self.params[k].data_ptr(), grads[k].data_ptr()
+            g.m, g.v = self.opt_m[k].data_ptr(), self.opt_v[k].data_ptr()
+            g.n = self.params[k].numel()
+            if k == "mlp":
+                P = self.params[k].shape[1]
+                F, K = self.scene["F"], self.scene["K"]
+                n_in, h = F + 4, self.scene["hidden"]
+                ends = []
+                for out in (K, 3 * K, 7 * K):
+                    ends.append((ends[-1] if ends else 0) + h * n_in + h + out * h + out)
+                assert ends[-1] == P
+                g.period, g.n_seg = P, 3
+                for j in range(3):
+                    g.seg_end[j], g.lr[j] = ends[j], lrs[k][j]
+            else:
+                g.period, g.n_seg = 1, 1  # one learning rate for the whole array
+                g.seg_end[0], g.lr[0] = 1, lrs[k]
+        self.opt_groups = groups
+
+    def adam_step(self, s=None, step: int | None = None):
+        """The optimiser step after a backward (step number: the next one by default)."""
+        if not hasattr(self, "opt_groups"):
+            self.init_optimizer()
+        self.opt_t = self.opt_t + 1 if step is None else int(step)
+        B.glam_adam_step(self.opt_groups, len(self.opt_groups), self.opt_t, ADAM["beta1"], ADAM["beta2"],
+                         ADAM["eps"], s or self.stream())
 
     def set_tuning(self, tuning: dict | None):
         """Changes the compositing schedule (takes effect from the next bin_sort)."""
