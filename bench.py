@@ -273,6 +273,30 @@ def main():
     log(f"bench: with the optimiser step {t_opt:.3f} ms/step ({n_views * 1000.0 / t_opt:.1f} iterations/s), "
         f"Adam {t_adam:.3f} ms over {n_opt} parameters")
 
+    # loop-closure deformation of config 3's anchors by 40 corrected keyframes (on
+    # scratch copies of the anchor positions and offsets)
+    fixes = synth.loop_fixes(77, 40, spacing=2.0)
+    table = (binding.KeyframeFix * len(fixes))()
+    for i, f in enumerate(fixes):
+        c = table[i].before
+        for k in range(9):
+            c.R[k], table[i].R_new[k] = float(np.asarray(f["R_old"]).ravel()[k]), float(np.asarray(f["R_new"]).ravel()[k])
+        for k in range(3):
+            c.t[k], table[i].t_new[k] = float(f["t_old"][k]), float(f["t_new"][k])
+        c.fx, c.fy, c.cx, c.cy, c.width, c.height = f["fx"], f["fy"], f["cx"], f["cy"], f["W"], f["H"]
+    dtable = torch.from_numpy(np.frombuffer(bytes(table), np.uint8).copy()).to(dev)
+    A3, K3 = pipe.anchors.A, pipe.anchors.K
+    xpos, xoffs = pipe.params["pos"].clone(), pipe.params["offs"].clone()
+    xown = torch.empty(A3, dtype=torch.int32, device=dev)
+    dstep, dg_ = make_graph(torch, lambda: [binding.glam_deform_anchors(xpos, xoffs, A3, K3, dtable, len(fixes), 0.2,
+                                                                        80.0, xown, torch.cuda.current_stream())
+                                            for _ in range(10)], True)
+    t_def = timed(torch, dstep, 3, stream) / 10
+    moved = int((xown >= 0).sum().item())
+    del dg_, xpos, xoffs
+    log(f"bench: loop-closure deformation {t_def * 1e3:.1f} us for {A3} anchors x {len(fixes)} keyframes "
+        f"({moved} anchors in a frustum)")
+
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * 262144, device=dev)
         dst = torch.empty_like(src)
@@ -296,6 +320,8 @@ def main():
         "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
                               "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
         "roofline": roofline,
+        "loop_closure": {"workload": f"{A3} anchors (K = {K3} offsets), {len(fixes)} corrected keyframes",
+                         "us": round(t_def * 1e3, 2), "anchors_in_a_frustum": moved},
         "with_optimizer": {"ms_per_step": round(t_opt, 4), "iterations_per_s": round(n_views * 1000.0 / t_opt, 2),
                            "adam_ms": round(t_adam, 4), "parameters": n_opt,
                            "adam_hbm_GBs": round(28.0 * n_opt / (t_adam * 1e-3) / 1e9, 1)},

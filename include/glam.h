@@ -12,6 +12,8 @@
  *   glam_render_bwd  reverse compositing, projection adjoint, decode adjoint
  *   glam_adam_step   the optimiser step of the mapping iteration (fused Adam)
  *   glam_sample_keyframes  which keyframes an iteration renders (host)
+ *   glam_deform_anchors    loop-closure correction of the anchor grid (Eq. 7)
+ *   glam_epipolar_triangulate  flow correspondences: epipolar filter, triangulation (Eq. 5)
  *
  * Conventions shared by every call:
  *  - Array arguments are DEVICE pointers owned by the caller; the library never
@@ -352,6 +354,47 @@ glam_status glam_adam_step(const glam_adam_group* groups, int32_t n_groups, int3
    (seed, counter).  out: [count] host.  Pure host function. */
 glam_status glam_sample_keyframes(int32_t n_keyframes, int32_t k_recent, float p_recent,
                                   int32_t count, uint64_t seed, uint64_t counter, int32_t* out);
+
+/* --- loop closure ----------------------------------------------------------------- */
+
+/* One keyframe's loop-closure correction: its pose before (a camera whose intrinsics and
+   image size also define the keyframe's view frustum) and its corrected world->camera
+   pose. */
+typedef struct {
+  glam_camera before;
+  float R_new[9];
+  float t_new[3];
+} glam_keyframe_fix;
+
+/* Eq. 7: each corrected keyframe i moves the anchors of its view frustum by
+   dT_i = T_new,i^-1 T_old,i (T = world->camera), so they keep their coordinates in the
+   keyframe's camera frame.  An anchor lies in the frustum when its depth in the old
+   camera frame is in [near, far] and it projects inside the image; an anchor in several
+   frusta follows the keyframe whose old camera centre is nearest (ties: the lower
+   index).  Positions move as x <- R_d x + t_d and the anchor's K offsets rotate with it,
+   o <- R_d o; anchors outside every frustum stay.  pos [3][A] and offs [3][A*K] device,
+   updated in place; fixes [n_fix] device; owner [A] device (may be NULL) receives the
+   keyframe applied or -1.  0 < near < far. */
+glam_status glam_deform_anchors(float* pos, float* offs, int32_t A, int32_t K,
+                                const glam_keyframe_fix* fixes, int32_t n_fix, float near,
+                                float far, int32_t* owner, hipStream_t stream);
+
+/* --- flow densification ------------------------------------------------------------ */
+
+/* Eq. 5: filters N correspondences x1 <-> x2 between two keyframes with known cameras by
+   the epipolar residual |x2^T F x1| < tau (x homogeneous pixel coordinates [u, v, 1]) and
+   triangulates the retained ones.  F = [e2]x P2 P1^+ with P = K [R | t], e2 = P2 C1 (C1
+   the first camera's centre) and P1^+ the pseudo-inverse of P1, scaled to unit Frobenius
+   norm with the sign that makes its largest-magnitude entry positive (tau is in those
+   units); computed on the host in double precision.  Retained pairs are triangulated by
+   linear least squares with the known poses (the four DLT rows in normalised image
+   coordinates, X = (X, Y, Z, 1)), in double precision on the GPU.  x1, x2 [2][N] device
+   (u row, then v row); residual [N], keep [N] (1 retained, 0 not, or when the
+   triangulation is singular), X [3][N] world points (NaN where keep is 0) device. */
+glam_status glam_epipolar_triangulate(const glam_camera* cam1, const glam_camera* cam2,
+                                      const float* x1, const float* x2, int64_t n, float tau,
+                                      float* residual, int32_t* keep, float* X,
+                                      hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ EXPORTS = [
     "glam_status_string", "glam_mlp_param_count", "glam_views_build", "glam_bin_sort_workspace_bytes",
     "glam_decode", "glam_project", "glam_bin_sort", "glam_render_fwd", "glam_loss_workspace_bytes", "glam_loss",
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
-    "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes",
+    "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
 ]
 GLAM_ADAM_MAX_GROUPS = 16
 
@@ -88,6 +88,10 @@ class AdamGroup(C.Structure):
                 ("lr", C.c_float * 4)]
 
 
+class KeyframeFix(C.Structure):
+    _fields_ = [("before", Camera), ("R_new", C.c_float * 9), ("t_new", C.c_float * 3)]
+
+
 _lib = None
 
 
@@ -119,6 +123,7 @@ def load():
         "glam_render_bwd": (I32, [P, P, P, P, P, P, P, P, P, P, I32, U32, P, P, SZ, P]),
         "glam_adam_step": (I32, [P, I32, I32, F32, F32, F32, P]),
         "glam_sample_keyframes": (I32, [I32, I32, F32, I32, C.c_uint64, C.c_uint64, P]),
+        "glam_deform_anchors": (I32, [P, P, I32, I32, P, I32, F32, F32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -248,4 +253,10 @@ def glam_sample_keyframes(n_keyframes, k_recent, p_recent, count, seed, counter)
     _check("glam_sample_keyframes", load().glam_sample_keyframes(n_keyframes, k_recent, float(p_recent), count,
                                                                  C.c_uint64(seed), C.c_uint64(counter), ref(out)))
     return out[:count]
+
+
+def glam_deform_anchors(pos, offs, A, K, fixes, n_fix, near, far, owner, stream):
+    return _check("glam_deform_anchors", load().glam_deform_anchors(ref(pos), ref(offs), A, K, ref(fixes), n_fix,
+                                                                    float(near), float(far), ref(owner),
+                                                                    _stream(stream)))
 

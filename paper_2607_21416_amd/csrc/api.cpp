@@ -290,5 +290,25 @@ glam_status glam_sample_keyframes(int32_t n_keyframes, int32_t k_recent, float p
   return GLAM_OK;
 }
 
+glam_status glam_deform_anchors(float* pos, float* offs, int32_t A, int32_t K, const glam_keyframe_fix* fixes,
+                                int32_t n_fix, float near, float far, int32_t* owner, hipStream_t stream) {
+  if (A < 0 || K < 0 || n_fix < 0 || !(near > 0.f) || !(far > near) || (owner && !aligned16(owner)))
+    return GLAM_ERR_INVALID_ARG;
+  if (A > 0 && (!ok_ptr(pos) || (K > 0 && !ok_ptr(offs)) || (n_fix > 0 && !ok_ptr(fixes))))
+    return GLAM_ERR_INVALID_ARG;
+  return glam::launch_deform(pos, offs, A, K, fixes, n_fix, near, far, owner, stream);
+}
+
+glam_status glam_epipolar_triangulate(const glam_camera* cam1, const glam_camera* cam2, const float* x1,
+                                      const float* x2, int64_t n, float tau, float* residual, int32_t* keep,
+                                      float* X, hipStream_t stream) {
+  if (!cam1 || !cam2 || n < 0 || !(tau >= 0.f) || !(cam1->fx > 0.f) || !(cam1->fy > 0.f) || !(cam2->fx > 0.f) ||
+      !(cam2->fy > 0.f))
+    return GLAM_ERR_INVALID_ARG;
+  if (n > 0 && (!ok_ptr(x1) || !ok_ptr(x2) || !ok_ptr(residual) || !ok_ptr(keep) || !ok_ptr(X)))
+    return GLAM_ERR_INVALID_ARG;
+  return glam::launch_epipolar(*cam1, *cam2, x1, x2, n, tau, residual, keep, X, stream);
+}
+
 }  // extern "C"
 

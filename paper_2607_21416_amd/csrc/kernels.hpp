@@ -57,4 +57,11 @@ glam_status launch_adam(const glam_adam_group* groups, int n_groups, int step, f
 void sample_keyframes(int n, int k_recent, float p_recent, int count, uint64_t seed, uint64_t counter,
                       int32_t* out);
 
+glam_status launch_deform(float* pos, float* offs, int A, int K, const glam_keyframe_fix* fixes, int n_fix,
+                          float near, float far, int32_t* owner, hipStream_t s);
+
+bool fundamental_from_cameras(const glam_camera& c1, const glam_camera& c2, double F[9]);
+glam_status launch_epipolar(const glam_camera& c1, const glam_camera& c2, const float* x1, const float* x2,
+                            long long n, float tau, float* residual, int32_t* keep, float* X, hipStream_t s);
+
 }  // namespace glam

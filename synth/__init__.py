@@ -261,3 +261,30 @@ def long_path_scene(seed: int = 1005, n_parts: int = 64, views_per_part: int = 8
                 part_begin=np.concatenate([[0], np.cumsum(counts)]).astype(np.int32),
                 mlp=f32(np.stack(mlps)), cams=cams, targets=targets, ssim_weight=0.2,
                 opacity_mode="tanh")
+
+# ----------------------------------------------------------------------------------
+# Loop-closure corrections: keyframes along the corridor and small pose corrections
+# ----------------------------------------------------------------------------------
+
+def _axis_angle(axis, angle):
+    a = np.asarray(axis, np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
+
+
+def loop_fixes(seed: int, n: int, W: int = 1226, H: int = 370, spacing: float = 3.0, rot_deg: float = 1.0,
+               trans_m: float = 0.1) -> list:
+    """n keyframes along the corridor (old poses) with random corrections of up to rot_deg
+    degrees about a random axis and trans_m metres: dicts with R_old, t_old, R_new, t_new
+    (world->camera) and the intrinsics."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, c in enumerate(corridor_views(rng, n, W, H, spacing=spacing)):
+        dR = _axis_angle(rng.normal(size=3), math.radians(rng.uniform(-rot_deg, rot_deg)))
+        R_new = (dR @ c["R"].astype(np.float64)).astype(np.float32)
+        t_new = (c["t"] + rng.uniform(-trans_m, trans_m, 3)).astype(np.float32)
+        out.append(dict(R_old=c["R"], t_old=c["t"], R_new=R_new, t_new=t_new, fx=c["fx"], fy=c["fy"],
+                        cx=c["cx"], cy=c["cy"], W=c["W"], H=c["H"]))
+    return out
+
