@@ -297,6 +297,28 @@ def main():
     log(f"bench: loop-closure deformation {t_def * 1e3:.1f} us for {A3} anchors x {len(fixes)} keyframes "
         f"({moved} anchors in a frustum)")
 
+    # flow densification geometry: one flow field's correspondences between two
+    # keyframes (a pair per pixel of a 1226x370 view), epipolar filter + triangulation
+    from paper_2607_21416_amd.pipeline import camera_array
+    npx = 1226 * 370
+    fc1, fc2, fx1, fx2, _, _ = synth.flow_pairs(91, npx, baseline=1.0, noise_px=0.5, outlier_frac=0.2)
+    fcams = camera_array([fc1, fc2])
+    gx1, gx2 = torch.from_numpy(np.ascontiguousarray(fx1)).to(dev), torch.from_numpy(np.ascontiguousarray(fx2)).to(dev)
+    fres = torch.empty(npx, device=dev)
+    fkeep = torch.empty(npx, dtype=torch.int32, device=dev)
+    fX = torch.empty((3, npx), device=dev)
+    tau = 0.05  # unit-norm F: keeps ~95% of the inliers and drops most outliers here
+
+    def epi():
+        binding.glam_epipolar_triangulate(fcams[0], fcams[1], gx1, gx2, npx, tau, fres, fkeep, fX,
+                                          torch.cuda.current_stream())
+
+    estep, eg = make_graph(torch, lambda: [epi() for _ in range(10)], True)
+    t_epi = timed(torch, estep, 3, stream) / 10
+    kept = int(fkeep.sum().item())
+    del eg
+    log(f"bench: epipolar filter + triangulation {t_epi * 1e3:.1f} us for {npx} correspondences ({kept} kept)")
+
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * 262144, device=dev)
         dst = torch.empty_like(src)
@@ -320,6 +342,10 @@ def main():
         "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
                               "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
         "roofline": roofline,
+        "flow_densification": {"workload": f"{npx} correspondences between two 1226x370 keyframes 1 m apart "
+                                           "(0.5 px noise, 20% outliers)",
+                               "us": round(t_epi * 1e3, 2), "kept": kept,
+                               "correspondences_per_s": round(npx / (t_epi * 1e-3), 1)},
         "loop_closure": {"workload": f"{A3} anchors (K = {K3} offsets), {len(fixes)} corrected keyframes",
                          "us": round(t_def * 1e3, 2), "anchors_in_a_frustum": moved},
         "with_optimizer": {"ms_per_step": round(t_opt, 4), "iterations_per_s": round(n_views * 1000.0 / t_opt, 2),

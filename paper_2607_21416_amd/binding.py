@@ -24,6 +24,7 @@ EXPORTS = [
     "glam_decode", "glam_project", "glam_bin_sort", "glam_render_fwd", "glam_loss_workspace_bytes", "glam_loss",
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
+    "glam_epipolar_triangulate",
 ]
 GLAM_ADAM_MAX_GROUPS = 16
 
@@ -124,6 +125,7 @@ def load():
         "glam_adam_step": (I32, [P, I32, I32, F32, F32, F32, P]),
         "glam_sample_keyframes": (I32, [I32, I32, F32, I32, C.c_uint64, C.c_uint64, P]),
         "glam_deform_anchors": (I32, [P, P, I32, I32, P, I32, F32, F32, P, P]),
+        "glam_epipolar_triangulate": (I32, [P, P, P, P, I64, F32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -148,6 +150,8 @@ def ref(x):
     pointer), a numpy array, an int address or None."""
     if x is None:
         return None
+    if isinstance(x, C.c_void_p):
+        return x
     if isinstance(x, (C.Structure, C.Array)):
         return C.cast(C.byref(x), C.c_void_p)
     if hasattr(x, "data_ptr"):
@@ -259,4 +263,10 @@ def glam_deform_anchors(pos, offs, A, K, fixes, n_fix, near, far, owner, stream)
     return _check("glam_deform_anchors", load().glam_deform_anchors(ref(pos), ref(offs), A, K, ref(fixes), n_fix,
                                                                     float(near), float(far), ref(owner),
                                                                     _stream(stream)))
+
+
+def glam_epipolar_triangulate(cam1, cam2, x1, x2, n, tau, residual, keep, X, stream):
+    return _check("glam_epipolar_triangulate",
+                  load().glam_epipolar_triangulate(ref(cam1), ref(cam2), ref(x1), ref(x2), n, float(tau),
+                                                   ref(residual), ref(keep), ref(X), _stream(stream)))
 

@@ -288,3 +288,28 @@ def loop_fixes(seed: int, n: int, W: int = 1226, H: int = 370, spacing: float = 
                         cx=c["cx"], cy=c["cy"], W=c["W"], H=c["H"]))
     return out
 
+# ----------------------------------------------------------------------------------
+# Flow correspondences between two keyframes of the corridor
+# ----------------------------------------------------------------------------------
+
+def flow_pairs(seed: int, n: int, baseline: float = 1.0, noise_px: float = 0.0, outlier_frac: float = 0.0,
+               W: int = 1226, H: int = 370):
+    """Correspondences x1 <-> x2 of n corridor surface points seen by two keyframes
+    `baseline` metres apart along the corridor (yaw jitter as the keyframes of the
+    workloads), with Gaussian pixel noise on x2 and a fraction of outliers (x2 replaced by
+    a uniform random pixel).  Returns (cam1, cam2, x1 [2][n], x2 [2][n] float32, points
+    [3][n] float64, outlier mask)."""
+    rng = np.random.default_rng(seed)
+    cams = corridor_views(rng, 2, W, H, spacing=baseline)
+    vox = corridor_voxels(z0=baseline + 3.0, z1=80.0)
+    pts = vox[rng.choice(len(vox), n, replace=True)] + rng.uniform(-0.1, 0.1, (n, 3))
+    out = []
+    for c in cams:
+        y = c["R"].astype(np.float64) @ pts.T + c["t"].astype(np.float64)[:, None]
+        out.append(np.stack([c["fx"] * y[0] / y[2] + c["cx"], c["fy"] * y[1] / y[2] + c["cy"]]))
+    x1, x2 = out
+    x2 = x2 + rng.normal(0.0, noise_px, x2.shape) if noise_px > 0 else x2
+    bad = rng.uniform(size=n) < outlier_frac
+    x2[:, bad] = np.stack([rng.uniform(0, W, bad.sum()), rng.uniform(0, H, bad.sum())])
+    return cams[0], cams[1], x1.astype(np.float32), x2.astype(np.float32), pts.T, bad
+
