@@ -313,3 +313,26 @@ def flow_pairs(seed: int, n: int, baseline: float = 1.0, noise_px: float = 0.0, 
     x2[:, bad] = np.stack([rng.uniform(0, W, bad.sum()), rng.uniform(0, H, bad.sum())])
     return cams[0], cams[1], x1.astype(np.float32), x2.astype(np.float32), pts.T, bad
 
+
+
+def fused_points(seed: int, n: int, dup_frac: float = 0.3, dup_jitter: float = 2e-4, nan_frac: float = 0.0,
+                 far_frac: float = 0.0, far: float = 2.0e3, origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """A keyframe's fused point cloud [3][n] float32 (tracked plus triangulated flow
+    points): points on the corridor surfaces (positions of the corridor lattice plus a
+    uniform jitter of +-0.1 m, so the surfaces are covered continuously), shifted by
+    origin.  A fraction dup_frac repeats an earlier point with a uniform jitter of
+    +-dup_jitter m per axis (the same surface point seen again), nan_frac columns are NaN
+    (rejected triangulations) and far_frac points lie +-far m away on every axis (beyond
+    a 1 mm grid's key range)."""
+    rng = np.random.default_rng(seed)
+    vox = corridor_voxels()
+    pts = vox[rng.integers(0, len(vox), n)] + rng.uniform(-0.1, 0.1, (n, 3)) + np.asarray(origin, np.float64)
+    if n > 1:
+        dup = np.flatnonzero(rng.uniform(size=n) < dup_frac)
+        dup = dup[dup > 0]
+        src = (rng.uniform(size=len(dup)) * dup).astype(np.int64)  # an earlier point
+        pts[dup] = pts[src] + rng.uniform(-dup_jitter, dup_jitter, (len(dup), 3))
+    far_m = rng.uniform(size=n) < far_frac
+    pts[far_m] = rng.choice([-far, far], (int(far_m.sum()), 3))
+    pts[rng.uniform(size=n) < nan_frac] = np.nan
+    return np.ascontiguousarray(pts.T.astype(np.float32))
