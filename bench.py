@@ -319,6 +319,38 @@ def main():
     del eg
     log(f"bench: epipolar filter + triangulation {t_epi * 1e3:.1f} us for {npx} correspondences ({kept} kept)")
 
+    # anchor growth (Eq. 4): the triangulated flow points above (NaN where rejected) and
+    # 2,000 tracked points of the keyframe, snapped to 1 mm voxels and grown onto the key
+    # set of config 3's anchors (built once by the same call with no existing keys)
+    veps = 0.001
+    tracked = torch.from_numpy(synth.fused_points(92, 2000, dup_frac=0.0)).to(dev)
+    cloud = torch.cat([fX, tracked], dim=1).contiguous()
+    nv = int(cloud.shape[1])
+    vwsb = binding.glam_voxelize_workspace_bytes(max(nv, A3))
+    vws = torch.empty(vwsb, dtype=torch.uint8, device=dev)
+    akeys = torch.empty(A3, dtype=torch.int64, device=dev)
+    acen = torch.empty((3, A3), device=dev)
+    aset = torch.empty(A3, dtype=torch.int64, device=dev)
+    acnt = torch.empty(2, dtype=torch.int64, device=dev)
+    binding.glam_voxelize(pipe.params["pos"], A3, veps, None, 0, akeys, acen, A3, aset, acnt, vws, vwsb,
+                          torch.cuda.current_stream())
+    n_akeys = int(acnt[0].item())
+    gkeys = torch.empty(nv, dtype=torch.int64, device=dev)
+    gcen = torch.empty((3, nv), device=dev)
+    gset = torch.empty(n_akeys + nv, dtype=torch.int64, device=dev)
+    gcnt = torch.empty(2, dtype=torch.int64, device=dev)
+
+    def grow():
+        binding.glam_voxelize(cloud, nv, veps, aset, n_akeys, gkeys, gcen, nv, gset, gcnt, vws, vwsb,
+                              torch.cuda.current_stream())
+
+    vstep, vg = make_graph(torch, lambda: [grow() for _ in range(10)], True)
+    t_vox = timed(torch, vstep, 3, stream) / 10
+    n_new, n_drop = (int(x) for x in gcnt.cpu().tolist())
+    del vg, vws
+    log(f"bench: anchor growth {t_vox * 1e3:.1f} us for {nv} points onto {n_akeys} anchor voxels "
+        f"({n_new} new voxels, {n_drop} points dropped)")
+
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * 262144, device=dev)
         dst = torch.empty_like(src)
@@ -346,6 +378,10 @@ def main():
                                            "(0.5 px noise, 20% outliers)",
                                "us": round(t_epi * 1e3, 2), "kept": kept,
                                "correspondences_per_s": round(npx / (t_epi * 1e-3), 1)},
+        "anchor_growth": {"workload": f"{nv} fused points (triangulated flow points, NaN where rejected, and "
+                                      f"2000 tracked points), 1 mm voxels, onto {n_akeys} anchor voxels",
+                          "us": round(t_vox * 1e3, 2), "new_voxels": n_new, "dropped": n_drop,
+                          "points_per_s": round(nv / (t_vox * 1e-3), 1)},
         "loop_closure": {"workload": f"{A3} anchors (K = {K3} offsets), {len(fixes)} corrected keyframes",
                          "us": round(t_def * 1e3, 2), "anchors_in_a_frustum": moved},
         "with_optimizer": {"ms_per_step": round(t_opt, 4), "iterations_per_s": round(n_views * 1000.0 / t_opt, 2),

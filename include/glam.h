@@ -14,6 +14,7 @@
  *   glam_sample_keyframes  which keyframes an iteration renders (host)
  *   glam_deform_anchors    loop-closure correction of the anchor grid (Eq. 7)
  *   glam_epipolar_triangulate  flow correspondences: epipolar filter, triangulation (Eq. 5)
+ *   glam_voxelize    fused points -> unique voxels, those not yet anchors (Eq. 4)
  *
  * Conventions shared by every call:
  *  - Array arguments are DEVICE pointers owned by the caller; the library never
@@ -395,6 +396,40 @@ glam_status glam_epipolar_triangulate(const glam_camera* cam1, const glam_camera
                                       const float* x1, const float* x2, int64_t n, float tau,
                                       float* residual, int32_t* keep, float* X,
                                       hipStream_t stream);
+
+/* --- anchor voxelisation and growth -------------------------------------------------- */
+
+/* Bytes of workspace glam_voxelize needs for n_points points (0 when n_points is out of
+   range). */
+size_t glam_voxelize_workspace_bytes(int64_t n_points);
+
+/* Eq. 4: the fused point cloud (tracked points and triangulated flow points, Sec. III-A)
+   snapped to the voxel grid of size eps, keeping unique voxels, and of those the ones
+   not already anchors (the incremental growth of the anchor set).  Per point and axis
+   k = round(p / eps), the FP32 quotient rounded to the nearest integer with ties to
+   even; k must lie in [-2^20, 2^20) on every axis, otherwise (or for a NaN coordinate,
+   as in a rejected triangulation) the point is dropped and counted.  A voxel's key packs
+   (k_x + 2^20, k_y + 2^20, k_z + 2^20) into bits 62..42, 41..21, 20..0, so key order is
+   lexicographic (x, y, z) order; its centre is k * eps (FP32 product).
+     points [3][n_points] device
+     existing [n_existing] device: keys of the current anchors, strictly ascending
+     new_keys [capacity], new_centres [3][capacity] device: the voxels of the points
+       whose keys are absent from existing, ascending by key (centres row by row with
+       row stride capacity)
+     merged [n_existing + capacity] device, or NULL: the ascending union of existing and
+       the new keys (the key set after growth), in its first n_existing + min(count,
+       capacity) entries
+     counts [2] int64 device: the number of new voxels (which may exceed capacity: then
+       only the first capacity are written and merged lacks the rest), and the number of
+       dropped points
+   n_points <= 2^31 (else GLAM_ERR_UNSUPPORTED); eps > 0 and finite.  Workspace:
+   glam_voxelize_workspace_bytes(n_points).  If existing is not strictly ascending the
+   outputs are unspecified, but no memory outside the given buffers is touched. */
+glam_status glam_voxelize(const float* points, int64_t n_points, float eps,
+                          const uint64_t* existing, int64_t n_existing, uint64_t* new_keys,
+                          float* new_centres, int64_t capacity, uint64_t* merged,
+                          int64_t* counts, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ EXPORTS = [
     "glam_decode", "glam_project", "glam_bin_sort", "glam_render_fwd", "glam_loss_workspace_bytes", "glam_loss",
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
-    "glam_epipolar_triangulate",
+    "glam_epipolar_triangulate", "glam_voxelize_workspace_bytes", "glam_voxelize",
 ]
 GLAM_ADAM_MAX_GROUPS = 16
 
@@ -126,6 +126,8 @@ def load():
         "glam_sample_keyframes": (I32, [I32, I32, F32, I32, C.c_uint64, C.c_uint64, P]),
         "glam_deform_anchors": (I32, [P, P, I32, I32, P, I32, F32, F32, P, P]),
         "glam_epipolar_triangulate": (I32, [P, P, P, P, I64, F32, P, P, P, P]),
+        "glam_voxelize_workspace_bytes": (SZ, [I64]),
+        "glam_voxelize": (I32, [P, I64, F32, P, I64, P, P, I64, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -270,3 +272,14 @@ def glam_epipolar_triangulate(cam1, cam2, x1, x2, n, tau, residual, keep, X, str
                   load().glam_epipolar_triangulate(ref(cam1), ref(cam2), ref(x1), ref(x2), n, float(tau),
                                                    ref(residual), ref(keep), ref(X), _stream(stream)))
 
+
+def glam_voxelize_workspace_bytes(n_points):
+    return load().glam_voxelize_workspace_bytes(n_points)
+
+
+def glam_voxelize(points, n_points, eps, existing, n_existing, new_keys, new_centres, capacity, merged, counts,
+                  workspace, workspace_bytes, stream):
+    return _check("glam_voxelize",
+                  load().glam_voxelize(ref(points), n_points, float(eps), ref(existing), n_existing, ref(new_keys),
+                                       ref(new_centres), capacity, ref(merged), ref(counts), ref(workspace),
+                                       workspace_bytes, _stream(stream)))

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglam.so")
-SOURCES = ["api.cpp", "project.hip", "binsort.hip", "render.hip", "loss.hip", "decode.hip", "optim.hip", "deform.hip", "epipolar.hip"]
+SOURCES = ["api.cpp", "project.hip", "binsort.hip", "render.hip", "loss.hip", "decode.hip", "optim.hip", "deform.hip", "epipolar.hip", "voxel.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

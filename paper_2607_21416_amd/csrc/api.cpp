@@ -3,6 +3,7 @@
 // synchronises; every launch goes to the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 
@@ -308,6 +309,26 @@ glam_status glam_epipolar_triangulate(const glam_camera* cam1, const glam_camera
   if (n > 0 && (!ok_ptr(x1) || !ok_ptr(x2) || !ok_ptr(residual) || !ok_ptr(keep) || !ok_ptr(X)))
     return GLAM_ERR_INVALID_ARG;
   return glam::launch_epipolar(*cam1, *cam2, x1, x2, n, tau, residual, keep, X, stream);
+}
+
+size_t glam_voxelize_workspace_bytes(int64_t n_points) {
+  return n_points < 0 || n_points > glam::kVoxelMaxPoints ? 0 : glam::voxelize_workspace(n_points);
+}
+
+glam_status glam_voxelize(const float* points, int64_t n_points, float eps, const uint64_t* existing,
+                          int64_t n_existing, uint64_t* new_keys, float* new_centres, int64_t capacity,
+                          uint64_t* merged, int64_t* counts, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
+  if (n_points < 0 || n_existing < 0 || capacity < 0 || !(eps > 0.f) || !std::isfinite(eps) || !ok_ptr(counts))
+    return GLAM_ERR_INVALID_ARG;
+  if (n_points > glam::kVoxelMaxPoints) return GLAM_ERR_UNSUPPORTED;
+  if ((n_points > 0 && !ok_ptr(points)) || (n_existing > 0 && !ok_ptr(existing)) ||
+      (capacity > 0 && (!ok_ptr(new_keys) || !ok_ptr(new_centres))) || (merged && !aligned16(merged)))
+    return GLAM_ERR_INVALID_ARG;
+  if (!workspace || !aligned16(workspace)) return GLAM_ERR_WORKSPACE;
+  if (workspace_bytes < glam::voxelize_workspace(n_points)) return GLAM_ERR_WORKSPACE;
+  return glam::launch_voxelize(points, n_points, eps, existing, n_existing, new_keys, new_centres, capacity, merged,
+                               counts, workspace, stream);
 }
 
 }  // extern "C"

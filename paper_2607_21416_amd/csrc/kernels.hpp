@@ -64,4 +64,10 @@ bool fundamental_from_cameras(const glam_camera& c1, const glam_camera& c2, doub
 glam_status launch_epipolar(const glam_camera& c1, const glam_camera& c2, const float* x1, const float* x2,
                             long long n, float tau, float* residual, int32_t* keep, float* X, hipStream_t s);
 
+constexpr long long kVoxelMaxPoints = 1ll << 31;
+size_t voxelize_workspace(long long n);
+glam_status launch_voxelize(const float* points, long long n, float eps, const uint64_t* existing,
+                            long long n_existing, uint64_t* new_keys, float* new_pos, long long capacity,
+                            uint64_t* merged, int64_t* counts, void* ws, hipStream_t s);
+
 }  // namespace glam

@@ -141,6 +141,36 @@ def test_calls_reject_before_launch():
     assert B.status_string(B.GLAM_ERR_CAPACITY) == "pair capacity exceeded"
 
 
+def test_voxelize_rejects_before_launch():
+    lib = B.load()
+    fake = 0x100000  # aligned, never dereferenced: validation fails first
+    need = lib.glam_voxelize_workspace_bytes(100000)
+    assert need >= 100000 * 20 and lib.glam_voxelize_workspace_bytes(200000) > need
+    assert lib.glam_voxelize_workspace_bytes(-1) == 0 and lib.glam_voxelize_workspace_bytes((1 << 31) + 1) == 0
+    P = C.c_void_p
+
+    def call(n=100000, eps=0.001, existing=fake, n_existing=10, new=fake, cen=fake, cap=1000, merged=fake,
+             counts=fake, ws=fake, wsb=need):
+        return lib.glam_voxelize(P(fake), n, eps, P(existing) if existing else None, n_existing,
+                                 P(new) if new else None, P(cen) if cen else None, cap,
+                                 P(merged) if merged else None, P(counts) if counts else None,
+                                 P(ws) if ws else None, wsb, None)
+
+    assert call(eps=0.0) == B.GLAM_ERR_INVALID_ARG
+    assert call(eps=float("nan")) == B.GLAM_ERR_INVALID_ARG
+    assert call(eps=float("inf")) == B.GLAM_ERR_INVALID_ARG
+    assert call(n=-1) == B.GLAM_ERR_INVALID_ARG
+    assert call(cap=-1) == B.GLAM_ERR_INVALID_ARG
+    assert call(counts=None) == B.GLAM_ERR_INVALID_ARG
+    assert call(existing=None) == B.GLAM_ERR_INVALID_ARG
+    assert call(new=fake + 8) == B.GLAM_ERR_INVALID_ARG
+    assert call(cen=None) == B.GLAM_ERR_INVALID_ARG
+    assert call(merged=fake + 4) == B.GLAM_ERR_INVALID_ARG
+    assert call(n=(1 << 31) + 1, wsb=1 << 40) == B.GLAM_ERR_UNSUPPORTED
+    assert call(wsb=need - 1) == B.GLAM_ERR_WORKSPACE
+    assert call(ws=None) == B.GLAM_ERR_WORKSPACE
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libglam.so"))
