@@ -116,9 +116,10 @@ def make_step(torch, pipe, use_graph):
     return make_graph(torch, pipe.step, use_graph)
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, launch):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    the compositing source has changed since the counters were taken."""
+    the compositing source has changed since the counters were taken or they were taken
+    at another launch configuration (tile edge and schedule)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_config3.json")
     try:
@@ -126,7 +127,7 @@ def profiled_traffic(kernel):
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("launch") != launch:
         return None
     k = rec.get("kernels", {}).get(kernel)
     if not k:
@@ -160,6 +161,8 @@ def main():
                     help="also run config 5 (2 km path, 64 partitions x 8 views, mixed resolutions) once")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (built-in tile edge and compositing schedule)")
+    ap.add_argument("--retune", action="store_true",
+                    help="measure the tuner's choice now instead of using a stored one")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -181,10 +184,10 @@ def main():
     log("bench: generating config 3 (50k anchors, 4 views 1226x370)")
     scene = synth.config("C3")
     if args.no_tune:
-        choice = dict(tuning.DEFAULT)
+        choice = dict(tuning.DEFAULT, source="built-in default")
     else:
-        log("bench: autotuning tile edge and compositing schedule (outside the timed region)")
-        choice = tuning.autotune(scene, device=dev, log=log)
+        log("bench: tuner choice of tile edge and compositing schedule (any measuring is outside the timed region)")
+        choice = tuning.autotune(scene, device=dev, log=log, use_cache=not args.retune)
     log("bench: tile %d, long tiles >= 2^%d, grids %d/%d workgroups per CU" % (
         choice["tile"], choice["long_log2"], choice["fwd_blocks_per_cu"], choice["bwd_blocks_per_cu"]))
     pipe = Pipeline(scene, device=dev, tile=choice["tile"], tuning=tuning.schedule(choice))
@@ -231,7 +234,7 @@ def main():
     flops = evals_fwd * FLOP_FWD if dom == "render_fwd" else evals_bwd * FLOP_BWD
     achieved = flops / (st[dom] * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(dom),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)}),
                 "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
                         f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
 
@@ -369,7 +372,7 @@ def main():
                    "views_per_step": n_views, "view_gaussians": int(pipe.vt.n_gauss), "pairs": int(need),
                    "launch": "hip graph" if graph else "eager",
                    "tile": choice["tile"], "schedule": tuning.schedule(choice),
-                   "autotuned": not args.no_tune},
+                   "tuning": choice["source"]},
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
         "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
                               "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
@@ -395,7 +398,8 @@ def main():
     if not args.no_batched:
         log("bench: config 4 (16 partitions x 4 views), batched vs plain")
         s4 = synth.config("C4")
-        c4 = dict(tuning.DEFAULT) if args.no_tune else tuning.autotune(s4, device=dev, log=log)
+        c4 = dict(tuning.DEFAULT) if args.no_tune else tuning.autotune(s4, device=dev, log=log,
+                                                                        use_cache=not args.retune)
         bp = Pipeline(s4, device=dev, tile=c4["tile"], tuning=tuning.schedule(c4))
         bp.fit_capacity()
         bp.status.zero_()

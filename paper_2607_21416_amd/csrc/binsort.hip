@@ -343,9 +343,16 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
                                                                        uint64_t* keys_alt, uint32_t* vals_alt) {
   const Plan pl = *plan;
   if ((uint32_t)pass >= pl.npasses || blockIdx.x >= pl.active_blocks) return;
-  __shared__ uint32_t s_cnt[kSortItems][kSortThreads / 64][kRadix];
+  // the per-(item round, wave, digit) counts, and once ranked the tile's keys and values
+  // in digit order
+  __shared__ __align__(16) uint32_t s_lds[kSortItems * (kSortThreads / 64) * kRadix];
+  static_assert(kSortTile * (sizeof(uint64_t) + sizeof(uint32_t)) <= sizeof(s_lds), "staging fits");
+  auto& s_cnt = *reinterpret_cast<uint32_t(*)[kSortItems][kSortThreads / 64][kRadix]>(s_lds);
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(s_lds);
+  uint32_t* s_val = s_lds + 2 * kSortTile;
   __shared__ uint32_t s_run[kRadix];
   __shared__ uint32_t s_scan[kRadix];
+  __shared__ uint32_t s_lbase[kRadix];
   const bool src_is_out = ((pass & 1) == 0) == ((pl.npasses & 1u) == 0);
   const uint64_t* ksrc = src_is_out ? keys_out : keys_alt;
   const uint32_t* vsrc = src_is_out ? vals_out : vals_alt;
@@ -367,7 +374,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
   __syncthreads();
   const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
   const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
-  uint32_t* cnt = &s_cnt[0][0][0];
+  uint32_t* cnt = s_lds;
   for (uint32_t tile = t0; tile < t1; ++tile) {
     for (int k = t; k < kSortItems * (kSortThreads / 64) * kRadix; k += kSortThreads) cnt[k] = 0;
     __syncthreads();
@@ -402,14 +409,40 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
       s_cnt[k / (kSortThreads / 64)][k % (kSortThreads / 64)][t] = run;
       run += c[k];
     }
+    // first place of digit t in the tile's own digit order
+    s_lbase[t] = run;
     __syncthreads();
+    for (int off = 1; off < kRadix; off <<= 1) {
+      const uint32_t v = t >= off ? s_lbase[t - off] : 0u;
+      __syncthreads();
+      s_lbase[t] += v;
+      __syncthreads();
+    }
+    const uint32_t lbase = s_lbase[t] - run;
+    __syncthreads();
+    s_lbase[t] = lbase;
+    uint32_t lpos[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) lpos[i] = s_cnt[i][w][dig[i]] + rank[i];
+    __syncthreads();
+    // the tile in digit order in LDS (over the counts, which are no longer needed), then
+    // written out by consecutive threads so that each digit's run is stored contiguously
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       if (!valid[i]) continue;
-      const uint32_t pos = s_run[dig[i]] + s_cnt[i][w][dig[i]] + rank[i];
+      const uint32_t lp = s_lbase[dig[i]] + lpos[i];
+      s_key[lp] = key[i];
+      s_val[lp] = val[i];
+    }
+    __syncthreads();
+    const uint32_t n_here = min((uint32_t)kSortTile, pl.P - min(pl.P, start));
+    for (uint32_t j = t; j < n_here; j += kSortThreads) {
+      const uint64_t k = s_key[j];
+      const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+      const uint32_t pos = s_run[d] + (j - s_lbase[d]);
       if (pos < pl.P) {  // always true for consistent counts; keeps any fault impossible
-        kdst[pos] = key[i];
-        vdst[pos] = val[i];
+        kdst[pos] = k;
+        vdst[pos] = s_val[j];
       }
     }
     __syncthreads();

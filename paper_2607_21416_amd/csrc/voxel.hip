@@ -285,8 +285,10 @@ __global__ void __launch_bounds__(kVThreads) vox_scatter_kernel(const VoxState* 
   const unsigned long long n = p.n_sort;
   const unsigned long long* src = (pass & 1) ? b : a;
   unsigned long long* dst = (pass & 1) ? a : b;
-  __shared__ unsigned s_cnt[kVItems][kVThreads / 64][kVRadix];
+  __shared__ __align__(16) unsigned s_cnt[kVItems][kVThreads / 64][kVRadix];
+  static_assert(kVTile * sizeof(unsigned long long) <= sizeof(s_cnt), "staging fits");
   __shared__ unsigned s_base[kVRadix];
+  __shared__ unsigned s_lbase[kVRadix];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const unsigned long long base = (unsigned long long)blockIdx.x * kVTile;
   unsigned long long key[kVItems];
@@ -323,12 +325,27 @@ __global__ void __launch_bounds__(kVThreads) vox_scatter_kernel(const VoxState* 
       s_cnt[i][ww][t] = run;
       run += c;
     }
-  __syncthreads();
+  // first place of digit t in the tile's own digit order
+  unsigned all;
+  const unsigned lbase = block_scan_256(run, s_lbase, all) - run;
+  s_lbase[t] = lbase;
+  unsigned lpos[kVItems];
 #pragma unroll
-  for (int i = 0; i < kVItems; ++i) {
-    if (!valid[i]) continue;
-    const unsigned long long pos = (unsigned long long)s_base[dig[i]] + s_cnt[i][w][dig[i]] + rank[i];
-    if (pos < n) dst[pos] = key[i];
+  for (int i = 0; i < kVItems; ++i) lpos[i] = s_cnt[i][w][dig[i]] + rank[i];
+  __syncthreads();
+  // the tile in digit order in LDS (over the counts), written out by consecutive
+  // threads so that each digit's run is stored contiguously
+  unsigned long long* s_key = reinterpret_cast<unsigned long long*>(&s_cnt[0][0][0]);
+#pragma unroll
+  for (int i = 0; i < kVItems; ++i)
+    if (valid[i]) s_key[s_lbase[dig[i]] + lpos[i]] = key[i];
+  __syncthreads();
+  const unsigned n_here = (unsigned)min((unsigned long long)kVTile, n - min(n, base));
+  for (unsigned j = t; j < n_here; j += kVThreads) {
+    const unsigned long long k = s_key[j];
+    const unsigned d = digit(k, p, pass);
+    const unsigned long long pos = (unsigned long long)s_base[d] + (j - s_lbase[d]);
+    if (pos < n) dst[pos] = k;
   }
 }
 

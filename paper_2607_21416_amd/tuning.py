@@ -12,7 +12,10 @@ Search, by coordinate descent on the measured time:
   3. forward and backward grid sizes (workgroups per CU), each on its own kernel.
 Choices are cached per workload signature (scene kind, views and their resolutions,
 Gaussian and anchor counts, loss); set GLAM_TUNE_CACHE to a file path to keep them
-across processes.
+across processes.  Choices measured earlier ship in tune_choices.json beside this file
+and are used when neither cache holds the workload; use_cache=False measures afresh.
+The returned choice names where it came from under "source" ("measured", "cache",
+"stored").
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ BWD_BLOCKS = (4, 5, 6)
 DEFAULT = {"tile": TILE, "long_log2": 10, "fwd_blocks_per_cu": 5, "bwd_blocks_per_cu": 6}
 
 _cache: dict = {}
+STORED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_choices.json")
 
 
 def workload_key(scene: dict) -> str:
@@ -50,6 +54,13 @@ def _load_disk() -> dict:
     if path and os.path.exists(path):
         with open(path) as f:
             return json.load(f)
+    return {}
+
+
+def _load_stored() -> dict:
+    if os.path.exists(STORED):
+        with open(STORED) as f:
+            return {k: v for k, v in json.load(f).items() if not k.startswith("_")}
     return {}
 
 
@@ -80,11 +91,15 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
     key = workload_key(scene)
     if use_cache:
         if key in _cache:
-            return dict(_cache[key])
+            return dict(_cache[key], source="cache")
         disk = _load_disk()
         if key in disk:
             _cache[key] = disk[key]
-            return dict(disk[key])
+            return dict(disk[key], source="cache")
+        stored = _load_stored()
+        if key in stored:
+            _cache[key] = stored[key]
+            return dict(stored[key], source="stored")
     say = log or (lambda msg: None)
     ms: dict = {}
     best = dict(DEFAULT)
@@ -148,7 +163,7 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
         disk = _load_disk()
         disk[key] = best
         _save_disk(disk)
-    return dict(best)
+    return dict(best, source="measured")
 
 
 def schedule(choice: dict) -> dict:

@@ -19,3 +19,17 @@ def test_schedule_and_defaults():
     assert set(s) == {"long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu"}
     assert s["long_log2"] in tuning.LONG_LOG2 and s["fwd_blocks_per_cu"] == max(tuning.FWD_BLOCKS)
     assert s["bwd_blocks_per_cu"] == max(tuning.BWD_BLOCKS)
+
+
+def test_stored_choices_are_valid_and_used():
+    stored = tuning._load_stored()
+    assert stored
+    for key, c in stored.items():
+        assert c["tile"] in tuning.TILES and c["long_log2"] in tuning.LONG_LOG2
+        assert c["fwd_blocks_per_cu"] in tuning.FWD_BLOCKS and c["bwd_blocks_per_cu"] in tuning.BWD_BLOCKS
+    # the benchmark workloads have a stored choice, returned without measuring (no GPU here)
+    for name in ("C3", "C4"):
+        scene = synth.config(name)
+        assert tuning.workload_key(scene) in stored
+        got = tuning.autotune(scene, device="cpu")
+        assert got["source"] in ("stored", "cache") and got["tile"] == stored[tuning.workload_key(scene)]["tile"]
