@@ -353,6 +353,27 @@ def main():
     del vg, vws
     log(f"bench: anchor growth {t_vox * 1e3:.1f} us for {nv} points onto {n_akeys} anchor voxels "
         f"({n_new} new voxels, {n_drop} points dropped)")
+    # its bookkeeping: the new anchors inserted at the end of the last partition in the
+    # four per-anchor arrays and the six Adam moments of config 3 (into scratch copies)
+    F3 = pipe.anchors.F
+    at3 = A3  # config 3 has one partition: its end is the end of the arrays
+    lay = [(pipe.params["pos"], 3, 1, gcen), (pipe.params["feat"], 1, F3, None), (pipe.params["log_scale"], 1, 1, None),
+           (pipe.params["offs"], 3, K3, None)]
+    lay += [(pipe.opt_m[k], r, w, None) for k, r, w in (("feat", 1, F3), ("offs", 3, K3), ("log_scale", 1, 1))]
+    lay += [(pipe.opt_v[k], r, w, None) for k, r, w in (("feat", 1, F3), ("offs", 3, K3), ("log_scale", 1, 1))]
+    outs = [torch.empty(r * (A3 + n_new) * w, device=dev) for _, r, w, _ in lay]
+    ins_bytes = sum(4 * r * w * (2 * A3 + n_new) + (4 * r * w * n_new if i is not None else 0) for _, r, w, i in lay)
+
+    def insert_all():
+        for (src, r, w, ins), dst in zip(lay, outs):
+            binding.glam_insert_rows(src, dst, r, A3, w, at3, n_new, ins, nv if ins is not None else 0, 0.0,
+                                     torch.cuda.current_stream())
+
+    istep, ig = make_graph(torch, lambda: [insert_all() for _ in range(10)], True)
+    t_ins = timed(torch, istep, 3, stream) / 10
+    del ig, outs
+    log(f"bench: growth bookkeeping {t_ins * 1e3:.1f} us ({len(lay)} arrays, {A3} + {n_new} anchors, "
+        f"{ins_bytes / (t_ins * 1e-3) / 1e12:.2f} TB/s)")
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * 262144, device=dev)
@@ -384,7 +405,9 @@ def main():
         "anchor_growth": {"workload": f"{nv} fused points (triangulated flow points, NaN where rejected, and "
                                       f"2000 tracked points), 1 mm voxels, onto {n_akeys} anchor voxels",
                           "us": round(t_vox * 1e3, 2), "new_voxels": n_new, "dropped": n_drop,
-                          "points_per_s": round(nv / (t_vox * 1e-3), 1)},
+                          "points_per_s": round(nv / (t_vox * 1e-3), 1),
+                          "bookkeeping_us": round(t_ins * 1e3, 2),
+                          "bookkeeping_hbm_TBs": round(ins_bytes / (t_ins * 1e-3) / 1e12, 2)},
         "loop_closure": {"workload": f"{A3} anchors (K = {K3} offsets), {len(fixes)} corrected keyframes",
                          "us": round(t_def * 1e3, 2), "anchors_in_a_frustum": moved},
         "with_optimizer": {"ms_per_step": round(t_opt, 4), "iterations_per_s": round(n_views * 1000.0 / t_opt, 2),

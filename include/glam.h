@@ -15,6 +15,7 @@
  *   glam_deform_anchors    loop-closure correction of the anchor grid (Eq. 7)
  *   glam_epipolar_triangulate  flow correspondences: epipolar filter, triangulation (Eq. 5)
  *   glam_voxelize    fused points -> unique voxels, those not yet anchors (Eq. 4)
+ *   glam_insert_rows the growth's bookkeeping: new anchors inserted into per-anchor arrays
  *
  * Conventions shared by every call:
  *  - Array arguments are DEVICE pointers owned by the caller; the library never
@@ -430,6 +431,23 @@ glam_status glam_voxelize(const float* points, int64_t n_points, float eps,
                           float* new_centres, int64_t capacity, uint64_t* merged,
                           int64_t* counts, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
+
+/* The bookkeeping of anchor growth (Sec. III-A): anchors are stored grouped by
+   partition (Eq. 6), so the anchors a keyframe adds are inserted at the end of its
+   partition's range in every per-anchor array (and in the optimiser's moments), and the
+   later partitions' ranges shift by n_new.  Copies rows rows of n_old * width floats
+   from src to dst rows of (n_old + n_new) * width floats, inserting n_new * width floats
+   at float at * width of each row (0 <= at <= n_old): taken from ins (rows rows of
+   n_new * width floats starting ins_stride >= n_new * width floats apart, device, may be
+   NULL: the centres glam_voxelize writes have ins_stride = its capacity) or, without
+   ins, all equal to fill.  The
+   layouts of the library's anchors are of this form: pos and offs [3][...] (rows 3,
+   width 1 and K), feat [A][F] and log_scale [A] (rows 1, width F and 1).  src, dst
+   device, 16-byte aligned, not overlapping; rows <= 65535.  The caller updates its
+   partition offsets. */
+glam_status glam_insert_rows(const float* src, float* dst, int32_t rows, int64_t n_old,
+                             int32_t width, int64_t at, int64_t n_new, const float* ins,
+                             int64_t ins_stride, float fill, hipStream_t stream);
 
 #ifdef __cplusplus
 }

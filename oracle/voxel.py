@@ -21,9 +21,14 @@ around known lattice points recover exactly those lattice points; ties at half-i
 go to the even neighbour; every point lies within half a voxel of its voxel's centre
 and every voxel holds a point; re-voxelising the centres is the identity; growth is a
 set difference whose union with the existing keys equals the voxels of the union of
-the clouds; keys sort as (x, y, z) tuples.
+the clouds; keys sort as (x, y, z) tuples.  grow_anchors (the bookkeeping) is pinned by
+its invariants (old anchors keep their values, offsets and partition; the new ones
+close their partition's range; offsets shift); the new anchors' initial values (zero
+features and offsets, log-scale ln eps) are a stated definition: parity unpinned.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -70,3 +75,25 @@ def voxelize(points, eps, existing=None):
     new = np.array(sorted(voxels - have), np.uint64)
     grown = np.array(sorted(voxels | have), np.uint64)
     return new, centres(new, eps), grown, dropped
+
+
+def grow_anchors(pos, feat, log_scale, offs, part_begin, partition, centres, eps):
+    """Growth bookkeeping (Sec. III-A with the partitions of Eq. 6): the new anchors at
+    the voxel centres [3][n] join `partition`, inserted at the end of its range of the
+    partition-grouped arrays pos [3][A], feat [A][F], log_scale [A], offs [3][A*K];
+    initialised as an anchor created from points (zero features and offsets, log-scale
+    ln(eps)).  Returns the grown arrays and the shifted partition offsets."""
+    c = np.asarray(centres, np.float32)
+    n = c.shape[1]
+    A = pos.shape[1]
+    K = offs.shape[1] // A if A else 0
+    at = int(part_begin[partition + 1])
+    F = feat.shape[1]
+    pos2 = np.concatenate([pos[:, :at], c, pos[:, at:]], axis=1)
+    feat2 = np.concatenate([feat[:at], np.zeros((n, F), feat.dtype), feat[at:]], axis=0)
+    ln_eps = np.float32(math.log(float(np.float32(eps))))  # natural log in double, rounded once
+    ls2 = np.concatenate([log_scale[:at], np.full(n, ln_eps, log_scale.dtype), log_scale[at:]])
+    offs2 = np.concatenate([offs[:, :at * K], np.zeros((3, n * K), offs.dtype), offs[:, at * K:]], axis=1)
+    pb = np.asarray(part_begin, np.int64).copy()
+    pb[partition + 1:] += n
+    return pos2, feat2, ls2, offs2, pb

@@ -331,5 +331,22 @@ glam_status glam_voxelize(const float* points, int64_t n_points, float eps, cons
                                counts, workspace, stream);
 }
 
+glam_status glam_insert_rows(const float* src, float* dst, int32_t rows, int64_t n_old, int32_t width, int64_t at,
+                             int64_t n_new, const float* ins, int64_t ins_stride, float fill, hipStream_t stream) {
+  if (rows < 0 || rows > 65535 || n_old < 0 || width < 0 || n_new < 0 || at < 0 || at > n_old)
+    return GLAM_ERR_INVALID_ARG;
+  if (ins && ins_stride < n_new * (long long)width) return GLAM_ERR_INVALID_ARG;
+  const long long len_old = n_old * (long long)width, len_new = (n_old + n_new) * (long long)width;
+  if (len_new >= (1ll << 31)) return GLAM_ERR_UNSUPPORTED;
+  if (rows > 0 && len_new > 0) {
+    if (!ok_ptr(dst) || (len_old > 0 && !ok_ptr(src)) || (ins && !aligned16(ins))) return GLAM_ERR_INVALID_ARG;
+    // src and dst must not overlap (the copy is not ordered)
+    const char *s0 = reinterpret_cast<const char*>(src), *d0 = reinterpret_cast<const char*>(dst);
+    const size_t sb = 4ull * rows * len_old, db = 4ull * rows * len_new;
+    if (len_old > 0 && s0 < d0 + db && d0 < s0 + sb) return GLAM_ERR_INVALID_ARG;
+  }
+  return glam::launch_insert_rows(src, dst, rows, n_old, width, at, n_new, ins, ins_stride, fill, stream);
+}
+
 }  // extern "C"
 

@@ -69,5 +69,7 @@ size_t voxelize_workspace(long long n);
 glam_status launch_voxelize(const float* points, long long n, float eps, const uint64_t* existing,
                             long long n_existing, uint64_t* new_keys, float* new_pos, long long capacity,
                             uint64_t* merged, int64_t* counts, void* ws, hipStream_t s);
+glam_status launch_insert_rows(const float* src, float* dst, int rows, long long n_old, int width, long long at,
+                               long long n_new, const float* ins, long long ins_stride, float fill, hipStream_t s);
 
 }  // namespace glam

@@ -544,7 +544,37 @@ VoxLayout vox_layout(long long n) {
   return L;
 }
 
+// Growth bookkeeping: rows of per-anchor entries widened by n_new anchors inserted at
+// anchor `at` (the end of the partition that receives them).  One thread per output
+// float; rows of the source and the inserted block are read contiguously.
+__global__ void __launch_bounds__(256) insert_rows_kernel(const float* src, float* dst, long long n_old, int width,
+                                                          long long at, long long n_new, const float* ins,
+                                                          long long ins_stride, float fill) {
+  const long long len_new = (n_old + n_new) * width;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len_new) return;
+  const int r = blockIdx.y;
+  const long long lo = at * width, hi = (at + n_new) * width;
+  float v;
+  if (i < lo)
+    v = src[(long long)r * n_old * width + i];
+  else if (i >= hi)
+    v = src[(long long)r * n_old * width + i - n_new * width];
+  else
+    v = ins ? ins[(long long)r * ins_stride + (i - lo)] : fill;
+  dst[(long long)r * len_new + i] = v;
+}
+
 }  // namespace
+
+glam_status launch_insert_rows(const float* src, float* dst, int rows, long long n_old, int width, long long at,
+                               long long n_new, const float* ins, long long ins_stride, float fill, hipStream_t s) {
+  const long long len_new = (n_old + n_new) * width;
+  if (rows == 0 || len_new == 0) return GLAM_OK;
+  hipLaunchKernelGGL(insert_rows_kernel, dim3((unsigned)((len_new + 255) / 256), (unsigned)rows), dim3(256), 0, s,
+                     src, dst, n_old, width, at, n_new, ins, ins_stride, fill);
+  return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
+}
 
 size_t voxelize_workspace(long long n) { return vox_layout(n).bytes; }
 

@@ -9,6 +9,7 @@ torch.autograd.Functions.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 import torch
@@ -101,6 +102,7 @@ class Pipeline:
             self.flags |= B.GLAM_OPACITY_SIGMOID
         self.ssim_weight = float(scene.get("ssim_weight", 0.0))
         cams = scene["cams"]
+        self.tile = int(tile)
         if self.plain:
             G = scene["mean"].shape[1]
             self.vt = ViewTable(cams, dev, plain_G=G, tile=tile)
@@ -110,26 +112,10 @@ class Pipeline:
                                      self.params["rgb"].data_ptr(), G)
             self.n_parts = 0
         else:
-            F, K = scene["F"], scene["K"]
-            self.vt = ViewTable(cams, dev, part_begin=scene["part_begin"], K=K, tile=tile)
             self.params = {k: _f32(scene[k], dev) for k in ("pos", "feat", "log_scale", "offs", "mlp")}
-            A = scene["feat"].shape[0]
-            self.anchors = B.Anchors(self.params["pos"].data_ptr(), self.params["feat"].data_ptr(),
-                                     self.params["log_scale"].data_ptr(), self.params["offs"].data_ptr(), A, F, K,
-                                     scene["hidden"])
+            self.part_begin = np.asarray(scene["part_begin"], np.int64).copy()
             self.n_parts = scene["mlp"].shape[0]
-            n = self.vt.n_gauss
-            self.dec = {k: torch.empty((r, n) if r > 1 else (n,), device=dev, dtype=torch.float32)
-                        for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
-            self.gauss = B.Gaussians(*(self.dec[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "rgb")),
-                                     n)
-        n = self.vt.n_gauss
-        self.proj_t = dict(uv=torch.empty((2, n), device=dev), conic=torch.empty((3, n), device=dev),
-                           depth=torch.empty(n, device=dev), ext=torch.empty((2, n), device=dev),
-                           ntiles=torch.empty(n, device=dev, dtype=torch.int32),
-                           splat=torch.empty((n, 12), device=dev))
-        self.proj = B.Projected(*(self.proj_t[k].data_ptr() for k in ("uv", "conic", "depth", "ext", "ntiles",
-                                                                     "splat")))
+            self._anchor_views()
         npix = self.vt.n_pix
         self.image = torch.empty(3 * npix, device=dev)
         self.T_final = torch.empty(npix, device=dev)
@@ -142,6 +128,34 @@ class Pipeline:
         self.bg[:3] = torch.tensor(bg, dtype=torch.float32)
         self.ws_loss = torch.empty(B.glam_loss_workspace_bytes(self.vt.views), device=dev, dtype=torch.uint8)
         self.status = torch.zeros(8, device=dev, dtype=torch.int32)
+        self._alloc_gauss_buffers(capacity)
+
+    def _anchor_views(self):
+        """View table, anchor descriptor and decoded-Gaussian buffers for the current
+        anchors and partition ranges."""
+        dev = self.device
+        F, K = self.scene["F"], self.scene["K"]
+        self.vt = ViewTable(self.scene["cams"], dev, part_begin=self.part_begin, K=K, tile=self.tile)
+        A = self.params["feat"].shape[0]
+        self.anchors = B.Anchors(self.params["pos"].data_ptr(), self.params["feat"].data_ptr(),
+                                 self.params["log_scale"].data_ptr(), self.params["offs"].data_ptr(), A, F, K,
+                                 self.scene["hidden"])
+        n = self.vt.n_gauss
+        self.dec = {k: torch.empty((r, n) if r > 1 else (n,), device=dev, dtype=torch.float32)
+                    for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
+        self.gauss = B.Gaussians(*(self.dec[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "rgb")), n)
+
+    def _alloc_gauss_buffers(self, capacity: int | None):
+        """Buffers sized by the view-Gaussian count: projection, pairs, gradients and the
+        decode adjoint's workspace."""
+        dev = self.device
+        n = self.vt.n_gauss
+        self.proj_t = dict(uv=torch.empty((2, n), device=dev), conic=torch.empty((3, n), device=dev),
+                           depth=torch.empty(n, device=dev), ext=torch.empty((2, n), device=dev),
+                           ntiles=torch.empty(n, device=dev, dtype=torch.int32),
+                           splat=torch.empty((n, 12), device=dev))
+        self.proj = B.Projected(*(self.proj_t[k].data_ptr() for k in ("uv", "conic", "depth", "ext", "ntiles",
+                                                                     "splat")))
         self._alloc_bins(capacity if capacity else max(1024, 4 * n))
         # gradients
         self.g2d = torch.empty((n, 9), device=dev)
@@ -167,6 +181,55 @@ class Pipeline:
             self.ws_dec = torch.empty(max(16, nb), device=dev, dtype=torch.uint8)
 
     # ------------------------------------------------------------------------------
+    def grow_anchors(self, centres, n_new: int, partition: int, eps: float, centres_stride: int | None = None):
+        """Anchor growth at a keyframe (Eq. 4 and its bookkeeping): n_new anchors at the
+        voxel centres (device rows x, y, z of centres_stride floats each, by default
+        centres.shape[1]; glam_voxelize's new_centres with its capacity as stride) join
+        `partition`, inserted at the end of its range of every per-anchor array, as
+        anchors created from points: zero features and offsets, log-scale ln(eps), zero
+        Adam moments.  Later partitions' ranges shift; the view table and every buffer
+        sized by the view-Gaussian count are rebuilt (the pair capacity keeps its slack
+        rule through fit_capacity).  Runs on the current stream."""
+        if self.plain:
+            raise ValueError("anchor growth needs an anchor scene")
+        n_new = int(n_new)
+        if n_new <= 0:
+            return
+        if not 0 <= partition < self.n_parts:
+            raise ValueError(f"partition {partition} out of range [0, {self.n_parts})")
+        s = self.stream()
+        A, F, K = self.anchors.A, self.anchors.F, self.anchors.K
+        at = int(self.part_begin[partition + 1])
+        stride = int(centres.shape[1] if centres_stride is None else centres_stride)
+        ln_eps = math.log(float(np.float32(eps)))
+        layout = {"pos": (3, 1), "feat": (1, F), "log_scale": (1, 1), "offs": (3, K)}
+
+        def grow(t, name, ins=None, fill=0.0):
+            rows, width = layout[name]
+            if name == "feat":
+                out = t.new_empty((A + n_new, F))
+            elif rows == 1:
+                out = t.new_empty(A + n_new)
+            else:
+                out = t.new_empty((3, (A + n_new) * width))
+            B.glam_insert_rows(t, out, rows, A, width, at, n_new, ins, stride if ins is not None else 0, fill, s)
+            return out
+
+        self.params["pos"] = grow(self.params["pos"], "pos", centres)
+        self.params["feat"] = grow(self.params["feat"], "feat")
+        self.params["log_scale"] = grow(self.params["log_scale"], "log_scale", fill=ln_eps)
+        self.params["offs"] = grow(self.params["offs"], "offs")
+        if hasattr(self, "opt_m"):
+            for k in ("feat", "offs", "log_scale"):
+                self.opt_m[k] = grow(self.opt_m[k], k)
+                self.opt_v[k] = grow(self.opt_v[k], k)
+        self.part_begin[partition + 1:] += n_new
+        self._anchor_views()
+        self._alloc_gauss_buffers(None)
+        if hasattr(self, "opt_groups"):
+            self.opt_groups = self._adam_groups()
+
+    # ------------------------------------------------------------------------------
     def _alloc_bins(self, capacity: int):
         dev = self.device
         self.capacity = int(capacity)
@@ -185,7 +248,15 @@ class Pipeline:
         """Adam state (zeroed moments) and the parameter groups of glam_adam_step: the
         anchors' features, offsets and log-scales and the MLP sets (one group, a segment
         per MLP), or the plain Gaussians' parameters.  Anchor positions stay fixed."""
-        dev = self.device
+        names = list(ADAM_LR_PLAIN) if self.plain else list(ADAM_LR_ANCHOR)
+        self.opt_m = {k: torch.zeros_like(self.params[k]) for k in names}
+        self.opt_v = {k: torch.zeros_like(self.params[k]) for k in names}
+        self.opt_t = 0
+        self.opt_groups = self._adam_groups()
+
+    def _adam_groups(self):
+        """glam_adam_step's parameter groups over the current parameter, gradient and
+        moment tensors."""
         if self.plain:
             names, lrs = list(ADAM_LR_PLAIN), ADAM_LR_PLAIN
             grads = {"mean": self.dg["mean"], "log_scale": self.dg["log_scale"], "quat": self.dg["quat"],
@@ -193,9 +264,6 @@ class Pipeline:
         else:
             names, lrs = list(ADAM_LR_ANCHOR), ADAM_LR_ANCHOR
             grads = self.pgrad
-        self.opt_m = {k: torch.zeros_like(self.params[k]) for k in names}
-        self.opt_v = {k: torch.zeros_like(self.params[k]) for k in names}
-        self.opt_t = 0
         groups = (B.AdamGroup * len(names))()
         for i, k in enumerate(names):
             g = groups[i]
@@ -216,7 +284,7 @@ class Pipeline:
             else:
                 g.period, g.n_seg = 1, 1  # one learning rate for the whole array
                 g.seg_end[0], g.lr[0] = 1, lrs[k]
-        self.opt_groups = groups
+        return groups
 
     def adam_step(self, s=None, step: int | None = None):
         """The optimiser step after a backward (step number: the next one by default)."""

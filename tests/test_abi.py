@@ -171,6 +171,28 @@ def test_voxelize_rejects_before_launch():
     assert call(ws=None) == B.GLAM_ERR_WORKSPACE
 
 
+def test_insert_rows_rejects_before_launch():
+    lib = B.load()
+    fake = 0x100000
+    P = C.c_void_p
+    ok = dict(src=fake, dst=fake + (1 << 24), rows=3, n_old=100, width=2, at=50, n_new=10, ins=None, stride=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.glam_insert_rows(P(a["src"]) if a["src"] else None, P(a["dst"]) if a["dst"] else None, a["rows"],
+                                    a["n_old"], a["width"], a["at"], a["n_new"], P(a["ins"]) if a["ins"] else None,
+                                    a["stride"], 0.0, None)
+
+    assert call(at=101) == B.GLAM_ERR_INVALID_ARG  # beyond the end
+    assert call(at=-1) == B.GLAM_ERR_INVALID_ARG
+    assert call(rows=70000) == B.GLAM_ERR_INVALID_ARG
+    assert call(dst=fake + 16) == B.GLAM_ERR_INVALID_ARG  # overlaps the source
+    assert call(dst=fake + (1 << 24) + 4) == B.GLAM_ERR_INVALID_ARG  # misaligned
+    assert call(ins=fake + (1 << 26), stride=19) == B.GLAM_ERR_INVALID_ARG  # rows of ins shorter than 20
+    assert call(src=None) == B.GLAM_ERR_INVALID_ARG
+    assert call(n_old=1 << 30, at=0, width=4) == B.GLAM_ERR_UNSUPPORTED
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libglam.so"))

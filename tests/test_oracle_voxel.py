@@ -162,3 +162,34 @@ def test_fp32_decision_at_near_ties():
     # rounding the exact quotient instead would move some of them
     exact_k = [round(Fraction(c) / Fraction(float(eps))) for c in cand]
     assert exact_k != k[0].tolist()
+
+
+def test_growth_bookkeeping():
+    rng = np.random.default_rng(12)
+    A, F, K = 40, 5, 3
+    part_begin = [0, 15, 15, 32, 40]  # an empty partition too
+    pos = rng.normal(size=(3, A)).astype(np.float32)
+    feat = rng.normal(size=(A, F)).astype(np.float32)
+    ls = rng.normal(size=A).astype(np.float32)
+    offs = rng.normal(size=(3, A * K)).astype(np.float32)
+    cen = rng.normal(size=(3, 6)).astype(np.float32)
+    for part in range(4):
+        pos2, feat2, ls2, offs2, pb = V.grow_anchors(pos, feat, ls, offs, part_begin, part, cen, 0.25)
+        at = part_begin[part + 1]
+        assert pb.tolist() == [b + (6 if i > part else 0) for i, b in enumerate(part_begin)]
+        # every old anchor keeps its values (and its K offsets) at its new index
+        new_idx = [a if a < at else a + 6 for a in range(A)]
+        assert np.array_equal(pos2[:, new_idx], pos) and np.array_equal(feat2[new_idx], feat)
+        assert np.array_equal(ls2[new_idx], ls)
+        o2 = offs2.reshape(3, A + 6, K)
+        assert np.array_equal(o2[:, new_idx], offs.reshape(3, A, K))
+        # the new anchors close the partition's range, initialised from the points
+        assert np.array_equal(pos2[:, at:at + 6], cen)
+        assert (feat2[at:at + 6] == 0).all() and (o2[:, at:at + 6] == 0).all()
+        assert np.allclose(ls2[at:at + 6], np.log(0.25), rtol=1e-7)
+        # partition ranges: same anchors per partition, plus the new ones in `part`
+        for q in range(4):
+            old = pos[:, part_begin[q]:part_begin[q + 1]]
+            got = pos2[:, pb[q]:pb[q + 1]]
+            want = np.concatenate([old, cen], axis=1) if q == part else old
+            assert np.array_equal(got, want)
