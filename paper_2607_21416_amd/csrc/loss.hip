@@ -29,6 +29,12 @@ constexpr int kQ = kT + 2 * kR;      // 42: window centres touching the tile
 constexpr int kI = kT + 4 * kR;      // 52: inputs those windows read
 constexpr int kIS = kI + 1, kQS = kQ + 1, kTS = kT + 1;  // padded LDS row strides
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
+// 512 threads per workgroup: the LDS plan allows two workgroups per CU, so eight waves
+// per workgroup keep four per SIMD resident
+constexpr int kThreads = 512;
+constexpr int kRun4 = 4;                  // step 4: runs of 4 output columns
+constexpr int kRun5 = kT * kT / kThreads;  // step 5: rows per run (16 runs of 2 per column)
+static_assert((kThreads / kT) * kRun5 == kT && kRun5 >= 1, "step 5 covers the tile");
 
 // LDS plan (floats): region A holds the staged inputs, later the partial maps;
 // region B holds the row sums of the statistics, later the row sums of the partials.
@@ -38,12 +44,12 @@ static_assert(3 * kQ * kQS <= kA && 3 * kQ * kTS <= kB, "LDS aliasing");
 
 __device__ __forceinline__ float sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
 
-__global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, int max_t32, const float* image,
+__global__ void __launch_bounds__(kThreads) loss_kernel(const glam_view_info* views, int max_t32, const float* image,
                                                    const float* target, float w_ssim, float* dimage,
                                                    float* partial) {
   __shared__ float sA[kA];
   __shared__ float sB[kB];
-  __shared__ float s_red[2][8];
+  __shared__ float s_red[2][kThreads / 64];
   const glam_view_info vw = views[blockIdx.y];
   const int W = vw.cam.width, H = vw.cam.height;
   const int tx_n = (W + kT - 1) / kT, ty_n = (H + kT - 1) / kT;
@@ -64,11 +70,11 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
     float* sx = sA;
     float* sy = sA + kI * kIS;
     // all loads in flight before the first LDS store
-    constexpr int kLoads = (kI * kI + 255) / 256;
+    constexpr int kLoads = (kI * kI + kThreads - 1) / kThreads;
     float vx[kLoads], vy[kLoads];
 #pragma unroll
     for (int n = 0; n < kLoads; ++n) {
-      const int k = t + 256 * n;
+      const int k = t + kThreads * n;
       const int r = k / kI, j = k % kI;
       const int gx = x0 - 2 * kR + j, gy = y0 - 2 * kR + r;
       const bool in = k < kI * kI && gx >= 0 && gx < W && gy >= 0 && gy < H;
@@ -78,7 +84,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
     }
 #pragma unroll
     for (int n = 0; n < kLoads; ++n) {
-      const int k = t + 256 * n;
+      const int k = t + kThreads * n;
       if (k < kI * kI) {
         const int r = k / kI, j = k % kI;
         sx[r * kIS + j] = vx[n];
@@ -88,7 +94,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
     __syncthreads();
     // 2. row sums: 52 rows x 42 window columns, runs of 7 columns
     float* sH = sB;                  // [5][kI][kQS]
-    for (int task = t; task < kI * 6; task += 256) {
+    for (int task = t; task < kI * 6; task += kThreads) {
       const int r = task % kI, j0 = (task / kI) * 7;
       const float* rx = sx + r * kIS + j0;
       const float* ry = sy + r * kIS + j0;
@@ -161,9 +167,9 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
       }
     }
     __syncthreads();
-    // 4. row sums of the partials: 42 rows x 32 output columns, runs of 8
-    for (int task = t; task < kQ * 4; task += 256) {
-      const int i = task % kQ, j0 = (task / kQ) * 8;
+    // 4. row sums of the partials: 42 rows x 32 output columns, runs of 4
+    for (int task = t; task < kQ * (kT / kRun4); task += kThreads) {
+      const int i = task % kQ, j0 = (task / kQ) * kRun4;
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const float* row = sP + p * kQ * kQS + i * kQS + j0;
@@ -171,18 +177,18 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
 #pragma unroll
         for (int o = 0; o < kWin; ++o) acc += row[o];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < kRun4; ++m) {
           sHP[p * kQ * kTS + i * kTS + j0 + m] = acc;
-          if (m < 7) acc += row[m + kWin] - row[m];
+          if (m < kRun4 - 1) acc += row[m + kWin] - row[m];
         }
       }
     }
     __syncthreads();
   }
-  // 5. column sums of the partials and dL/dC: 32 output columns x runs of 4 rows
+  // 5. column sums of the partials and dL/dC: 32 output columns x runs of 2 rows
   const long long n_all = 3 * HW;
   const float inv_n = 1.f / (float)n_all;
-  const int jo = t % kT, io0 = (t / kT) * 4;
+  const int jo = t % kT, io0 = (t / kT) * kRun5;
   float pa = 0.f, pb = 0.f, pc = 0.f;
   if (w_ssim != 0.f) {
 #pragma unroll
@@ -194,9 +200,9 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
   }
   float l1 = 0.f;
   const int gx = x0 + jo;
-  float xs[4], ys[4];
+  float xs[kRun5], ys[kRun5];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < kRun5; ++m) {
     const int gy = y0 + io0 + m;
     const bool in = gx < W && gy < H;
     const long long o = in ? (long long)gy * W + gx : 0;
@@ -204,7 +210,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
     ys[m] = in ? yp[o] : 0.f;
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < kRun5; ++m) {
     const int io = io0 + m, gy = y0 + io;
     if (gx < W && gy < H) {
       const long long o = (long long)gy * W + gx;
@@ -215,7 +221,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
       if (w_ssim != 0.f) g -= w_ssim * inv_n * (1.f / 121.f) * (pa + 2.f * xv * pb + yv * pc);
       dimage[3 * vw.pix_begin + c * HW + o] = g;
     }
-    if (w_ssim != 0.f && m < 3) {
+    if (w_ssim != 0.f && m < kRun5 - 1) {
       pa += sHP[(io + kWin) * kTS + jo] - sHP[io * kTS + jo];
       pb += sHP[kQ * kTS + (io + kWin) * kTS + jo] - sHP[kQ * kTS + io * kTS + jo];
       pc += sHP[2 * kQ * kTS + (io + kWin) * kTS + jo] - sHP[2 * kQ * kTS + io * kTS + jo];
@@ -228,7 +234,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const glam_view_info* views, 
   __syncthreads();
   if (t == 0) {
     float a = 0.f, b = 0.f;
-    for (int w = 0; w < 4; ++w) { a += s_red[0][w]; b += s_red[1][w]; }
+    for (int w = 0; w < kThreads / 64; ++w) { a += s_red[0][w]; b += s_red[1][w]; }
     float* pp = partial + 2 * (((long long)blockIdx.y * max_t32 + t32) * 3 + c);
     pp[0] = a;
     pp[1] = b;
@@ -282,7 +288,7 @@ glam_status launch_loss(const glam_views& v, const float* image, const float* ta
   if (v.n_tiles == 0 || v.n == 0) return GLAM_OK;
   const int mt = max_tiles32(v);
   float* partial = static_cast<float*>(ws);
-  hipLaunchKernelGGL(loss_kernel, dim3((unsigned)mt, (unsigned)v.n, 3), dim3(256), 0, s, v.dev, mt, image, target,
+  hipLaunchKernelGGL(loss_kernel, dim3((unsigned)mt, (unsigned)v.n, 3), dim3(kThreads), 0, s, v.dev, mt, image, target,
                      w_ssim, dimage, partial);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, mt, partial, w_ssim, loss);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
