@@ -515,46 +515,69 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Two values folded at once within each 16-lane row: a DPP move with a bank mask (a bank
-// is four lanes of a row) writes only the enabled banks, so two moves and an add leave
-// a + a(partner) in banks BANKS and b + b(partner) in the others.
-template <int CTRL, int BANKS>
-__device__ __forceinline__ float pair_fold(float a, float b) {
-  const int t = __builtin_amdgcn_update_dpp(__float_as_int(b), __float_as_int(a), CTRL, 0xf, BANKS, false);
-  const int u = __builtin_amdgcn_update_dpp(__float_as_int(a), __float_as_int(b), CTRL, 0xf, 0xf ^ BANKS, false);
-  return __int_as_float(t) + __int_as_float(u);
+// Per-Gaussian reduction of the nine gradient terms, split in two.  Per hit, two
+// lane-swap stages fold the nine per-lane values to partial sums over four lanes: each
+// of x0 and x1 then holds four components, one per 16-lane row, and x2 the ninth in
+// its first row.  Those 144 words go to a wave-private LDS slot with the Gaussian's
+// index.  Every kFlush hits one flush sums each (hit, component) row of 16 words in its
+// own lane and issues all their atomics with one instruction: the per-hit DPP folding
+// and its wait states are replaced by one LDS store per register.
+constexpr int kFlush = 4;         // hits staged per flush (9 kFlush lanes flush)
+constexpr int kStageWords = 144;  // x0 and x1 (64 lanes each), the first row of x2
+struct GradStage {
+  float v[kFlush][kStageWords];
+  uint32_t gid[kFlush];
+};
+static_assert(9 * kFlush <= 64, "one flush lane per (hit, component)");
+
+// Offset in a slot of the row holding component lane % 9 after the swap stages: the
+// stages are applied to component tags (the swaps move whole rows or half-waves, so a
+// row holds one component), and the row whose tag matches is looked up.
+__device__ __forceinline__ int stage_offset(int lane) {
+  const uint32_t none = 0xffffffffu, c = (uint32_t)(lane % 9);
+  const uint32_t x0 = swap16_first(swap32_first(0, 1), swap32_first(2, 3));
+  const uint32_t x1 = swap16_first(swap32_first(4, 5), swap32_first(6, 7));
+  const uint32_t x2 = swap16_first(swap32_first(8, none), none);
+  int off = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if ((uint32_t)__builtin_amdgcn_readlane((int)x0, 16 * r) == c) off = 16 * r;
+    if ((uint32_t)__builtin_amdgcn_readlane((int)x1, 16 * r) == c) off = 64 + 16 * r;
+  }
+  if ((uint32_t)__builtin_amdgcn_readlane((int)x2, 0) == c) off = 128;
+  return off;
 }
 
-constexpr int kRowMirror = 0x140, kHalfMirror = 0x141, kQuadSwap2 = 0x4e, kQuadSwap1 = 0xb1;
-
-// Component of the total that reduce9 leaves in this lane, or -1: the swaps applied to
-// the value tags (each swap moves whole rows or half-waves, so a lane's two swap outputs
-// always belong to one component, whatever half goes where), then the row stage, which
-// leaves in the first lane of banks 0, 2 and 1 of a row its x0, x1 and x2.
-__device__ __forceinline__ int reduce9_comp() {
-  const uint32_t none = 0xffffffffu;
-  const uint32_t w0 = swap32_first(0, 1), w1 = swap32_first(2, 3), w2 = swap32_first(4, 5), w3 = swap32_first(6, 7),
-                 w4 = swap32_first(8, none);
-  const uint32_t x0 = swap16_first(w0, w1), x1 = swap16_first(w2, w3), x2 = swap16_first(w4, none);
-  const int bank = (threadIdx.x >> 2) & 3;
-  if (threadIdx.x & 3) return -1;
-  return bank == 0 ? (int)x0 : (bank == 2 ? (int)x1 : (bank == 1 ? (int)x2 : -1));
+// Sums and adds the n staged hits (lane 9 h + c: component c of hit h).  The wave must
+// be fully active.
+__device__ __forceinline__ void stage_flush(GradStage& G, int n, int off, int lane, float* g2d) {
+  __builtin_amdgcn_wave_barrier();
+  const int h = lane / 9, c = lane - 9 * (lane / 9);
+  if (h < n) {
+    const float4* p = reinterpret_cast<const float4*>(&G.v[h][off]);
+    const float4 a = p[0], b = p[1], d = p[2], e = p[3];
+    const float sum = (((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w))) +
+                      (((d.x + d.y) + (d.z + d.w)) + ((e.x + e.y) + (e.z + e.w)));
+    atomicAdd(&g2d[(size_t)G.gid[h] * 9 + c], sum);
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Sum of nine per-lane values over the wave, scattered so that nine lanes hold one total
-// each (reduce-scatter): two lane-swap stages, then within each row x0 and x1 folded
-// across the row's halves together, and the three values across each half together.
-// The wave must be fully active.
-__device__ __forceinline__ float reduce9(const float v[9]) {
+// Stages one hit's nine per-lane values (a fully active wave); flushes when full.
+__device__ __forceinline__ void stage_hit(const float v[9], uint32_t gid, GradStage& G, int& nst, int off, int lane,
+                                          float* g2d) {
   const float w0 = swap32_sum(v[0], v[1]), w1 = swap32_sum(v[2], v[3]), w2 = swap32_sum(v[4], v[5]),
               w3 = swap32_sum(v[6], v[7]), w4 = swap32_sum(v[8], 0.f);
   const float x0 = swap16_sum(w0, w1), x1 = swap16_sum(w2, w3), x2 = swap16_sum(w4, 0.f);
-  const float y = pair_fold<kRowMirror, 0x3>(x0, x1);  // row lanes 0-7: x0, 8-15: x1
-  const float z = x2 + dpp<kRowMirror>(x2);
-  float t = pair_fold<kHalfMirror, 0x5>(y, z);  // banks 0, 2: x0, x1; banks 1, 3: x2
-  t += dpp<kQuadSwap2>(t);
-  t += dpp<kQuadSwap1>(t);
-  return t;
+  float* sl = G.v[nst];
+  sl[lane] = x0;
+  sl[64 + lane] = x1;
+  if (lane < 16) sl[128 + lane] = x2;
+  if (lane == 0) G.gid[nst] = gid;
+  if (++nst == kFlush) {
+    stage_flush(G, kFlush, off, lane, g2d);
+    nst = 0;
+  }
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -579,8 +602,8 @@ struct BwdState {
 // lo; compacted into L with the Gaussian's index as tag) in reverse order: per hit
 // T_i = T_{i+1} / (1 - alpha_i), the nine gradient terms, one reduction and one atomic
 // per Gaussian, then the colour behind.
-__device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, float px, float py, int comp,
-                                         BwdState& st, float* g2d) {
+__device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, float px, float py, int lane,
+                                         GradStage& G, int& nst, int off, BwdState& st, float* g2d) {
   const int nhit = __popcll(hm);
   // the entry offset of hit i is the position of the i-th set bit of the mask
   uint64_t rem = hm;
@@ -617,15 +640,15 @@ __device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, 
     v[6] = st.g0 * wgt;
     v[7] = st.g1 * wgt;
     v[8] = st.g2 * wgt;
-    const float tot = reduce9(v);
-    if (comp >= 0) atomicAdd(&g2d[(size_t)__float_as_uint(bx.y) * 9 + comp], tot);
+    stage_hit(v, __float_as_uint(bx.y), G, nst, off, lane, g2d);
   }
 }
 
 // The reverse walk over range offsets [lo_end, hi) (from hi - 1 down), relative to the
 // range start s, in batches of 64 with a register prefetch of the next batch.
 __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, int lo_end, int hi, uint32_t n_gauss,
-                         const Item& it, WaveLds& L, int lane, int comp, BwdState& st, float* g2d) {
+                         const Item& it, WaveLds& L, int lane, GradStage& G, int& nst, int off, BwdState& st,
+                         float* g2d) {
   if (!it.live || hi <= lo_end) return;
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   Rec nxt;
@@ -637,7 +660,7 @@ __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, i
     const uint32_t cgid = ngid;
     if (lo > lo_end) fetch_batch(splat, vals, s + max(lo_end, lo - 64), s + lo, n_gauss, lane, nxt, ngid);
     const uint64_t hm = compact_hits(cur, lo + lane < bh, __uint_as_float(cgid), it, L, lane);
-    bwd_hits(L, hm, lo, px, py, comp, st, g2d);
+    bwd_hits(L, hm, lo, px, py, lane, G, nst, off, st, g2d);
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -696,7 +719,8 @@ __device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const 
 // A chunk is one gathered batch, compacted once for both passes; the next round's
 // records are fetched while the current round is walked.
 __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t n_gauss, const Item& it,
-                         WaveLds& L, RoundLds& R, int w, int lane, int comp, BwdState st, float* g2d) {
+                         WaveLds& L, RoundLds& R, int w, int lane, GradStage& G, int& nst, int off, BwdState st,
+                         float* g2d) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int top = it.live ? wave_max(st.last) : 0;  // the same in every wave
   Rec nxt;
@@ -730,7 +754,7 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
       cs.B1 = fmaf(Pj, cs.B1, R.v[j][2][lane]);
       cs.B2 = fmaf(Pj, cs.B2, R.v[j][3][lane]);
     }
-    bwd_hits(L, hm, c0, px, py, comp, cs, g2d);
+    bwd_hits(L, hm, c0, px, py, lane, G, nst, off, cs, g2d);
     // state in front of the round (identical in every wave)
     for (int j = 0; j < kWaves; ++j) {
       const float Pj = R.v[j][0][lane];
@@ -750,10 +774,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
     const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss) {
   __shared__ WaveLds lds[kWaves];
   __shared__ RoundLds round;
+  __shared__ GradStage stage[kWaves];
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveLds& L = lds[w];
-  const int comp = reduce9_comp();
+  GradStage& G = stage[w];
+  const int off = stage_offset(lane);
+  int nst = 0;  // staged hits of this wave (uniform)
   const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
   const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
   uint32_t* q = queue + kQueueWords;
@@ -764,7 +791,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
     const Item it = make_item(views, n_views, tile, (int)(li & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
-    bwd_long(splat, vals, s, n_gauss, it, L, round, w, lane, comp,
+    bwd_long(splat, vals, s, n_gauss, it, L, round, w, lane, G, nst, off,
              bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d);
   }
   __builtin_amdgcn_s_setprio(0);
@@ -776,8 +803,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
     const uint32_t s = min(ranges[2 * tile], e);
     BwdState st = bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage);
     const int top = it.live ? wave_max(st.last) : 0;
-    bwd_walk(splat, vals, s, 0, top, n_gauss, it, L, lane, comp, st, g2d);
+    bwd_walk(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, st, g2d);
   }
+  stage_flush(G, nst, off, lane, g2d);
   leave_queue(q, gridDim.x * kWaves, lane);
 }
 
