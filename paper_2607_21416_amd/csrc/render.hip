@@ -523,7 +523,7 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
 // own lane and issues all their atomics with one instruction: the per-hit DPP folding
 // and its wait states are replaced by one LDS store per register.
 constexpr int kFlush = 4;         // hits staged per flush (9 kFlush lanes flush)
-constexpr int kStageWords = 144;  // x0 and x1 (64 lanes each), the first row of x2
+constexpr int kStageWords = 192;  // x0, x1 and x2 (64 lanes each; only x2's first row is read)
 struct GradStage {
   float v[kFlush][kStageWords];
   uint32_t gid[kFlush];
@@ -572,8 +572,8 @@ __device__ __forceinline__ void stage_hit(const float v[9], uint32_t gid, GradSt
   float* sl = G.v[nst];
   sl[lane] = x0;
   sl[64 + lane] = x1;
-  if (lane < 16) sl[128 + lane] = x2;
-  if (lane == 0) G.gid[nst] = gid;
+  sl[128 + lane] = x2;
+  G.gid[nst] = gid;  // the same value from every lane
   if (++nst == kFlush) {
     stage_flush(G, kFlush, off, lane, g2d);
     nst = 0;
