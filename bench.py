@@ -80,7 +80,8 @@ def stage_times(torch, pipe, iters):
     """Average duration of each C-ABI call of the step, HIP events on the stream the
     kernels run on (eager launches)."""
     s = torch.cuda.current_stream()
-    calls = [("decode", pipe.decode), ("project", pipe.project), ("bin_sort", pipe.bin_sort),
+    first = [("project", pipe.project)] if pipe.plain else [("decode_project", pipe.decode_project)]
+    calls = first + [("bin_sort", pipe.bin_sort),
              ("render_fwd", pipe.render), ("loss", pipe.compute_loss),
              ("composite_bwd", pipe.composite_bwd), ("project_bwd", pipe.project_bwd),
              ("decode_bwd", pipe.decode_bwd)]

@@ -6,6 +6,7 @@
  *   glam_decode      anchor features -> Gaussians, view-conditioned MLPs (Eq. 2) with
  *                    one MLP set per spatial partition (Eq. 6)
  *   glam_project     3-D Gaussians -> projected 2-D Gaussians + footprint boxes
+ *   glam_decode_project  the two above in one launch
  *   glam_bin_sort    (tile, depth) pairs, device radix sort, per-tile ranges
  *   glam_render_fwd  front-to-back alpha compositing per tile (Eq. 1)
  *   glam_loss        L1 + SSIM objective (Eq. 3) and its image gradient
@@ -222,6 +223,14 @@ size_t glam_bin_sort_workspace_bytes(const glam_views* views, int64_t capacity);
 glam_status glam_decode(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
                         const glam_views* views, uint32_t flags, glam_gaussians* out,
                         hipStream_t stream);
+
+/* glam_decode followed by glam_project in one launch: each decoded Gaussian is projected
+   from the registers that hold it (identical results to the two calls; saves re-reading
+   the decoded Gaussians).  Same arguments and errors as glam_decode, plus the projection
+   outputs proj (as glam_project). */
+glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
+                                const glam_views* views, uint32_t flags, glam_gaussians* out,
+                                glam_projected* proj, hipStream_t stream);
 
 /* Projection and footprint of every view-Gaussian.  Culls depth <= 0.2 and opacity
    <= 1/255; Jacobian x/z, y/z clamped to 1.15x the image (beyond a 0.15-image border);

@@ -25,7 +25,7 @@ EXPORTS = [
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
     "glam_epipolar_triangulate", "glam_voxelize_workspace_bytes", "glam_voxelize",
-    "glam_insert_rows",
+    "glam_insert_rows", "glam_decode_project",
 ]
 GLAM_ADAM_MAX_GROUPS = 16
 
@@ -130,6 +130,7 @@ def load():
         "glam_voxelize_workspace_bytes": (SZ, [I64]),
         "glam_voxelize": (I32, [P, I64, F32, P, I64, P, P, I64, P, P, P, SZ, P]),
         "glam_insert_rows": (I32, [P, P, I32, I64, I32, I64, I64, P, I64, F32, P]),
+        "glam_decode_project": (I32, [P, P, I32, P, U32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -290,3 +291,8 @@ def glam_voxelize(points, n_points, eps, existing, n_existing, new_keys, new_cen
 def glam_insert_rows(src, dst, rows, n_old, width, at, n_new, ins, ins_stride, fill, stream):
     return _check("glam_insert_rows", load().glam_insert_rows(ref(src), ref(dst), rows, n_old, width, at, n_new,
                                                               ref(ins), ins_stride, float(fill), _stream(stream)))
+
+
+def glam_decode_project(anchors, mlp, n_parts, views, flags, out, proj, stream):
+    return _check("glam_decode_project", load().glam_decode_project(ref(anchors), ref(mlp), n_parts, ref(views),
+                                                                    flags, ref(out), ref(proj), _stream(stream)))

@@ -157,7 +157,20 @@ glam_status glam_decode(const glam_anchors* anchors, const float* mlp, int32_t n
   if (!anchor_views_ok(anchors, views) || out->n != views->n_gauss || max_partition(views) >= n_parts)
     return GLAM_ERR_INVALID_ARG;
   if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
-  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, stream);
+  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, nullptr, stream);
+}
+
+glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
+                                const glam_views* views, uint32_t flags, glam_gaussians* out,
+                                glam_projected* proj, hipStream_t stream) {
+  if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(out, true) || n_parts <= 0 ||
+      !proj_ok(proj))
+    return GLAM_ERR_INVALID_ARG;
+  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if (!anchor_views_ok(anchors, views) || out->n != views->n_gauss || max_partition(views) >= n_parts)
+    return GLAM_ERR_INVALID_ARG;
+  if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
+  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, proj, stream);
 }
 
 glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, uint32_t flags, glam_projected* out,

@@ -23,6 +23,7 @@
 // views of the partition in registers, so every anchor is written exactly once.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "projection.hpp"
 
 namespace glam {
 
@@ -182,7 +183,8 @@ struct BwdGrid {
 template <int F, int K>
 __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const float* __restrict__ mlp,
                                                      const glam_view_info* views, int sigmoid_op, BwdGrid grid,
-                                                     glam_gaussians out) {
+                                                     glam_gaussians out, int fuse_project, int tl,
+                                                     glam_projected proj) {
   using C = Cfg<F, K>;
   constexpr LdsOff L = lds_offsets(F, K);
   extern __shared__ float smem[];
@@ -288,13 +290,20 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
         const float* y = s_y + ai * C::YS;
         const long long g = vw.g_begin + (long long)a * K + j;
         const float yo = y[j];
-        out.opacity[g] = sigmoid_op ? sigmoid(yo) : tanhf(yo);
-        for (int c3 = 0; c3 < 3; ++c3) out.rgb[c3 * n + g] = sigmoid(y[K + 3 * j + c3]);
-        for (int k = 0; k < 3; ++k) out.scale[k * n + g] = es[q] * sigmoid(y[4 * K + 7 * j + k]);
+        const float op = sigmoid_op ? sigmoid(yo) : tanhf(yo);
+        float rgb[3], sc[3], qn[4];
+        for (int c3 = 0; c3 < 3; ++c3) rgb[c3] = sigmoid(y[K + 3 * j + c3]);
+        for (int k = 0; k < 3; ++k) sc[k] = es[q] * sigmoid(y[4 * K + 7 * j + k]);
         const float* qv = y + 4 * K + 7 * j + 3;
         const float inv = 1.f / sqrtf(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3] + 1e-24f);
-        for (int k = 0; k < 4; ++k) out.quat[k * n + g] = qv[k] * inv;
+        for (int k = 0; k < 4; ++k) qn[k] = qv[k] * inv;
+        out.opacity[g] = op;
+        for (int c3 = 0; c3 < 3; ++c3) out.rgb[c3 * n + g] = rgb[c3];
+        for (int k = 0; k < 3; ++k) out.scale[k * n + g] = sc[k];
+        for (int k = 0; k < 4; ++k) out.quat[k * n + g] = qn[k];
         for (int i = 0; i < 3; ++i) out.mean[i * n + g] = mu[q][i];
+        // the projection of the Gaussian just decoded, from the same registers
+        if (fuse_project) project_one(vw.cam, mu[q], sc, qn, op, rgb, g, n, tl, proj);
       }
       // the next view's rows overwrite rows these outputs were read from
       wave_sync();
@@ -886,14 +895,15 @@ bool bwd_grid(const glam_views& v, BwdGrid& g, int budget) {
 
 template <int F, int K>
 glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig,
-                       const glam_gaussians& out, hipStream_t s) {
+                       const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {
   if (max_anchors(v) == 0 || v.n == 0) return GLAM_OK;
   BwdGrid g;
   if (!bwd_grid(v, g, 2 * cu_count())) return GLAM_ERR_UNSUPPORTED;  // two workgroups per CU
   const size_t sm = fwd_smem<F, K>();
   if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
+  const glam_projected none{};
   hipLaunchKernelGGL((decode_kernel<F, K>), dim3(g.first[g.n_parts]), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0, g,
-                     out);
+                     out, proj ? 1 : 0, tile_log2(v.tile_w), proj ? *proj : none);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -968,8 +978,8 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
 #define GLAM_DECODE_CASES(X) X(32, 10) X(16, 4)
 
 glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig,
-                          const glam_gaussians& out, hipStream_t s) {
-#define X(F_, K_) if (a.F == F_ && a.K == K_) return run_decode<F_, K_>(a, mlp, v, sig, out, s);
+                          const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {
+#define X(F_, K_) if (a.F == F_ && a.K == K_) return run_decode<F_, K_>(a, mlp, v, sig, out, proj, s);
   GLAM_DECODE_CASES(X)
 #undef X
   return GLAM_ERR_UNSUPPORTED;

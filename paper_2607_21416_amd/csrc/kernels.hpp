@@ -45,7 +45,7 @@ glam_status launch_loss(const glam_views& v, const float* image, const float* ta
                         float* dimage, float* loss, void* ws, hipStream_t s);
 
 glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sigmoid_opacity,
-                          const glam_gaussians& out, hipStream_t s);
+                          const glam_gaussians& out, const glam_projected* proj, hipStream_t s);
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts);
 glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v,
                               bool sigmoid_opacity, const glam_gaussians& dg, float* dfeat, float* doffs,

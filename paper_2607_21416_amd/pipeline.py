@@ -309,6 +309,14 @@ class Pipeline:
             B.glam_decode(self.anchors, self.params["mlp"], self.n_parts, self.vt.views, self.flags, self.gauss,
                           s or self.stream())
 
+    def decode_project(self, s=None):
+        """decode() and project() in one launch (anchor scenes; plain scenes project)."""
+        if self.plain:
+            self.project(s)
+        else:
+            B.glam_decode_project(self.anchors, self.params["mlp"], self.n_parts, self.vt.views, self.flags,
+                                  self.gauss, self.proj, s or self.stream())
+
     def project(self, s=None):
         B.glam_project(self.gauss, self.vt.views, self.flags, self.proj, s or self.stream())
 
@@ -348,8 +356,7 @@ class Pipeline:
                               s or self.stream())
 
     def forward(self, s=None):
-        self.decode(s)
-        self.project(s)
+        self.decode_project(s)
         self.bin_sort(s)
         self.render(s)
         self.compute_loss(s)
@@ -372,8 +379,7 @@ class Pipeline:
         """Runs the forward up to the sort once and sizes the pair buffers to the
         required count times `slack` (one synchronising sizing pass; buffers more than
         twice that size are shrunk, since the sort's grids scale with the capacity)."""
-        self.decode()
-        self.project()
+        self.decode_project()
         self.bin_sort()
         torch.cuda.synchronize(self.device)
         need = self.pair_count()
@@ -400,8 +406,7 @@ class GlamRender(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pipe: Pipeline, *params):
-        pipe.decode()
-        pipe.project()
+        pipe.decode_project()
         pipe.bin_sort()
         pipe.render()
         ctx.pipe = pipe
