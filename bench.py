@@ -40,6 +40,25 @@ FLOP_FWD = 23
 FLOP_BWD = 41
 PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, scalar (non-packed) FP32
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_FP32_TFLOPS = 157.3  # dense FP32 matrix cores
+
+# Algorithmic work per unit of the other stages, for the whole-step roofline fraction
+# (each stage's ideal time is the larger of its compute and HBM times at the peaks):
+#   decode + projection: 13,952 FLOP per anchor-view (three MLPs 36 -> 32 -> {10, 30, 70},
+#     FMA = 2, on the matrix cores); 264 B read per anchor (position 3, features 32,
+#     log-scale 1, offsets 30 words) once per partition; 96 B written per view-Gaussian
+#     (14 decoded words, 10 projected words)
+#   bin + sort: 24 B per pair (key and value written once, ranges scanned) + 24 B per pair
+#     and radix pass (key and value read and written)
+#   loss: 36 B per pixel (image and target read, dL/dC written, 3 channels each)
+#   projection adjoint: 132 B per view-Gaussian (23 words read, 10 written)
+#   decode adjoint: 27,904 FLOP per anchor-view (the two products of each forward one),
+#     264 B per anchor and 56 B of incoming gradients per view-Gaussian read
+DECODE_FLOP, DECODE_READ_B, DECODE_WRITE_B = 13952, 264, 96
+SORT_PAIR_B, SORT_PASS_B = 24, 24
+LOSS_PIXEL_B = 36
+PROJ_BWD_B = 132
+DECODE_BWD_FLOP, DECODE_BWD_READ_B = 27904, 56
 
 
 def log(*a):
@@ -211,6 +230,19 @@ def main():
     n_views = pipe.vt.n
     value = n_views * 1000.0 / ms
     log(f"bench: {ms:.3f} ms/step, {value:.1f} iterations/s (wall {wall:.2f} s)")
+    # the spread of single replays (after the timed region)
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for a, b in rev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    rt = np.array([a.elapsed_time(b) for a, b in rev])
+    replay = {"n": len(rt), "median_ms": round(float(np.median(rt)), 4),
+              "p10_ms": round(float(np.percentile(rt, 10)), 4), "p90_ms": round(float(np.percentile(rt, 90)), 4)}
+    pipe.check_status()
+    log("bench: single replays median %.3f ms, p10 %.3f, p90 %.3f" % (replay["median_ms"], replay["p10_ms"],
+                                                                    replay["p90_ms"]))
 
     # per-stage times and evaluation counts (eager, outside the timed region)
     st = stage_times(torch, pipe, args.stage_iters)
@@ -238,6 +270,35 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)}),
                 "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
                         f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
+
+    # whole-step roofline: every stage's ideal time at its own bound, summed, over the
+    # measured step (the optimiser excluded, as in the headline rate)
+    passes = int(pipe.status.cpu()[6].item())
+    anchor_views = sum(int(pipe.vt.info[i].anchor_count) for i in range(pipe.vt.n))
+    n_anchors = int(pipe.anchors.A) if getattr(pipe, "anchors", None) is not None else 0
+    G, npix = int(pipe.vt.n_gauss), int(pipe.vt.n_pix)
+    hbm, alu, mfma = PEAK_HBM_GBS * 1e9, PEAK_FP32_TFLOPS * 1e12, PEAK_MFMA_FP32_TFLOPS * 1e12
+    ideal = {  # seconds, bound
+        "decode_project": max((anchor_views * DECODE_FLOP / mfma, "mfma"),
+                              ((n_anchors * DECODE_READ_B + G * DECODE_WRITE_B) / hbm, "hbm")),
+        "bin_sort": (need * (SORT_PAIR_B + passes * SORT_PASS_B) / hbm, "hbm"),
+        "render_fwd": (evals_fwd * FLOP_FWD / alu, "alu"),
+        "loss": (npix * LOSS_PIXEL_B / hbm, "hbm"),
+        "composite_bwd": (evals_bwd * FLOP_BWD / alu, "alu"),
+        "project_bwd": (G * PROJ_BWD_B / hbm, "hbm"),
+        "decode_bwd": max((anchor_views * DECODE_BWD_FLOP / mfma, "mfma"),
+                          ((n_anchors * DECODE_READ_B + G * DECODE_BWD_READ_B) / hbm, "hbm")),
+    }
+    t_ideal = sum(t for t, _ in ideal.values())
+    step_roofline = {
+        "frac": round(t_ideal * 1e3 / ms, 4), "ideal_ms": round(t_ideal * 1e3, 4), "measured_ms": round(ms, 4),
+        "stages": {k: {"bound": b, "ideal_ms": round(t * 1e3, 4), "frac": round(t * 1e3 / st[k], 4)}
+                   for k, (t, b) in ideal.items()},
+        "units": {"anchor_views": anchor_views, "anchors": n_anchors, "view_gaussians": G, "pairs": int(need),
+                  "radix_passes": passes, "pixels": npix, "evaluations_fwd": evals_fwd,
+                  "evaluations_bwd": evals_bwd},
+    }
+    log(f"bench: whole-step roofline {t_ideal * 1e3:.3f} ms ideal / {ms:.3f} ms = {t_ideal * 1e3 / ms:.3f}")
 
     # the optimiser step that closes the mapping iteration (Adam over the anchors'
     # features, offsets, log-scales and the MLP sets); the headline rate excludes it.
@@ -399,6 +460,8 @@ def main():
         "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
                               "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
         "roofline": roofline,
+        "step_roofline": step_roofline,
+        "replays": replay,
         "flow_densification": {"workload": f"{npx} correspondences between two 1226x370 keyframes 1 m apart "
                                            "(0.5 px noise, 20% outliers)",
                                "us": round(t_epi * 1e3, 2), "kept": kept,
