@@ -1,0 +1,163 @@
+"""The benchmark's own workload in the benchmark's own launch configuration: config 3
+(50k anchors x 10 offsets = 500k Gaussians, four 1226x370 views, L1 + 0.2 (1 - SSIM)) at
+the tuner's stored choice for it (32x32 tiles, long tiles >= 2^10, 5/4 workgroups per
+CU), the whole step replayed from a HIP graph as the benchmark times it.
+
+Against the oracle, at full size and on every output: the tile assignment, sort order,
+ranges and longest-first order bit for bit at that tile edge; every pixel, T and
+contributor count stage-wise; the 2-D gradients of the compositing adjoint, the
+projection adjoint and the anchor and MLP gradients stage-wise; and end to end, raw
+inputs to the images, the loss and the anchor and MLP gradients (the same bars as the
+16x16 parity tests).  The graph replay reproduces an eager step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import AMB_STAGE, AMB_VALUE, gpu_splats, grad_close, host, view_image, view_pixels, view_slices
+from paper_2607_21416_amd import tuning
+from paper_2607_21416_amd.pipeline import Pipeline
+from test_gpu_parity import g2d_gradients
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bench_case():
+    scene = synth.config("C3")
+    choice = tuning.autotune(scene, device="cuda")  # the stored choice: nothing is measured
+    assert choice["source"] == "stored"
+    tile = choice["tile"]
+    print(f"config 3 at tile {tile}, schedule {tuning.schedule(choice)}", flush=True)
+    pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning.schedule(choice))
+    pipe.fit_capacity()
+    pipe.status.zero_()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pipe.step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipe.step()
+    for _ in range(3):
+        pipe.image.fill_(-1.0)  # the replay must overwrite it
+        g.replay()
+    torch.cuda.synchronize()
+    pipe.check_status()
+    return scene, choice, pipe, host(pipe), g
+
+
+def _view_inputs(h, sl):
+    pr, gs = gpu_splats(h, sl)
+    vals = h["vals"].astype(np.int64) - sl["g0"]
+    ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
+    return pr, gs, vals, ranges
+
+
+def test_sort_bit_exact(bench_case):
+    scene, choice, pipe, h, _ = bench_case
+    tile = choice["tile"]
+    sls = view_slices(pipe)
+    G = h["ntiles"].shape[0]
+    prect = np.zeros((4, G), np.int32)
+    nt = np.zeros(G, np.int32)
+    for sl in sls:
+        g0, g1 = sl["g0"], sl["g1"]
+        prect[:, g0:g1], nt[g0:g1] = oracle.rect_f32(h["uv"][0, g0:g1], h["uv"][1, g0:g1], h["ext"][0, g0:g1],
+                                                     h["ext"][1, g0:g1], sl["W"], sl["H"], (tile, tile))
+    assert np.array_equal(nt, h["ntiles"])
+    gb = [sl["g0"] for sl in sls] + [sls[-1]["g1"]]
+    ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), gb, scene["cams"], (tile, tile))
+    assert h["P"] == ref["P"] > 10 ** 6
+    assert np.array_equal(h["vals"], ref["vals"])
+    assert np.array_equal((h["keys"] >> np.uint64(h["dbits"])).astype(np.int64), ref["tiles"].astype(np.int64))
+    assert np.array_equal(h["ranges"], ref["ranges"])
+    lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    long_min = 1 << choice["long_log2"]
+    n_long = int((lens >= long_min).sum())
+    assert n_long > 0 and int(pipe.status.cpu().numpy()[7]) == n_long
+    order = pipe.order.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(len(lens)))
+    assert (lens[order[:n_long]] >= long_min).all() and (lens[order[n_long:]] < long_min).all()
+
+
+def test_forward_stagewise(bench_case):
+    scene, choice, pipe, h, _ = bench_case
+    tile = choice["tile"]
+    for v, sl in enumerate(view_slices(pipe)):
+        pr, gs, vals, ranges = _view_inputs(h, sl)
+        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v], tile=(tile, tile))
+        ok = (ref["amb"] & AMB_STAGE) == 0
+        assert ok.mean() > 0.95
+        assert np.abs(view_image(h, sl) - ref["image"])[:, ok].max() <= 1e-4
+        assert np.abs(view_pixels(h, sl, "T_final") - ref["T_final"])[ok].max() <= 1e-4
+        assert np.array_equal(view_pixels(h, sl, "n_contrib")[ok], ref["n_contrib"][ok])
+
+
+def test_backward_stagewise(bench_case):
+    scene, choice, pipe, h, _ = bench_case
+    tile = choice["tile"]
+    sls = view_slices(pipe)
+    dims = []
+    for v, sl in enumerate(sls):
+        pr, gs, vals, ranges = _view_inputs(h, sl)
+        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v], tile=(tile, tile))
+        _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
+        d[:, (ref["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0] = 0.0
+        dims.append(d)
+    flat = np.concatenate([d.reshape(-1) for d in dims]).astype(np.float32)
+    pipe.backward(dimage=torch.from_numpy(flat).cuda())
+    torch.cuda.synchronize()
+    hb = host(pipe)
+    acc = oracle.zero_grads(scene)
+    for v, sl in enumerate(sls):
+        pr, gs, vals, ranges = _view_inputs(h, sl)
+        g2d = oracle.render_bwd(pr, gs, vals, ranges, scene["cams"][v], dims[v], tile=(tile, tile))
+        got = g2d_gradients(hb["g2d"][sl["g0"]:sl["g1"]], h["conic"][:, sl["g0"]:sl["g1"]])
+        for k, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
+            grad_close(got[k], g2d[k], name=f"config 3 view {v} d{nm}")
+        gin = {k: hb["dec"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dec"]}
+        dgp = oracle.project_bwd(gin, scene["cams"][v], h["ntiles"][sl["g0"]:sl["g1"]], got.astype(np.float64))
+        for k in ("mean", "scale", "quat", "opacity", "rgb"):
+            grad_close(hb["dg"][k][..., sl["g0"]:sl["g1"]], dgp[k], name=f"config 3 view {v} dgauss {k}")
+        dgv = {k: hb["dg"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dg"]}
+        oracle.decode_bwd(scene, scene["cams"][v]["partition"], scene["cams"][v], dgv, acc)
+    for k in acc:
+        grad_close(hb["pgrad"][k], acc[k], name=f"config 3 anchor d{k}")
+
+
+def test_end_to_end(bench_case):
+    scene, choice, pipe, h, _ = bench_case
+    fwd = oracle.forward(scene)
+    dims = []
+    for v, (sl, r) in enumerate(zip(view_slices(pipe), fwd)):
+        ok = (r["amb"] & AMB_VALUE) == 0
+        assert ok.mean() > 0.85
+        assert np.abs(view_image(h, sl) - r["image"])[:, ok].max() <= 1e-4
+        assert h["loss"][v] == pytest.approx(r["loss"], rel=1e-4)
+        d = r["dimage"].copy()
+        d[:, (r["amb"] & (AMB_VALUE | oracle.AMB_CLAMP)) != 0] = 0.0
+        dims.append(d)
+    ref = oracle.backward(scene, fwd, dimages=dims)
+    flat = np.concatenate([d.reshape(-1) for d in dims]).astype(np.float32)
+    pipe.backward(dimage=torch.from_numpy(flat).cuda())
+    torch.cuda.synchronize()
+    got = host(pipe)["pgrad"]
+    for k in ref:
+        grad_close(got[k], ref[k], rel=1e-3, floor=1e-5, name=f"config 3 end-to-end d{k}")
+
+
+def test_replay_equals_eager_step(bench_case):
+    scene, choice, pipe, h, g = bench_case
+    pipe.step()
+    torch.cuda.synchronize()
+    pipe.check_status()
+    e = host(pipe)
+    for k in ("image", "T_final", "n_contrib", "keys", "vals", "ranges"):
+        assert np.array_equal(h[k], e[k]), k
+    np.testing.assert_allclose(h["loss"], e["loss"], rtol=1e-5)
+    for k in e["pgrad"]:
+        grad_close(h["pgrad"][k], e["pgrad"][k], rel=1e-5, floor=1e-6, norm_rel=1e-5, name=f"replay d{k}")
