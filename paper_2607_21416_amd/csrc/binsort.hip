@@ -74,6 +74,24 @@ int bit_length(uint64_t x) {
 
 __device__ __forceinline__ int dbit_length(uint32_t x) { return x ? 32 - __clz(x) : 0; }
 
+// Inclusive scan of one value per thread over a workgroup of 256 threads: each wave scans
+// its 64 lanes with shuffles, then adds the totals of the waves before it (one barrier).
+// s_wave: 4 words of LDS; every thread calls it.
+__device__ __forceinline__ uint32_t block_scan256(uint32_t v, uint32_t* s_wave) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(v, o);
+    v += lane >= o ? u : 0u;
+  }
+  if (lane == 63) s_wave[w] = v;
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) before += k < w ? s_wave[k] : 0u;
+  return v + before;
+}
+
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t* ntiles, const float* depth,
                                                                    long long n, uint32_t* psum, uint32_t* pmax) {
   __shared__ uint32_t s_sum, s_max;
@@ -222,17 +240,11 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
   uint32_t sum = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) { local[i] = sum; sum += s_pre[t * kScanItems + i]; }
-  s_scan[t] = sum;
+  const uint32_t incl = block_scan256(sum, s_scan);
+  if (t == kScanThreads - 1) s_scan[4] = incl;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = t >= off ? s_scan[t - off] : 0u;
-    __syncthreads();
-    s_scan[t] += v;
-    __syncthreads();
-  }
-  const uint32_t before = s_scan[t] - sum;
-  const uint32_t total = s_scan[kScanThreads - 1];
-  __syncthreads();
+  const uint32_t before = incl - sum;
+  const uint32_t total = s_scan[4];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) s_pre[t * kScanItems + i] = before + local[i];
   __syncthreads();
@@ -319,21 +331,14 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(const Plan* plan, int p
   const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
   uint32_t local = 0;
   for (int i = lo; i < hi; ++i) local += row[i];
-  s[threadIdx.x] = local;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
-    __syncthreads();
-    s[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = s[threadIdx.x] - local;
+  const uint32_t incl = block_scan256(local, s);
+  uint32_t run = incl - local;
   for (int i = lo; i < hi; ++i) {
     const uint32_t v = row[i];
     row[i] = run;
     run += v;
   }
-  if (threadIdx.x == 255) digit_total[blockIdx.x] = s[255];
+  if (threadIdx.x == 255) digit_total[blockIdx.x] = incl;
 }
 
 __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Plan* plan, int pass, int n_blocks,
@@ -362,15 +367,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
   const int t = threadIdx.x, w = t >> 6;
   // global base of each digit = exclusive scan of the digit totals
   const uint32_t tot = digit_total[t];
-  s_scan[t] = tot;
-  __syncthreads();
-  for (int off = 1; off < kRadix; off <<= 1) {
-    const uint32_t v = t >= off ? s_scan[t - off] : 0u;
-    __syncthreads();
-    s_scan[t] += v;
-    __syncthreads();
-  }
-  s_run[t] = s_scan[t] - tot + hist[t * n_blocks + blockIdx.x];
+  s_run[t] = block_scan256(tot, s_scan) - tot + hist[t * n_blocks + blockIdx.x];
   __syncthreads();
   const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
   const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
@@ -410,16 +407,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
       run += c[k];
     }
     // first place of digit t in the tile's own digit order
-    s_lbase[t] = run;
-    __syncthreads();
-    for (int off = 1; off < kRadix; off <<= 1) {
-      const uint32_t v = t >= off ? s_lbase[t - off] : 0u;
-      __syncthreads();
-      s_lbase[t] += v;
-      __syncthreads();
-    }
-    const uint32_t lbase = s_lbase[t] - run;
-    __syncthreads();
+    const uint32_t lbase = block_scan256(run, s_scan + 4 * (1 + (tile & 1))) - run;
     s_lbase[t] = lbase;
     uint32_t lpos[kSortItems];
 #pragma unroll
