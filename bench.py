@@ -155,6 +155,40 @@ def profiled_traffic(kernel, launch):
     return int(round(k["fetch_bytes"] + k["write_bytes"]))
 
 
+def whole_step_roofline(pipe, ms, pairs, evals_fwd, evals_bwd, st=None):
+    """Sum over the stages of the step of each stage's ideal time (the larger of its
+    compute and HBM times at the peaks, for its algorithmic work counted from the
+    pipeline's own sizes), against the measured step; per stage too when `st` holds the
+    stages' measured times."""
+    passes = int(pipe.status.cpu()[6].item())
+    anchor_views = sum(int(pipe.vt.info[i].anchor_count) for i in range(pipe.vt.n))
+    n_anchors = int(pipe.anchors.A) if getattr(pipe, "anchors", None) is not None else 0
+    G, npix = int(pipe.vt.n_gauss), int(pipe.vt.n_pix)
+    hbm, alu, mfma = PEAK_HBM_GBS * 1e9, PEAK_FP32_TFLOPS * 1e12, PEAK_MFMA_FP32_TFLOPS * 1e12
+    ideal = {  # seconds, bound
+        "decode_project": max((anchor_views * DECODE_FLOP / mfma, "mfma"),
+                              ((n_anchors * DECODE_READ_B + G * DECODE_WRITE_B) / hbm, "hbm")),
+        "bin_sort": (pairs * (SORT_PAIR_B + passes * SORT_PASS_B) / hbm, "hbm"),
+        "render_fwd": (evals_fwd * FLOP_FWD / alu, "alu"),
+        "loss": (npix * LOSS_PIXEL_B / hbm, "hbm"),
+        "composite_bwd": (evals_bwd * FLOP_BWD / alu, "alu"),
+        "project_bwd": (G * PROJ_BWD_B / hbm, "hbm"),
+        "decode_bwd": max((anchor_views * DECODE_BWD_FLOP / mfma, "mfma"),
+                          ((n_anchors * DECODE_READ_B + G * DECODE_BWD_READ_B) / hbm, "hbm")),
+    }
+    t_ideal = sum(t for t, _ in ideal.values())
+    out = {"frac": round(t_ideal * 1e3 / ms, 4), "ideal_ms": round(t_ideal * 1e3, 4), "measured_ms": round(ms, 4)}
+    if st is not None:
+        out["stages"] = {k: {"bound": b, "ideal_ms": round(t * 1e3, 4), "frac": round(t * 1e3 / st[k], 4)}
+                         for k, (t, b) in ideal.items()}
+    else:
+        out["stages_ideal_ms"] = {k: round(t * 1e3, 4) for k, (t, _) in ideal.items()}
+    out["units"] = {"anchor_views": anchor_views, "anchors": n_anchors, "view_gaussians": G, "pairs": int(pairs),
+                    "radix_passes": passes, "pixels": npix, "evaluations_fwd": evals_fwd,
+                    "evaluations_bwd": evals_bwd}
+    return out
+
+
 def cpu_baseline(scene, views):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -273,31 +307,8 @@ def main():
 
     # whole-step roofline: every stage's ideal time at its own bound, summed, over the
     # measured step (the optimiser excluded, as in the headline rate)
-    passes = int(pipe.status.cpu()[6].item())
-    anchor_views = sum(int(pipe.vt.info[i].anchor_count) for i in range(pipe.vt.n))
-    n_anchors = int(pipe.anchors.A) if getattr(pipe, "anchors", None) is not None else 0
-    G, npix = int(pipe.vt.n_gauss), int(pipe.vt.n_pix)
-    hbm, alu, mfma = PEAK_HBM_GBS * 1e9, PEAK_FP32_TFLOPS * 1e12, PEAK_MFMA_FP32_TFLOPS * 1e12
-    ideal = {  # seconds, bound
-        "decode_project": max((anchor_views * DECODE_FLOP / mfma, "mfma"),
-                              ((n_anchors * DECODE_READ_B + G * DECODE_WRITE_B) / hbm, "hbm")),
-        "bin_sort": (need * (SORT_PAIR_B + passes * SORT_PASS_B) / hbm, "hbm"),
-        "render_fwd": (evals_fwd * FLOP_FWD / alu, "alu"),
-        "loss": (npix * LOSS_PIXEL_B / hbm, "hbm"),
-        "composite_bwd": (evals_bwd * FLOP_BWD / alu, "alu"),
-        "project_bwd": (G * PROJ_BWD_B / hbm, "hbm"),
-        "decode_bwd": max((anchor_views * DECODE_BWD_FLOP / mfma, "mfma"),
-                          ((n_anchors * DECODE_READ_B + G * DECODE_BWD_READ_B) / hbm, "hbm")),
-    }
-    t_ideal = sum(t for t, _ in ideal.values())
-    step_roofline = {
-        "frac": round(t_ideal * 1e3 / ms, 4), "ideal_ms": round(t_ideal * 1e3, 4), "measured_ms": round(ms, 4),
-        "stages": {k: {"bound": b, "ideal_ms": round(t * 1e3, 4), "frac": round(t * 1e3 / st[k], 4)}
-                   for k, (t, b) in ideal.items()},
-        "units": {"anchor_views": anchor_views, "anchors": n_anchors, "view_gaussians": G, "pairs": int(need),
-                  "radix_passes": passes, "pixels": npix, "evaluations_fwd": evals_fwd,
-                  "evaluations_bwd": evals_bwd},
-    }
+    step_roofline = whole_step_roofline(pipe, ms, need, evals_fwd, evals_bwd, st)
+    t_ideal = step_roofline["ideal_ms"] * 1e-3
     log(f"bench: whole-step roofline {t_ideal * 1e3:.3f} ms ideal / {ms:.3f} ms = {t_ideal * 1e3 / ms:.3f}")
 
     # the optimiser step that closes the mapping iteration (Adam over the anchors'
@@ -530,15 +541,29 @@ def main():
         p5.status.zero_()
         for _ in range(2):
             p5.step()
-        t5 = timed(torch, p5.step, 3, stream)
+        step5, g5 = make_step(torch, p5, True)
+        for _ in range(2):
+            step5()
+        t5 = timed(torch, step5, 3, stream)
+        p5.check_status()
+        del g5
+        # evaluations of the step (the timed launches use 16x16 tiles already)
+        p5.count_evaluations()
+        p5.render()
+        torch.cuda.synchronize()
+        ev5_fwd = int(p5.n_eval.to(torch.int64).sum().item())
+        ev5_bwd = int(p5.n_contrib.to(torch.int64).sum().item())
+        p5.count_evaluations(False)
         p5.check_status()
         out["config5"] = {"workload": "config 5: 2 km path, 64 partitions (log-uniform 30k-300k Gaussians), "
                                       "8 views each at 1226x370 / 1280x384 / 1280x960",
                           "views": p5.vt.n, "view_gaussians": int(p5.vt.n_gauss), "pixels": int(p5.vt.n_pix),
                           "pairs": int(need5), "step_ms": round(t5, 2),
-                          "view_iterations_per_s": round(p5.vt.n * 1000.0 / t5, 1), "launch": "eager",
+                          "view_iterations_per_s": round(p5.vt.n * 1000.0 / t5, 1), "launch": "hip graph",
+                          "step_roofline": whole_step_roofline(p5, t5, need5, ev5_fwd, ev5_bwd),
                           "peak_hbm_gib": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2)}
-        log(f"bench: config 5 step {t5:.2f} ms")
+        log(f"bench: config 5 step {t5:.2f} ms (graph), whole-step roofline "
+            f"{out['config5']['step_roofline']['frac']:.3f}")
         del p5, s5
 
     if not args.no_cpu:
