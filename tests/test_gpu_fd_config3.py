@@ -48,6 +48,7 @@ def test_view0_gradients_match_finite_differences():
     grads = {k: v.cpu().numpy().astype(np.float64) for k, v in pipe.pgrad.items()}
     rng = np.random.default_rng(3003)
     checked = skipped = 0
+    worst = 0.0
     t0 = time.time()
     for name, count in COUNTS.items():
         g = grads[name]
@@ -63,6 +64,8 @@ def test_view0_gradients_match_finite_differences():
                 continue
             tol = 1e-3 * abs(fd) + 1e-5 * flat.max()
             assert abs(g[idx] - fd) <= tol, (name, idx, g[idx], fd)
+            worst = max(worst, abs(g[idx] - fd) / tol)
             checked += 1
-        print(f"fd {name}: {checked} checked, {skipped} skipped so far ({time.time() - t0:.0f} s)", flush=True)
+        print(f"fd {name}: {checked} checked, {skipped} skipped so far, largest error / bound {worst:.3f} "
+              f"({time.time() - t0:.0f} s)", flush=True)
     assert checked >= 0.75 * sum(COUNTS.values())
