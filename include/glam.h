@@ -77,7 +77,28 @@ enum {
   GLAM_PLAIN = 1u << 0,
   /* Opacity activation sigmoid instead of the default tanh with non-positive values
      dropped (anchor mode); plain mode always uses sigmoid of the logit. */
-  GLAM_OPACITY_SIGMOID = 1u << 1
+  GLAM_OPACITY_SIGMOID = 1u << 1,
+  /* Footprint of the 3-D Gaussian splatting lineage the paper builds on (Sec. II,
+     Sec. III-A) instead of the default opacity-aware box: a square of radius
+     r = ceil(3 sqrt(lambda_max)) pixels around the centre (lambda_max the larger
+     eigenvalue of the dilated 2-D covariance), taken at tile granularity: a Gaussian is
+     a candidate at every pixel of every tile that square's pixel centres reach.  It
+     clips contributions with alpha >= 1/255 beyond 3 sigma whenever opacity exceeds
+     255^-1 e^4.5 (about 0.353), and the image then depends on the tile edge.  Read by
+     glam_project and glam_decode_project (the flag must then be passed to the backward
+     calls too). */
+  GLAM_FOOTPRINT_3SIGMA = 1u << 2,
+  /* Backward only: reproducible gradients.  The per-Gaussian sums of the reverse
+     compositing (the adjoint of Eq. 1) are formed without floating-point atomics: each
+     (tile, Gaussian) pair and 8x8 quadrant stores its partial sums in a workspace, and
+     a segmented reduction adds each Gaussian's partials in a fixed order (its tiles
+     row-major, then quadrants).  Results are bit-identical from run to run and across
+     schedules with the same tile edge.  Needs glam_bins.pair_begin from the
+     glam_bin_sort call and glam_render_bwd_workspace_bytes with this flag. */
+  GLAM_DETERMINISTIC_GRADS = 1u << 3,
+  /* Backward only: also write the 2-D gradients d(u, v, A, B, C, opacity, r, g, b) of
+     every view-Gaussian to glam_grads.d2d (stage-wise checks, inspection). */
+  GLAM_RETURN_INTERMEDIATES = 1u << 4
 };
 
 /* Pinhole camera: world->camera rotation R (row-major) and translation t, OpenCV
@@ -208,6 +229,11 @@ typedef struct {
                        compositing kernels; caller zeroes them once, every launch
                        leaves them zeroed                                             */
   glam_tuning tuning; /* host: the compositing schedule (rejected when out of range)  */
+  uint32_t* pair_begin; /* [n_gauss] device, or NULL: glam_bin_sort then writes each
+                           view-Gaussian's first pair before sorting (the exclusive
+                           prefix sum of the tile counts; its pairs are that one and the
+                           next ntiles - 1, its tiles row-major).  Required by
+                           GLAM_DETERMINISTIC_GRADS                                      */
 } glam_bins;
 
 /* Workspace bytes glam_bin_sort needs for this view table and pair capacity. */
@@ -262,11 +288,16 @@ glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins,
                             hipStream_t stream);
 
 /* Eq. 3 per view: L_v = mean |C - target| + w_ssim (1 - mean SSIM), SSIM over an 11x11
-   box window with zero padding, C1 = 0.01^2, C2 = 0.03^2.  Writes dL/dimage (same
-   layout as image) and loss[n_views] (device).  workspace: glam_loss_workspace_bytes. */
+   box window with zero padding, C1 = 0.01^2, C2 = 0.03^2 (the paper leaves the weight
+   and the window open; these are the readings of its anchor-based lineage).  image,
+   target, dimage: [3][H][W] per view at 3 * pix_begin (device).  Writes dL/dimage of the
+   step's loss, the sum of the views' losses (one sampled keyframe per iteration in the
+   paper, Sec. IV-B; a batch of views here), loss[n_views] (device) and, if total is not
+   NULL, total[0] = sum of loss[] in view order (device).  workspace:
+   glam_loss_workspace_bytes. */
 size_t glam_loss_workspace_bytes(const glam_views* views);
 glam_status glam_loss(const glam_views* views, const float* image, const float* target,
-                      float w_ssim, float* dimage, float* loss, void* workspace,
+                      float w_ssim, float* dimage, float* loss, float* total, void* workspace,
                       size_t workspace_bytes, hipStream_t stream);
 
 /* --- backward ------------------------------------------------------------------- */
@@ -287,6 +318,8 @@ typedef struct {
   float* doffs;
   float* dlog_scale;
   float* dmlp;
+  float* d2d;  /* [9][n_gauss] (GLAM_RETURN_INTERMEDIATES, else unused and may be NULL):
+                  d(u, v, A, B, C, opacity, r, g, b) per view-Gaussian, zero when culled */
 } glam_grads;
 
 /* Reverse compositing from (T_final, n_contrib): T_i recovered by division by
@@ -313,8 +346,23 @@ glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32
                             float* dlog_scale, float* dmlp, void* workspace,
                             size_t workspace_bytes, hipStream_t stream);
 
-/* The whole backward: composite adjoint, projection adjoint, then (anchor mode) the
-   decode adjoint.  workspace: glam_decode_bwd_workspace_bytes (0 in plain mode). */
+/* Workspace bytes of glam_render_bwd for these flags (0 when the arguments are invalid):
+   the decode adjoint's (anchor mode; anchors and n_parts ignored in plain mode) and,
+   with GLAM_DETERMINISTIC_GRADS, the per-(pair, quadrant) partials for a pair capacity
+   of capacity (36 bytes per pair and 8x8 quadrant of a tile). */
+size_t glam_render_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views,
+                                       int32_t n_parts, int64_t capacity, uint32_t flags);
+
+/* The whole backward, the adjoint of Eq. 1 -> projection -> Eq. 2 / Eq. 6 for the
+   image gradient dimage (the loss gradient of glam_loss, or any other): composite
+   adjoint (g2d), projection adjoint (dgauss), then in anchor mode the decode adjoint
+   (dfeat, doffs, dlog_scale, dmlp), each overwritten.  flags: those of the forward calls
+   (GLAM_PLAIN, GLAM_OPACITY_SIGMOID, GLAM_FOOTPRINT_3SIGMA) plus
+   GLAM_DETERMINISTIC_GRADS (needs bins->pair_begin as written by the glam_bin_sort that
+   produced bins) and GLAM_RETURN_INTERMEDIATES (needs grads->d2d).  workspace:
+   glam_render_bwd_workspace_bytes(anchors, views, n_parts, bins->capacity, flags)
+   bytes (may be NULL when that is 0).  GLAM_ERR_UNSUPPORTED when the reproducible
+   partials would need more than 2^32 slots. */
 glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins,
                             const glam_views* views, const float* bg, const float* T_final,
                             const int32_t* n_contrib, const float* dimage,

@@ -49,6 +49,16 @@ enum {
 int orc_num_threads(void);
 void orc_set_num_threads(int n);
 
+/* Widths of the ambiguity windows of the ORC_AMB_* flags (defaults 1e-6, 1e-8, 1e-6,
+   1e-6): |alpha - 1/255| < alpha, |T' - 1e-4| < T, relative depth gap < depth,
+   |raw alpha - 0.99| < clamp.  Bookkeeping for parity tests; values are unaffected. */
+void orc_set_margins(double alpha, double T, double depth, double clamp);
+
+/* Magnitude mode (0 off, the default): orc_render_bwd then accumulates, per element,
+   the sum of the magnitudes of the terms the element is a sum of (every factor by its
+   absolute value), the scale of the element's rounding error in finite precision. */
+void orc_set_magnitude_mode(int on);
+
 /* Number of packed parameters of one partition's MLP set. */
 int orc_mlp_param_count(int F, int K, int hidden);
 
@@ -61,6 +71,17 @@ void orc_decode(int A, int F, int K, int hidden, const double* pos, const double
                 const double* log_scale, const double* offs, const double* mlp,
                 const orc_cam* cam, int opacity_mode, double* mean, double* scale,
                 double* quat, double* opacity, double* rgb);
+
+/* orc_decode with its discrete decisions exposed: relu_out[A][3][hidden] (may be NULL)
+   receives, per anchor, MLP (opacity, colour, covariance) and hidden unit, whether the
+   ReLU passed (1) or not (0); relu_in (may be NULL) imposes those decisions instead of
+   taking them (the MLP then stays the same linear map near the point where they were
+   taken: finite-difference checks). */
+void orc_decode_ex(int A, int F, int K, int hidden, const double* pos, const double* feat,
+                   const double* log_scale, const double* offs, const double* mlp,
+                   const orc_cam* cam, int opacity_mode, double* mean, double* scale,
+                   double* quat, double* opacity, double* rgb, const uint8_t* relu_in,
+                   uint8_t* relu_out);
 
 /* Adjoint of orc_decode.  Accumulates (+=) into dfeat[A][F], doffs[3][A*K],
    dlog_scale[A] and dmlp[P] from gradients of the decoded Gaussians. */
@@ -90,6 +111,21 @@ void orc_project(int G, const double* mean, const double* scale, const double* q
                  const double* opacity, const orc_cam* cam, int tile_w, int tile_h,
                  double* uv, double* conic, double* cov2d, double* depth, double* ext,
                  int32_t* prect, int32_t* ntiles);
+
+/* orc_project with the Jacobian clamp decision exposed and a choice of footprint:
+   clamp_out[G][2] (may be NULL) receives per Gaussian and axis 0 (free), 1 (clamped at
+   the low limit) or 2 (high limit); clamp_in (may be NULL) imposes those decisions.
+   footprint 0: the opacity-aware box (orc_project).  footprint 1: the square of the
+   3-D Gaussian splatting lineage, ext = r = ceil(3 sqrt(lambda_max)) on both axes
+   (lambda_max the larger eigenvalue of the dilated 2-D covariance), the pixel centres
+   within r of the centre selecting tiles of tile_w x tile_h, and prect widened to
+   those tiles (clipped to the image): the Gaussian is a candidate at every pixel of
+   every tile it is binned to, so the image depends on the tile size. */
+void orc_project_ex(int G, const double* mean, const double* scale, const double* quat,
+                    const double* opacity, const orc_cam* cam, int tile_w, int tile_h,
+                    double* uv, double* conic, double* cov2d, double* depth, double* ext,
+                    int32_t* prect, int32_t* ntiles, const int8_t* clamp_in, int8_t* clamp_out,
+                    int footprint);
 
 /* Adjoint of orc_project for the differentiable outputs (uv, conic) plus the
    pass-through opacity and colour.  g2d[9][G] = d(u, v, A, B, C, opacity, r, g, b).
@@ -137,6 +173,29 @@ void orc_render_bwd(int G, const double* uv, const double* conic, const double* 
                     const int32_t* vals, const int64_t* ranges, int W, int H, int tile_w,
                     int tile_h, const double* bg, const double* dimage, double* g2d);
 
+/* The composited list of every pixel of one view (same arguments as orc_render_fwd):
+   the view-local Gaussians that took part, front to back, and whether each one's alpha
+   was clamped at 0.99.  Returns a handle and the total number of entries; the caller
+   allocates offsets[H*W+1], ids[total] and clamped[total] and passes them with the
+   handle to orc_render_lists_take, which fills them (pixel p's list is
+   [offsets[p], offsets[p+1])) and releases the handle.  Together with the decode and
+   projection decisions these are every discrete decision of the forward pass
+   (candidate set, depth order, skips, stop, clamps). */
+void* orc_render_lists(int G, const double* uv, const double* conic, const double* opacity,
+                       const double* rgb, const int32_t* prect, const double* depth,
+                       const int32_t* vals, const int64_t* ranges, int W, int H, int tile_w,
+                       int tile_h, int64_t* total);
+void orc_render_lists_take(void* handle, int64_t* offsets, int32_t* ids, uint8_t* clamped);
+
+/* Eq. 1 over given composited lists (from orc_render_lists), the decisions held fixed:
+   per pixel C = sum_i c_i a_i prod_{j<i}(1 - a_j) + bg prod_i (1 - a_i) with
+   a_i = opacity_i exp(power_i), or 0.99 where clamped[i].  The function of the
+   parameters that the analytic adjoint differentiates (finite-difference checks). */
+void orc_render_frozen(int G, const double* uv, const double* conic, const double* opacity,
+                       const double* rgb, int W, int H, const double* bg,
+                       const int64_t* offsets, const int32_t* ids, const uint8_t* clamped,
+                       double* image, double* T_final);
+
 /* Brute-force compositing without tiles: every Gaussian whose footprint box holds
    the pixel, ordered by (depth, index).  Same outputs as orc_render_fwd except that
    n_contrib counts positions in the pixel's own list. */
@@ -159,6 +218,11 @@ void orc_render_brute_bwd(int G, const double* uv, const double* conic,
    ssim[3][H][W] and dimage[3][H][W] = dL/dC.  Returns L. */
 double orc_loss(int W, int H, const double* image, const double* target, double w_ssim,
                 double* loss_px, double* ssim, double* dimage);
+
+/* orc_loss with the sign of each L1 term given (l1_sign[3][H][W] of -1, 0, 1; NULL: the
+   sign of C - T): the L1 term becomes sign * (C - T).  Finite-difference checks. */
+double orc_loss_signed(int W, int H, const double* image, const double* target, double w_ssim,
+                       const double* l1_sign, double* loss_px, double* ssim, double* dimage);
 
 #ifdef __cplusplus
 }

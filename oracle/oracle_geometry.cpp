@@ -54,9 +54,12 @@ void mlp_input(int A, int F, const double* pos, const double* feat, int a, const
 }
 
 // Two-layer ReLU MLP: pre = W1 z + b1, h = max(pre, 0), y = W2 h + b2.
+// relu_in (may be null) holds the ReLU decisions fixed (unit i passes when relu_in[i]);
+// relu_out (may be null) receives the decisions taken.
 void mlp_forward(const double* p, const MlpView& v, int hidden, int n_in,
                  const std::vector<double>& z, std::vector<double>& pre, std::vector<double>& h,
-                 std::vector<double>& y) {
+                 std::vector<double>& y, const uint8_t* relu_in = nullptr,
+                 uint8_t* relu_out = nullptr) {
   pre.assign(hidden, 0.0);
   h.assign(hidden, 0.0);
   y.assign(v.out, 0.0);
@@ -64,7 +67,9 @@ void mlp_forward(const double* p, const MlpView& v, int hidden, int n_in,
     double s = p[v.b1 + i];
     for (int k = 0; k < n_in; ++k) s += p[v.w1 + i * n_in + k] * z[k];
     pre[i] = s;
-    h[i] = s > 0.0 ? s : 0.0;
+    const bool on = relu_in ? relu_in[i] != 0 : s > 0.0;
+    h[i] = on ? s : 0.0;
+    if (relu_out) relu_out[i] = on ? 1 : 0;
   }
   for (int o = 0; o < v.out; ++o) {
     double s = p[v.b2 + o];
@@ -119,8 +124,14 @@ const double kAlphaMin = 1.0 / 255.0;
 
 // Projection of one Gaussian (Sec. III-A's projected 2-D Gaussian, built as in the
 // EWA splatting the 3DGS lineage uses).
+// clamp_in (may be null): the Jacobian clamp decision held fixed per axis, 0 free,
+// 1 at the low limit, 2 at the high limit (finite-difference checks only).
+// footprint: 0 the opacity-aware box (alpha >= 1/255 can only occur inside it); 1 the
+// 3-D Gaussian splatting lineage's square of radius ceil(3 sqrt(lambda_max)), widened to
+// whole tiles of tile_w x tile_h pixels.
 void project_one(const orc_cam* cam, const double mu[3], const double s[3], const double q[4],
-                 double opacity, Proj& p) {
+                 double opacity, Proj& p, const int8_t* clamp_in = nullptr, int footprint = 0,
+                 int tile_w = 16, int tile_h = 16) {
   p.visible = false;
   p.x0 = 0; p.x1 = -1; p.y0 = 0; p.y1 = -1;
   p.ex = p.ey = -1.0;
@@ -142,6 +153,12 @@ void project_one(const orc_cam* cam, const double mu[3], const double s[3], cons
   p.clamp_y = ry < p.limy_lo || ry > p.limy_hi;
   p.xt = std::min(std::max(rx, p.limx_lo), p.limx_hi) * tz;
   p.yt = std::min(std::max(ry, p.limy_lo), p.limy_hi) * tz;
+  if (clamp_in) {
+    p.clamp_x = clamp_in[0] != 0;
+    p.clamp_y = clamp_in[1] != 0;
+    p.xt = (clamp_in[0] == 1 ? p.limx_lo : clamp_in[0] == 2 ? p.limx_hi : rx) * tz;
+    p.yt = (clamp_in[1] == 1 ? p.limy_lo : clamp_in[1] == 2 ? p.limy_hi : ry) * tz;
+  }
   p.J[0] = cam->fx / tz; p.J[1] = 0.0; p.J[2] = -cam->fx * p.xt / (tz * tz);
   p.J[3] = 0.0; p.J[4] = cam->fy / tz; p.J[5] = -cam->fy * p.yt / (tz * tz);
   quat_to_rot(q, p.Rq);
@@ -180,9 +197,15 @@ void project_one(const orc_cam* cam, const double mu[3], const double s[3], cons
   // Opacity-aware footprint: outside |dx| <= sqrt(2 ln(255 alpha) a) (likewise y) the
   // Gaussian's alpha is below the 1/255 skip threshold, so the box is conservative.
   if (!(255.0 * opacity > 1.0)) return;
-  const double kappa = 2.0 * std::log(255.0 * opacity);
-  p.ex = std::sqrt(kappa * p.a);
-  p.ey = std::sqrt(kappa * p.c);
+  if (footprint == 1) {
+    // three standard deviations along the 2-D covariance's major axis, rounded up
+    const double lmax = 0.5 * (p.a + p.c) + std::sqrt(0.25 * (p.a - p.c) * (p.a - p.c) + p.b * p.b);
+    p.ex = p.ey = std::ceil(3.0 * std::sqrt(lmax));
+  } else {
+    const double kappa = 2.0 * std::log(255.0 * opacity);
+    p.ex = std::sqrt(kappa * p.a);
+    p.ey = std::sqrt(kappa * p.c);
+  }
   // pixel x holds its centre at x + 0.5: include x when |x + 0.5 - u| <= ex
   double lx = std::ceil(p.u - p.ex - 0.5), hx = std::floor(p.u + p.ex - 0.5);
   double ly = std::ceil(p.v - p.ey - 0.5), hy = std::floor(p.v + p.ey - 0.5);
@@ -190,6 +213,13 @@ void project_one(const orc_cam* cam, const double mu[3], const double s[3], cons
   ly = std::max(ly, 0.0); hy = std::min(hy, H - 1.0);
   if (lx > hx || ly > hy) { p.ex = p.ey = -1.0; return; }
   p.x0 = (int)lx; p.x1 = (int)hx; p.y0 = (int)ly; p.y1 = (int)hy;
+  if (footprint == 1) {
+    // a candidate at every pixel of the tiles the square reaches
+    p.x0 = (p.x0 / tile_w) * tile_w;
+    p.y0 = (p.y0 / tile_h) * tile_h;
+    p.x1 = std::min((p.x1 / tile_w + 1) * tile_w - 1, cam->W - 1);
+    p.y1 = std::min((p.y1 / tile_h + 1) * tile_h - 1, cam->H - 1);
+  }
   p.visible = true;
 }
 
@@ -202,10 +232,25 @@ int orc_mlp_param_count(int F, int K, int hidden) {
   return v.b2 + v.out;
 }
 
+void orc_decode_ex(int A, int F, int K, int hidden, const double* pos, const double* feat,
+                   const double* log_scale, const double* offs, const double* mlp,
+                   const orc_cam* cam, int opacity_mode, double* mean, double* scale,
+                   double* quat, double* opacity, double* rgb, const uint8_t* relu_in,
+                   uint8_t* relu_out);
+
 void orc_decode(int A, int F, int K, int hidden, const double* pos, const double* feat,
                 const double* log_scale, const double* offs, const double* mlp,
                 const orc_cam* cam, int opacity_mode, double* mean, double* scale,
                 double* quat, double* opacity, double* rgb) {
+  orc_decode_ex(A, F, K, hidden, pos, feat, log_scale, offs, mlp, cam, opacity_mode, mean, scale,
+                quat, opacity, rgb, nullptr, nullptr);
+}
+
+void orc_decode_ex(int A, int F, int K, int hidden, const double* pos, const double* feat,
+                   const double* log_scale, const double* offs, const double* mlp,
+                   const orc_cam* cam, int opacity_mode, double* mean, double* scale,
+                   double* quat, double* opacity, double* rgb, const uint8_t* relu_in,
+                   uint8_t* relu_out) {
   const int n_in = F + 4;
   const size_t GK = (size_t)A * K;
   double xc[3];
@@ -215,7 +260,11 @@ void orc_decode(int A, int F, int K, int hidden, const double* pos, const double
   std::vector<double> z, pre, h, y[3];
   for (int a = 0; a < A; ++a) {
     mlp_input(A, F, pos, feat, a, xc, z);
-    for (int l = 0; l < 3; ++l) mlp_forward(mlp, mv[l], hidden, n_in, z, pre, h, y[l]);
+    for (int l = 0; l < 3; ++l) {
+      const size_t o = ((size_t)a * 3 + l) * hidden;
+      mlp_forward(mlp, mv[l], hidden, n_in, z, pre, h, y[l], relu_in ? relu_in + o : nullptr,
+                  relu_out ? relu_out + o : nullptr);
+    }
     const double es = std::exp(log_scale[a]);
     for (int j = 0; j < K; ++j) {
       const size_t g = (size_t)a * K + j;
@@ -345,16 +394,44 @@ void orc_plain_activate_bwd(int G, const double* log_scale, const double* quat_r
   }
 }
 
+void orc_project_ex(int G, const double* mean, const double* scale, const double* quat,
+                    const double* opacity, const orc_cam* cam, int tile_w, int tile_h,
+                    double* uv, double* conic, double* cov2d, double* depth, double* ext,
+                    int32_t* prect, int32_t* ntiles, const int8_t* clamp_in, int8_t* clamp_out,
+                    int footprint);
+
 void orc_project(int G, const double* mean, const double* scale, const double* quat,
                  const double* opacity, const orc_cam* cam, int tile_w, int tile_h,
                  double* uv, double* conic, double* cov2d, double* depth, double* ext,
                  int32_t* prect, int32_t* ntiles) {
+  orc_project_ex(G, mean, scale, quat, opacity, cam, tile_w, tile_h, uv, conic, cov2d, depth, ext,
+                 prect, ntiles, nullptr, nullptr, 0);
+}
+
+void orc_project_ex(int G, const double* mean, const double* scale, const double* quat,
+                    const double* opacity, const orc_cam* cam, int tile_w, int tile_h,
+                    double* uv, double* conic, double* cov2d, double* depth, double* ext,
+                    int32_t* prect, int32_t* ntiles, const int8_t* clamp_in, int8_t* clamp_out,
+                    int footprint) {
   for (int g = 0; g < G; ++g) {
     double mu[3], s[3], q[4];
     for (int k = 0; k < 3; ++k) { mu[k] = mean[(size_t)k * G + g]; s[k] = scale[(size_t)k * G + g]; }
     for (int k = 0; k < 4; ++k) q[k] = quat[(size_t)k * G + g];
     Proj p;
-    project_one(cam, mu, s, q, opacity[g], p);
+    project_one(cam, mu, s, q, opacity[g], p, clamp_in ? clamp_in + 2 * (size_t)g : nullptr, footprint,
+                tile_w, tile_h);
+    if (clamp_out) {
+      // which limit, if any, the Jacobian clamp took on each axis
+      int8_t cx = 0, cy = 0;
+      if (p.t[2] > kZNear) {
+        const double rx = p.t[0] / p.t[2], ry = p.t[1] / p.t[2];
+        cx = rx < p.limx_lo ? 1 : rx > p.limx_hi ? 2 : 0;
+        cy = ry < p.limy_lo ? 1 : ry > p.limy_hi ? 2 : 0;
+        if (clamp_in) { cx = clamp_in[2 * (size_t)g]; cy = clamp_in[2 * (size_t)g + 1]; }
+      }
+      clamp_out[2 * (size_t)g] = cx;
+      clamp_out[2 * (size_t)g + 1] = cy;
+    }
     uv[g] = p.u; uv[(size_t)G + g] = p.v;
     depth[g] = p.t[2];
     if (p.t[2] > kZNear) {

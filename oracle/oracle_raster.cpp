@@ -41,6 +41,20 @@ const double kAlphaMin = 1.0 / 255.0;  // skip threshold
 const double kAlphaMax = 0.99;         // alpha clamp
 const double kTMin = 1e-4;             // transmittance stop threshold
 
+// Widths of the ambiguity windows (parity bookkeeping only; no effect on any value).
+struct Margins {
+  double alpha = 1e-6;   // |alpha - 1/255|
+  double T = 1e-8;       // |T' - 1e-4|
+  double depth = 1e-6;   // relative depth gap of two entries that take part
+  double clamp = 1e-6;   // |raw alpha - 0.99|
+};
+Margins g_margin;
+
+// When set, the compositing adjoint accumulates the magnitude of every term instead of
+// the term (each factor replaced by its absolute value): the sum of |terms| an element
+// is formed from, the scale of its floating-point rounding error.
+bool g_magnitude = false;
+
 // One Gaussian evaluated at a pixel centre.
 struct Eval {
   double dx, dy;   // u - (x + 0.5), v - (y + 0.5)
@@ -97,28 +111,28 @@ void composite(int n, GetG getg, IsCand cand, const double* uv, const double* co
     const double con[3] = {conic[g], conic[(size_t)G + g], conic[2 * (size_t)G + g]};
     const Eval e = evaluate(uv[g], uv[(size_t)G + g], con, opacity[g], x, y);
     if (!cand(i)) {
-      if (e.alpha > kAlphaMin - 1e-6) r.amb |= ORC_AMB_ALPHA;
+      if (e.alpha > kAlphaMin - g_margin.alpha) r.amb |= ORC_AMB_ALPHA;
       continue;
     }
-    if (std::fabs(e.alpha - kAlphaMin) < 1e-6) r.amb |= ORC_AMB_ALPHA;
-    if (std::fabs(e.raw - kAlphaMax) < 1e-6) r.amb |= ORC_AMB_CLAMP;
+    if (std::fabs(e.alpha - kAlphaMin) < g_margin.alpha) r.amb |= ORC_AMB_ALPHA;
+    if (std::fabs(e.raw - kAlphaMax) < g_margin.clamp) r.amb |= ORC_AMB_CLAMP;
     if (e.alpha < kAlphaMin) continue;
     // an order flip between two entries that both take part changes the pixel
-    if (prev_depth >= 0.0 && std::fabs(depth[g] - prev_depth) < 1e-6 * depth[g])
+    if (prev_depth >= 0.0 && std::fabs(depth[g] - prev_depth) < g_margin.depth * depth[g])
       r.amb |= ORC_AMB_DEPTH;
     prev_depth = depth[g];
     const double Tn = r.T * (1.0 - e.alpha);
-    if (std::fabs(Tn - kTMin) < 1e-8) r.amb |= ORC_AMB_T;
+    if (std::fabs(Tn - kTMin) < g_margin.T) r.amb |= ORC_AMB_T;
     if (Tn < kTMin) {
       r.n_eval = i + 1;
       // the stopping entry swapped with a near-tie that follows it changes which of
       // the two is composited: look ahead over the entries of equal depth
       for (int j = i + 1; j < n; ++j) {
         const int h = getg(j);
-        if (std::fabs(depth[h] - depth[g]) >= 1e-6 * depth[g]) break;
+        if (std::fabs(depth[h] - depth[g]) >= g_margin.depth * depth[g]) break;
         if (!cand(j)) continue;
         const double ch[3] = {conic[h], conic[(size_t)G + h], conic[2 * (size_t)G + h]};
-        if (evaluate(uv[h], uv[(size_t)G + h], ch, opacity[h], x, y).alpha > kAlphaMin - 1e-6)
+        if (evaluate(uv[h], uv[(size_t)G + h], ch, opacity[h], x, y).alpha > kAlphaMin - g_margin.alpha)
           r.amb |= ORC_AMB_DEPTH;
       }
       break;
@@ -131,6 +145,13 @@ void composite(int n, GetG getg, IsCand cand, const double* uv, const double* co
   for (int c = 0; c < 3; ++c) r.C[c] += r.T * bg[c];
 }
 
+// The composited lists of one image row (orc_render_lists).
+struct PixelLists {
+  std::vector<int64_t> count;
+  std::vector<int32_t> ids;
+  std::vector<uint8_t> clamped;
+};
+
 bool in_rect(const int32_t* prect, int G, int g, int x, int y) {
   return x >= prect[g] && x <= prect[(size_t)G + g] && y >= prect[2 * (size_t)G + g] &&
          y <= prect[3 * (size_t)G + g];
@@ -142,8 +163,15 @@ bool in_rect(const int32_t* prect, int G, int g, int x, int y) {
 //   dC/da_i = c_i T_i - (sum_{j>i} c_j a_j T_j + T_final bg) / (1 - a_i)
 //   da_i/dopacity = exp(power), da_i/dpower = a_i   (zero when the 0.99 clamp is active)
 //   power = -(A dx^2 + C dy^2)/2 - B dx dy with dx = u - x - 1/2, dy = v - y - 1/2.
+void pixel_backward_magnitude(const PixelResult& r, const double* rgb, const double* conic,
+                              int G, const double* bg, const double g[3], double* acc);
+
 void pixel_backward(const PixelResult& r, const double* rgb, const double* conic, int G,
                     const double* bg, const double g[3], double* acc /*[9][G]*/) {
+  if (g_magnitude) {
+    pixel_backward_magnitude(r, rgb, conic, G, bg, g, acc);
+    return;
+  }
   const int n = (int)r.list.size();
   double behind[3] = {r.T * bg[0], r.T * bg[1], r.T * bg[2]};
   for (int i = n - 1; i >= 0; --i) {
@@ -170,6 +198,37 @@ void pixel_backward(const PixelResult& r, const double* rgb, const double* conic
   }
 }
 
+// The same terms as pixel_backward with every factor taken by magnitude: for each of
+// the nine elements, the sum of |term| over this pixel's contributions.
+void pixel_backward_magnitude(const PixelResult& r, const double* rgb, const double* conic,
+                              int G, const double* bg, const double g[3], double* acc) {
+  const int n = (int)r.list.size();
+  double behind[3] = {r.T * std::fabs(bg[0]), r.T * std::fabs(bg[1]), r.T * std::fabs(bg[2])};
+  for (int i = n - 1; i >= 0; --i) {
+    const Contribution& k = r.list[i];
+    const int id = k.g;
+    const double a = k.e.alpha, T = k.T;
+    double dL_da = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double col = std::fabs(rgb[c * (size_t)G + id]);
+      acc[(6 + c) * (size_t)G + id] += std::fabs(g[c]) * a * T;
+      dL_da += std::fabs(g[c]) * (col * T + behind[c] / (1.0 - a));
+    }
+    for (int c = 0; c < 3; ++c) behind[c] += std::fabs(rgb[c * (size_t)G + id]) * a * T;
+    if (k.e.raw > kAlphaMax) continue;
+    acc[5 * (size_t)G + id] += dL_da * k.e.ep;
+    const double dp = dL_da * a;
+    const double A = std::fabs(conic[id]), B = std::fabs(conic[(size_t)G + id]),
+                 C = std::fabs(conic[2 * (size_t)G + id]);
+    const double dx = std::fabs(k.e.dx), dy = std::fabs(k.e.dy);
+    acc[0 * (size_t)G + id] += dp * (A * dx + B * dy);
+    acc[1 * (size_t)G + id] += dp * (B * dx + C * dy);
+    acc[2 * (size_t)G + id] += dp * (0.5 * dx * dx);
+    acc[3 * (size_t)G + id] += dp * (dx * dy);
+    acc[4 * (size_t)G + id] += dp * (0.5 * dy * dy);
+  }
+}
+
 // Brute-force candidate list of a pixel: every visible Gaussian whose footprint box
 // holds it, ordered by (depth, index).
 void brute_list(int G, const int32_t* prect, const double* depth, int x, int y,
@@ -186,6 +245,15 @@ extern "C" {
 
 int orc_num_threads(void) { return threads(); }
 void orc_set_num_threads(int n) { g_threads = n; }
+
+void orc_set_margins(double alpha, double T, double depth, double clamp) {
+  g_margin.alpha = alpha;
+  g_margin.T = T;
+  g_margin.depth = depth;
+  g_margin.clamp = clamp;
+}
+
+void orc_set_magnitude_mode(int on) { g_magnitude = on != 0; }
 
 void orc_bin_sort(int n_views, const int64_t* gbegin, const int32_t* tiles_x,
                   const int32_t* tiles_y, const int64_t* tile_base, int tile_w, int tile_h,
@@ -278,6 +346,75 @@ void orc_render_bwd(int G, const double* uv, const double* conic, const double* 
   }
 }
 
+void* orc_render_lists(int G, const double* uv, const double* conic, const double* opacity,
+                       const double* rgb, const int32_t* prect, const double* depth,
+                       const int32_t* vals, const int64_t* ranges, int W, int H, int tile_w,
+                       int tile_h, int64_t* total) {
+  const int tiles_x = (W + tile_w - 1) / tile_w;
+  const double bg[3] = {0.0, 0.0, 0.0};
+  auto* rows = new std::vector<PixelLists>(H);
+  parallel_for(H, [&](int lo, int hi, int) {
+    PixelResult r;
+    for (int y = lo; y < hi; ++y) {
+      PixelLists& row = (*rows)[y];
+      row.count.assign(W, 0);
+      for (int x = 0; x < W; ++x) {
+        const int t = (y / tile_h) * tiles_x + x / tile_w;
+        const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        composite((int)(e - s), [&](int i) { return vals[s + i]; },
+                  [&](int i) { return in_rect(prect, G, vals[s + i], x, y); }, uv, conic, opacity,
+                  rgb, depth, G, x, y, bg, r);
+        row.count[x] = (int64_t)r.list.size();
+        for (const Contribution& k : r.list) {
+          row.ids.push_back(k.g);
+          row.clamped.push_back(k.e.raw > kAlphaMax ? 1 : 0);
+        }
+      }
+    }
+  });
+  int64_t n = 0;
+  for (const PixelLists& row : *rows) n += (int64_t)row.ids.size();
+  *total = n;
+  return rows;
+}
+
+void orc_render_lists_take(void* handle, int64_t* offsets, int32_t* ids, uint8_t* clamped) {
+  auto* rows = static_cast<std::vector<PixelLists>*>(handle);
+  int64_t o = 0;
+  size_t p = 0;
+  offsets[0] = 0;
+  for (const PixelLists& row : *rows) {
+    for (int64_t c : row.count) offsets[++p] = (o += c);
+    std::copy(row.ids.begin(), row.ids.end(), ids + (o - (int64_t)row.ids.size()));
+    std::copy(row.clamped.begin(), row.clamped.end(), clamped + (o - (int64_t)row.ids.size()));
+  }
+  delete rows;
+}
+
+void orc_render_frozen(int G, const double* uv, const double* conic, const double* opacity,
+                       const double* rgb, int W, int H, const double* bg,
+                       const int64_t* offsets, const int32_t* ids, const uint8_t* clamped,
+                       double* image, double* T_final) {
+  const size_t HW = (size_t)H * W;
+  parallel_for(H, [&](int lo, int hi, int) {
+    for (int y = lo; y < hi; ++y)
+      for (int x = 0; x < W; ++x) {
+        const size_t p = (size_t)y * W + x;
+        double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+        for (int64_t o = offsets[p]; o < offsets[p + 1]; ++o) {
+          const int g = ids[o];
+          const double con[3] = {conic[g], conic[(size_t)G + g], conic[2 * (size_t)G + g]};
+          const Eval e = evaluate(uv[g], uv[(size_t)G + g], con, opacity[g], x, y);
+          const double a = clamped[o] ? kAlphaMax : e.raw;
+          for (int c = 0; c < 3; ++c) C[c] += rgb[c * (size_t)G + g] * a * T;
+          T *= 1.0 - a;
+        }
+        for (int c = 0; c < 3; ++c) image[c * HW + p] = C[c] + T * bg[c];
+        T_final[p] = T;
+      }
+  });
+}
+
 void orc_render_brute(int G, const double* uv, const double* conic, const double* opacity,
                       const double* rgb, const int32_t* prect, const double* depth, int W,
                       int H, const double* bg, double* image, double* T_final,
@@ -357,8 +494,16 @@ void orc_render_brute_bwd(int G, const double* uv, const double* conic,
     }
 }
 
+double orc_loss_signed(int W, int H, const double* image, const double* target, double w_ssim,
+                       const double* l1_sign, double* loss_px, double* ssim, double* dimage);
+
 double orc_loss(int W, int H, const double* image, const double* target, double w_ssim,
                 double* loss_px, double* ssim, double* dimage) {
+  return orc_loss_signed(W, H, image, target, w_ssim, nullptr, loss_px, ssim, dimage);
+}
+
+double orc_loss_signed(int W, int H, const double* image, const double* target, double w_ssim,
+                       const double* l1_sign, double* loss_px, double* ssim, double* dimage) {
   const size_t HW = (size_t)H * W;
   const double n = 3.0 * (double)HW;
   const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
@@ -372,8 +517,9 @@ double orc_loss(int W, int H, const double* image, const double* target, double 
     // L1 term: sign(0) = 0
     for (size_t p = 0; p < HW; ++p) {
       const double d = x[p] - y[p];
-      loss_px[p] += std::fabs(d) / n;
-      dx[p] = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) / n;
+      const double sg = l1_sign ? l1_sign[c * HW + p] : (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0));
+      loss_px[p] += sg * d / n;
+      dx[p] = sg / n;
     }
     if (w_ssim == 0.0) {
       for (size_t p = 0; p < HW; ++p) ssim[c * HW + p] = 1.0;

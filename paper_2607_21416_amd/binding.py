@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "libglam.so")
 GLAM_OK, GLAM_ERR_INVALID_ARG, GLAM_ERR_WORKSPACE, GLAM_ERR_CAPACITY, GLAM_ERR_HIP, GLAM_ERR_UNSUPPORTED = range(6)
 GLAM_PLAIN = 1
 GLAM_OPACITY_SIGMOID = 2
+GLAM_FOOTPRINT_3SIGMA = 4
+GLAM_DETERMINISTIC_GRADS = 8
+GLAM_RETURN_INTERMEDIATES = 16
 GLAM_QUEUE_WORDS = 1088
 
 EXPORTS = [
@@ -25,7 +28,7 @@ EXPORTS = [
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
     "glam_epipolar_triangulate", "glam_voxelize_workspace_bytes", "glam_voxelize",
-    "glam_insert_rows", "glam_decode_project",
+    "glam_insert_rows", "glam_decode_project", "glam_render_bwd_workspace_bytes",
 ]
 GLAM_ADAM_MAX_GROUPS = 16
 
@@ -76,12 +79,13 @@ class Tuning(C.Structure):
 
 class Bins(C.Structure):
     _fields_ = [("keys", C.c_void_p), ("vals", C.c_void_p), ("ranges", C.c_void_p), ("capacity", C.c_int64),
-                ("status", C.c_void_p), ("order", C.c_void_p), ("queue", C.c_void_p), ("tuning", Tuning)]
+                ("status", C.c_void_p), ("order", C.c_void_p), ("queue", C.c_void_p), ("tuning", Tuning),
+                ("pair_begin", C.c_void_p)]
 
 
 class Grads(C.Structure):
     _fields_ = [("g2d", C.c_void_p), ("dgauss", Gaussians), ("dfeat", C.c_void_p), ("doffs", C.c_void_p),
-                ("dlog_scale", C.c_void_p), ("dmlp", C.c_void_p)]
+                ("dlog_scale", C.c_void_p), ("dmlp", C.c_void_p), ("d2d", C.c_void_p)]
 
 
 class AdamGroup(C.Structure):
@@ -117,7 +121,7 @@ def load():
         "glam_bin_sort": (I32, [P, P, P, P, SZ, P]),
         "glam_render_fwd": (I32, [P, P, P, P, P, P, P, P, P]),
         "glam_loss_workspace_bytes": (SZ, [P]),
-        "glam_loss": (I32, [P, P, P, F32, P, P, P, SZ, P]),
+        "glam_loss": (I32, [P, P, P, F32, P, P, P, P, SZ, P]),
         "glam_composite_bwd": (I32, [P, P, P, P, P, P, P, P, P]),
         "glam_project_bwd": (I32, [P, P, P, U32, P, P, P]),
         "glam_decode_bwd_workspace_bytes": (SZ, [P, P, I32]),
@@ -131,6 +135,7 @@ def load():
         "glam_voxelize": (I32, [P, I64, F32, P, I64, P, P, I64, P, P, P, SZ, P]),
         "glam_insert_rows": (I32, [P, P, I32, I64, I32, I64, I64, P, I64, F32, P]),
         "glam_decode_project": (I32, [P, P, I32, P, U32, P, P, P]),
+        "glam_render_bwd_workspace_bytes": (SZ, [P, P, I32, I64, U32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -215,9 +220,9 @@ def glam_loss_workspace_bytes(views):
     return load().glam_loss_workspace_bytes(ref(views))
 
 
-def glam_loss(views, image, target, w_ssim, dimage, loss, ws, ws_bytes, stream):
+def glam_loss(views, image, target, w_ssim, dimage, loss, total, ws, ws_bytes, stream):
     return _check("glam_loss", load().glam_loss(ref(views), ref(image), ref(target), float(w_ssim), ref(dimage),
-                                                ref(loss), ref(ws), ws_bytes, _stream(stream)))
+                                                ref(loss), ref(total), ref(ws), ws_bytes, _stream(stream)))
 
 
 def glam_composite_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, g2d, stream):
@@ -241,6 +246,10 @@ def glam_decode_bwd(anchors, mlp, n_parts, views, flags, dgauss, dfeat, doffs, d
                   load().glam_decode_bwd(ref(anchors), ref(mlp), n_parts, ref(views), flags, ref(dgauss), ref(dfeat),
                                          ref(doffs), ref(dlog_scale), ref(dmlp), ref(ws), ws_bytes,
                                          _stream(stream)))
+
+
+def glam_render_bwd_workspace_bytes(anchors, views, n_parts, capacity, flags):
+    return load().glam_render_bwd_workspace_bytes(ref(anchors), ref(views), n_parts, capacity, flags)
 
 
 def glam_render_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, gauss, anchors, mlp, n_parts, flags, grads,

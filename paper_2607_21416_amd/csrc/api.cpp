@@ -20,8 +20,9 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 bool ok_ptr(const void* p) { return p != nullptr && aligned16(p); }
 
-bool views_ok(const glam_views* v) {
-  if (!v || !v->host || !v->dev || v->n <= 0) return false;
+// The host table is consistent with the totals (what the workspace queries read).
+bool views_host_ok(const glam_views* v) {
+  if (!v || !v->host || v->n <= 0) return false;
   if (v->tile_w != v->tile_h || !glam::tile_edge_supported(v->tile_w)) return false;
   if (v->n_gauss < 0 || v->n_pix <= 0 || v->n_tiles <= 0) return false;
   // totals must agree with the host table
@@ -36,6 +37,8 @@ bool views_ok(const glam_views* v) {
   }
   return g == v->n_gauss && p == v->n_pix && t == v->n_tiles && t < (1ll << 31) && g < (1ll << 32);
 }
+
+bool views_ok(const glam_views* v) { return views_host_ok(v) && v->dev != nullptr; }
 
 bool gauss_ok(const glam_gaussians* g, bool need) {
   if (!g) return false;
@@ -70,8 +73,15 @@ bool proj_ok(const glam_projected* p) {
 
 bool bins_ok(const glam_bins* b) {
   return b && ok_ptr(b->keys) && ok_ptr(b->vals) && ok_ptr(b->ranges) && ok_ptr(b->status) && ok_ptr(b->order) &&
-         ok_ptr(b->queue) && b->capacity > 0 && b->capacity < (1ll << 32) && glam::tuning_ok(b->tuning);
+         ok_ptr(b->queue) && b->capacity > 0 && b->capacity < (1ll << 32) && glam::tuning_ok(b->tuning) &&
+         (b->pair_begin == nullptr || aligned16(b->pair_begin));
 }
+
+// Flags each entry point understands (anything else is rejected).
+constexpr uint32_t kForwardFlags = GLAM_PLAIN | GLAM_OPACITY_SIGMOID | GLAM_FOOTPRINT_3SIGMA;
+constexpr uint32_t kBackwardFlags = kForwardFlags | GLAM_DETERMINISTIC_GRADS | GLAM_RETURN_INTERMEDIATES;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int max_partition(const glam_views* v) {
   int m = -1;
@@ -145,7 +155,7 @@ glam_status glam_views_build(const glam_camera* cams, int32_t n_views, const int
 }
 
 size_t glam_bin_sort_workspace_bytes(const glam_views* views, int64_t capacity) {
-  if (!views || capacity <= 0) return 0;
+  if (!views_host_ok(views) || capacity <= 0) return 0;
   return glam::bin_sort_workspace(*views, capacity);
 }
 
@@ -153,11 +163,12 @@ glam_status glam_decode(const glam_anchors* anchors, const float* mlp, int32_t n
                         uint32_t flags, glam_gaussians* out, hipStream_t stream) {
   if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(out, true) || n_parts <= 0)
     return GLAM_ERR_INVALID_ARG;
-  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if ((flags & GLAM_PLAIN) || (flags & ~kForwardFlags)) return GLAM_ERR_INVALID_ARG;
   if (!anchor_views_ok(anchors, views) || out->n != views->n_gauss || max_partition(views) >= n_parts)
     return GLAM_ERR_INVALID_ARG;
   if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
-  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, nullptr, stream);
+  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0,
+                             (flags & GLAM_FOOTPRINT_3SIGMA) != 0, *out, nullptr, stream);
 }
 
 glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
@@ -166,16 +177,18 @@ glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, i
   if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(out, true) || n_parts <= 0 ||
       !proj_ok(proj))
     return GLAM_ERR_INVALID_ARG;
-  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if ((flags & GLAM_PLAIN) || (flags & ~kForwardFlags)) return GLAM_ERR_INVALID_ARG;
   if (!anchor_views_ok(anchors, views) || out->n != views->n_gauss || max_partition(views) >= n_parts)
     return GLAM_ERR_INVALID_ARG;
   if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
-  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, *out, proj, stream);
+  return glam::launch_decode(*anchors, mlp, *views, (flags & GLAM_OPACITY_SIGMOID) != 0,
+                             (flags & GLAM_FOOTPRINT_3SIGMA) != 0, *out, proj, stream);
 }
 
 glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, uint32_t flags, glam_projected* out,
                          hipStream_t stream) {
-  if (!views_ok(views) || !gauss_ok(gauss, true) || !proj_ok(out)) return GLAM_ERR_INVALID_ARG;
+  if (!views_ok(views) || !gauss_ok(gauss, true) || !proj_ok(out) || (flags & ~kForwardFlags))
+    return GLAM_ERR_INVALID_ARG;
   const bool plain = (flags & GLAM_PLAIN) != 0;
   if (plain) {
     for (int i = 0; i < views->n; ++i)
@@ -183,7 +196,7 @@ glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, u
   } else if (gauss->n != views->n_gauss) {
     return GLAM_ERR_INVALID_ARG;
   }
-  return glam::launch_project(*gauss, *views, plain, *out, stream);
+  return glam::launch_project(*gauss, *views, plain, (flags & GLAM_FOOTPRINT_3SIGMA) != 0, *out, stream);
 }
 
 glam_status glam_bin_sort(const glam_projected* proj, const glam_views* views, glam_bins* bins, void* workspace,
@@ -203,17 +216,17 @@ glam_status glam_render_fwd(const glam_projected* proj, const glam_bins* bins, c
 }
 
 size_t glam_loss_workspace_bytes(const glam_views* views) {
-  if (!views) return 0;
+  if (!views_host_ok(views)) return 0;
   return glam::loss_workspace(*views);
 }
 
 glam_status glam_loss(const glam_views* views, const float* image, const float* target, float w_ssim, float* dimage,
-                      float* loss, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+                      float* loss, float* total, void* workspace, size_t workspace_bytes, hipStream_t stream) {
   if (!views_ok(views) || !ok_ptr(image) || !ok_ptr(target) || !ok_ptr(dimage) || !ok_ptr(loss) ||
-      !ok_ptr(workspace) || !(w_ssim >= 0.f))
+      !ok_ptr(workspace) || !(w_ssim >= 0.f) || (total && !aligned16(total)))
     return GLAM_ERR_INVALID_ARG;
   if (workspace_bytes < glam::loss_workspace(*views)) return GLAM_ERR_WORKSPACE;
-  return glam::launch_loss(*views, image, target, w_ssim, dimage, loss, workspace, stream);
+  return glam::launch_loss(*views, image, target, w_ssim, dimage, loss, total, workspace, stream);
 }
 
 glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
@@ -222,12 +235,13 @@ glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins
   if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(T_final) || !ok_ptr(n_contrib) ||
       !ok_ptr(dimage) || !ok_ptr(g2d) || (bg && !aligned16(bg)))
     return GLAM_ERR_INVALID_ARG;
-  return glam::launch_composite_bwd(*proj, *bins, *views, bg, T_final, n_contrib, dimage, g2d, stream);
+  return glam::launch_composite_bwd(*proj, *bins, *views, bg, T_final, n_contrib, dimage, g2d, nullptr, stream);
 }
 
 glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* proj, const glam_views* views,
                              uint32_t flags, const float* g2d, glam_gaussians* dgauss, hipStream_t stream) {
-  if (!gauss_ok(gauss, true) || !proj_ok(proj) || !views_ok(views) || !ok_ptr(g2d) || !gauss_ok(dgauss, true))
+  if (!gauss_ok(gauss, true) || !proj_ok(proj) || !views_ok(views) || !ok_ptr(g2d) || !gauss_ok(dgauss, true) ||
+      (flags & ~kBackwardFlags))
     return GLAM_ERR_INVALID_ARG;
   const bool plain = (flags & GLAM_PLAIN) != 0;
   if (plain) {
@@ -237,11 +251,11 @@ glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* 
   } else if (gauss->n != views->n_gauss || dgauss->n != views->n_gauss) {
     return GLAM_ERR_INVALID_ARG;
   }
-  return glam::launch_project_bwd(*gauss, *proj, *views, plain, g2d, *dgauss, stream);
+  return glam::launch_project_bwd(*gauss, *proj, *views, plain, g2d, *dgauss, nullptr, stream);
 }
 
 size_t glam_decode_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views, int32_t n_parts) {
-  if (!anchors || !views || n_parts <= 0) return 0;
+  if (!anchors || !views_host_ok(views) || n_parts <= 0) return 0;
   return glam::decode_bwd_workspace(*anchors, *views, n_parts);
 }
 
@@ -252,7 +266,7 @@ glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32
   if (!anchors_ok(anchors) || !ok_ptr(mlp) || !views_ok(views) || !gauss_ok(dgauss, true) || !ok_ptr(dfeat) ||
       !ok_ptr(doffs) || !ok_ptr(dlog_scale) || !ok_ptr(dmlp) || !ok_ptr(workspace) || n_parts <= 0)
     return GLAM_ERR_INVALID_ARG;
-  if (flags & GLAM_PLAIN) return GLAM_ERR_INVALID_ARG;
+  if ((flags & GLAM_PLAIN) || (flags & ~kBackwardFlags)) return GLAM_ERR_INVALID_ARG;
   if (!anchor_views_ok(anchors, views) || dgauss->n != views->n_gauss || max_partition(views) >= n_parts)
     return GLAM_ERR_INVALID_ARG;
   if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
@@ -261,31 +275,64 @@ glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32
                                  doffs, dlog_scale, dmlp, workspace, stream);
 }
 
+size_t glam_render_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views, int32_t n_parts,
+                                       int64_t capacity, uint32_t flags) {
+  if (!views_host_ok(views) || (flags & ~kBackwardFlags)) return 0;
+  size_t n = 0;
+  if (!(flags & GLAM_PLAIN)) {
+    if (!anchors || n_parts <= 0) return 0;
+    n = align256(glam::decode_bwd_workspace(*anchors, *views, n_parts));
+  }
+  if (flags & GLAM_DETERMINISTIC_GRADS) {
+    if (capacity <= 0) return 0;
+    n += align256(glam::det_partial_bytes(*views, capacity));
+  }
+  return n;
+}
+
 glam_status glam_render_bwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
                             const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
                             const glam_gaussians* gauss, const glam_anchors* anchors, const float* mlp,
                             int32_t n_parts, uint32_t flags, glam_grads* grads, void* workspace,
                             size_t workspace_bytes, hipStream_t stream) {
-  if (!grads) return GLAM_ERR_INVALID_ARG;
+  if (!grads || (flags & ~kBackwardFlags)) return GLAM_ERR_INVALID_ARG;
   const bool plain = (flags & GLAM_PLAIN) != 0;
+  const bool det = (flags & GLAM_DETERMINISTIC_GRADS) != 0;
+  const bool inter = (flags & GLAM_RETURN_INTERMEDIATES) != 0;
   // validate everything before the first launch
   if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(T_final) || !ok_ptr(n_contrib) ||
-      !ok_ptr(dimage) || !ok_ptr(grads->g2d) || !gauss_ok(gauss, true) || !gauss_ok(&grads->dgauss, true))
+      !ok_ptr(dimage) || !ok_ptr(grads->g2d) || !gauss_ok(gauss, true) || !gauss_ok(&grads->dgauss, true) ||
+      (bg && !aligned16(bg)) || (inter && !ok_ptr(grads->d2d)) || (det && !bins->pair_begin))
     return GLAM_ERR_INVALID_ARG;
-  if (!plain) {
+  if (plain) {
+    if (grads->dgauss.n != gauss->n) return GLAM_ERR_INVALID_ARG;
+    for (int i = 0; i < views->n; ++i)
+      if (views->host[i].g_count != gauss->n) return GLAM_ERR_INVALID_ARG;
+  } else {
     if (!anchors_ok(anchors) || !ok_ptr(mlp) || !ok_ptr(grads->dfeat) || !ok_ptr(grads->doffs) ||
         !ok_ptr(grads->dlog_scale) || !ok_ptr(grads->dmlp) || !ok_ptr(workspace) || n_parts <= 0)
       return GLAM_ERR_INVALID_ARG;
-    if (!anchor_views_ok(anchors, views) || max_partition(views) >= n_parts) return GLAM_ERR_INVALID_ARG;
+    if (!anchor_views_ok(anchors, views) || max_partition(views) >= n_parts || gauss->n != views->n_gauss ||
+        grads->dgauss.n != views->n_gauss)
+      return GLAM_ERR_INVALID_ARG;
     if (!glam::decode_supported(anchors->F, anchors->K)) return GLAM_ERR_UNSUPPORTED;
-    if (workspace_bytes < glam::decode_bwd_workspace(*anchors, *views, n_parts)) return GLAM_ERR_WORKSPACE;
   }
-  glam_status s = glam_composite_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, grads->g2d, stream);
+  if (det && !glam::det_supported(*views, bins->capacity)) return GLAM_ERR_UNSUPPORTED;
+  if (det && !ok_ptr(workspace)) return GLAM_ERR_INVALID_ARG;
+  if (workspace_bytes < glam_render_bwd_workspace_bytes(anchors, views, n_parts, bins->capacity, flags))
+    return GLAM_ERR_WORKSPACE;
+  // workspace: the decode adjoint's part (anchor mode), then the reproducible partials
+  char* ws = static_cast<char*>(workspace);
+  const size_t dec_bytes = plain ? 0 : align256(glam::decode_bwd_workspace(*anchors, *views, n_parts));
+  float* det_part = det ? reinterpret_cast<float*>(ws + dec_bytes) : nullptr;
+  glam_status s = glam::launch_composite_bwd(*proj, *bins, *views, bg, T_final, n_contrib, dimage, grads->g2d,
+                                             det_part, stream);
   if (s != GLAM_OK) return s;
-  s = glam_project_bwd(gauss, proj, views, flags, grads->g2d, &grads->dgauss, stream);
+  s = glam::launch_project_bwd(*gauss, *proj, *views, plain, grads->g2d, grads->dgauss, inter ? grads->d2d : nullptr,
+                               stream);
   if (s != GLAM_OK || plain) return s;
-  return glam_decode_bwd(anchors, mlp, n_parts, views, flags, &grads->dgauss, grads->dfeat, grads->doffs,
-                         grads->dlog_scale, grads->dmlp, workspace, workspace_bytes, stream);
+  return glam::launch_decode_bwd(*anchors, mlp, n_parts, *views, (flags & GLAM_OPACITY_SIGMOID) != 0, grads->dgauss,
+                                 grads->dfeat, grads->doffs, grads->dlog_scale, grads->dmlp, workspace, stream);
 }
 
 glam_status glam_adam_step(const glam_adam_group* groups, int32_t n_groups, int32_t step, float beta1, float beta2,

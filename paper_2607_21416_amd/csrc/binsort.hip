@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
                                                                  int n_views, int tl, const uint32_t* psum,
                                                                  const Plan* plan, uint64_t* keys_out,
                                                                  uint32_t* vals_out, uint64_t* keys_alt,
-                                                                 uint32_t* vals_alt) {
+                                                                 uint32_t* vals_alt, uint32_t* pair_begin) {
   __shared__ uint32_t s_pre[kScanBlock];   // count, then exclusive prefix within the workgroup
   __shared__ uint32_t s_tile[kScanBlock];  // global tile of the box's top-left corner
   __shared__ uint32_t s_dim[kScanBlock];   // box width in tiles | view tiles_x << 16
@@ -248,6 +248,14 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) s_pre[t * kScanItems + i] = before + local[i];
   __syncthreads();
+  if (pair_begin) {  // each view-Gaussian's first pair, in the same order as the emission below
+    const uint32_t gb = psum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const long long g = base + i * kScanThreads + t;
+      if (g < n) pair_begin[g] = gb + s_pre[i * kScanThreads + t];
+    }
+  }
   uint64_t* kout = (pl.npasses & 1u) ? keys_alt : keys_out;
   uint32_t* vout = (pl.npasses & 1u) ? vals_alt : vals_out;
   const uint32_t gbase = psum[blockIdx.x];
@@ -525,7 +533,8 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                      (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status,
                      bins.ranges, lpt);
   hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
-                     n, v.dev, v.n, tile_log2(v.tile_w), psum, plan, bins.keys, bins.vals, keys_alt, vals_alt);
+                     n, v.dev, v.n, tile_log2(v.tile_w), psum, plan, bins.keys, bins.vals, keys_alt, vals_alt,
+                     bins.pair_begin);
   // host bound on the passes: tile bits are known, depth keys take at most 31 bits
   const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
   const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;

@@ -184,7 +184,7 @@ template <int F, int K>
 __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const float* __restrict__ mlp,
                                                      const glam_view_info* views, int sigmoid_op, BwdGrid grid,
                                                      glam_gaussians out, int fuse_project, int tl,
-                                                     glam_projected proj) {
+                                                     int sigma3, glam_projected proj) {
   using C = Cfg<F, K>;
   constexpr LdsOff L = lds_offsets(F, K);
   extern __shared__ float smem[];
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
         for (int k = 0; k < 4; ++k) out.quat[k * n + g] = qn[k];
         for (int i = 0; i < 3; ++i) out.mean[i * n + g] = mu[q][i];
         // the projection of the Gaussian just decoded, from the same registers
-        if (fuse_project) project_one(vw.cam, mu[q], sc, qn, op, rgb, g, n, tl, proj);
+        if (fuse_project) project_one(vw.cam, mu[q], sc, qn, op, rgb, g, n, tl, sigma3 != 0, proj);
       }
       // the next view's rows overwrite rows these outputs were read from
       wave_sync();
@@ -724,31 +724,37 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   for (int i = t; i < C::PM; i += 64 * kBwdWaves) red[i] = 0.f;
   __syncthreads();
   constexpr int RW2 = kHid * C::NIN + kHid, RB2 = RW2 + OUT * kHid, RB1 = kHid * C::NIN;
+  // the waves add their shares one after another (every address takes one add per wave),
+  // so the sums are formed in wave order and the gradients are reproducible
+  for (int ww = 0; ww < kBwdWaves; ++ww) {
+    if (w == ww) {
 #pragma unroll
-  for (int ot = 0; ot < C::OT; ++ot)
+      for (int ot = 0; ot < C::OT; ++ot)
 #pragma unroll
-    for (int ht = 0; ht < 2; ++ht)
+        for (int ht = 0; ht < 2; ++ht)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = ot * 16 + 4 * lg + r;
-        if (o < OUT) atomicAdd(&red[RW2 + o * kHid + ht * 16 + li], dW2[ot * 2 + ht][r]);
+          for (int r = 0; r < 4; ++r) {
+            const int o = ot * 16 + 4 * lg + r;
+            if (o < OUT) red[RW2 + o * kHid + ht * 16 + li] += dW2[ot * 2 + ht][r];
+          }
+#pragma unroll
+      for (int i = 0; i < (OUT + 63) / 64; ++i) {
+        const int o = l + 64 * i;
+        if (o < OUT) red[RB2 + o] += db2[i];
       }
 #pragma unroll
-  for (int i = 0; i < (OUT + 63) / 64; ++i) {
-    const int o = l + 64 * i;
-    if (o < OUT) atomicAdd(&red[RB2 + o], db2[i]);
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ct = 0; ct < C::NC1; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int h = mt * 16 + 4 * lg + r, col = ct * 16 + li;
+            if (col < C::NIN) red[h * C::NIN + col] += dW1[mt * C::NC1 + ct][r];
+          }
+      if (l < kHid) red[RB1 + l] += db1;
+    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int ct = 0; ct < C::NC1; ++ct)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h = mt * 16 + 4 * lg + r, col = ct * 16 + li;
-        if (col < C::NIN) atomicAdd(&red[h * C::NIN + col], dW1[mt * C::NC1 + ct][r]);
-      }
-  if (l < kHid) atomicAdd(&red[RB1 + l], db1);
-  __syncthreads();
   // partial rows: plane 0 holds every MLP's share, plane 1 the second covariance half
   float* dst = partial + ((size_t)(ML == 2 ? half : 0) * gridDim.x + blockIdx.x) * O.total + O.w1[ML];
   for (int i = t; i < C::PM; i += 64 * kBwdWaves) dst[i] = red[i];
@@ -894,7 +900,7 @@ bool bwd_grid(const glam_views& v, BwdGrid& g, int budget) {
 }
 
 template <int F, int K>
-glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig,
+glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig, bool sigma3,
                        const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {
   if (max_anchors(v) == 0 || v.n == 0) return GLAM_OK;
   BwdGrid g;
@@ -903,7 +909,7 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
   if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
   const glam_projected none{};
   hipLaunchKernelGGL((decode_kernel<F, K>), dim3(g.first[g.n_parts]), dim3(256), sm, s, a, mlp, v.dev, sig ? 1 : 0, g,
-                     out, proj ? 1 : 0, tile_log2(v.tile_w), proj ? *proj : none);
+                     out, proj ? 1 : 0, tile_log2(v.tile_w), sigma3 ? 1 : 0, proj ? *proj : none);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -977,9 +983,9 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
 
 #define GLAM_DECODE_CASES(X) X(32, 10) X(16, 4)
 
-glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig,
+glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig, bool sigma3,
                           const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {
-#define X(F_, K_) if (a.F == F_ && a.K == K_) return run_decode<F_, K_>(a, mlp, v, sig, out, proj, s);
+#define X(F_, K_) if (a.F == F_ && a.K == K_) return run_decode<F_, K_>(a, mlp, v, sig, sigma3, out, proj, s);
   GLAM_DECODE_CASES(X)
 #undef X
   return GLAM_ERR_UNSUPPORTED;

@@ -24,10 +24,10 @@ inline bool tuning_ok(const glam_tuning& t) {
 // Compute units of the current device (256 if the runtime cannot say).
 int cu_count();
 
-glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain,
+glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain, bool sigma3,
                            const glam_projected& out, hipStream_t s);
 glam_status launch_project_bwd(const glam_gaussians& g, const glam_projected& proj, const glam_views& v,
-                               bool plain, const float* g2d, const glam_gaussians& dg, hipStream_t s);
+                               bool plain, const float* g2d, const glam_gaussians& dg, float* d2d, hipStream_t s);
 
 size_t bin_sort_workspace(const glam_views& v, long long capacity);
 glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, const glam_bins& bins,
@@ -36,16 +36,20 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
 glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                               const float* bg, float* image, float* T_final, int32_t* n_contrib,
                               int32_t* n_eval, hipStream_t s);
+// det_part (may be null): the reproducible backward's partial buffer of
+// det_partial_bytes, in place of floating-point atomics.
+size_t det_partial_bytes(const glam_views& v, long long capacity);
+bool det_supported(const glam_views& v, long long capacity);
 glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                                  const float* bg, const float* T_final, const int32_t* n_contrib,
-                                 const float* dimage, float* g2d, hipStream_t s);
+                                 const float* dimage, float* g2d, float* det_part, hipStream_t s);
 
 size_t loss_workspace(const glam_views& v);
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
-                        float* dimage, float* loss, void* ws, hipStream_t s);
+                        float* dimage, float* loss, float* total, void* ws, hipStream_t s);
 
 glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sigmoid_opacity,
-                          const glam_gaussians& out, const glam_projected* proj, hipStream_t s);
+                          bool sigma3, const glam_gaussians& out, const glam_projected* proj, hipStream_t s);
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts);
 glam_status launch_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts, const glam_views& v,
                               bool sigmoid_opacity, const glam_gaussians& dg, float* dfeat, float* doffs,

@@ -267,6 +267,14 @@ __global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* 
   }
 }
 
+// The step's loss: the views' losses added in view order (double precision).
+__global__ void loss_total_kernel(const float* loss, int n, float* total) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int v = 0; v < n; ++v) acc += (double)loss[v];
+  *total = (float)acc;
+}
+
 int max_tiles32(const glam_views& v) {
   int mx = 0;
   for (int i = 0; i < v.n; ++i) {
@@ -284,13 +292,14 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t loss_workspace(const glam_views& v) { return align256(8ull * 3 * (size_t)max_tiles32(v) * (size_t)v.n); }
 
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
-                        float* dimage, float* loss, void* ws, hipStream_t s) {
+                        float* dimage, float* loss, float* total, void* ws, hipStream_t s) {
   if (v.n_tiles == 0 || v.n == 0) return GLAM_OK;
   const int mt = max_tiles32(v);
   float* partial = static_cast<float*>(ws);
   hipLaunchKernelGGL(loss_kernel, dim3((unsigned)mt, (unsigned)v.n, 3), dim3(kThreads), 0, s, v.dev, mt, image, target,
                      w_ssim, dimage, partial);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, mt, partial, w_ssim, loss);
+  if (total) hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

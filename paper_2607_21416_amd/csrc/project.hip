@@ -31,7 +31,7 @@ __device__ __forceinline__ void load_gauss(const glam_gaussians& g, long long i,
 
 __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, const glam_view_info* views,
                                                       int n_views, long long n_total, int plain, int tl,
-                                                      glam_projected out) {
+                                                      int sigma3, glam_projected out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_total) return;
   const int vi = find_view(views, n_views, i, [](const glam_view_info& v) { return v.g_begin; });
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) project_kernel(glam_gaussians gauss, cons
   const long long src = plain ? i - vw.g_begin : i;
   GaussIn g;
   load_gauss(gauss, src, plain != 0, g);
-  project_one(cam, g.mu, g.s, g.q, g.op, g.rgb, i, n_total, tl, out);
+  project_one(cam, g.mu, g.s, g.q, g.op, g.rgb, i, n_total, tl, sigma3 != 0, out);
 }
 
 // Adjoint of the projection for one view-Gaussian.  g2d[n][9] holds, summed over the
@@ -117,15 +117,29 @@ __device__ __forceinline__ void project_adjoint(const glam_camera& cam, const Ga
 }
 
 // Anchor mode: one thread per view-Gaussian.
+// The 2-D gradients d(u, v, A, B, C, opacity, r, g, b) of view-Gaussian i, [9][n], from
+// its moments and conic (zero where culled: no moments, zero conic).
+__device__ __forceinline__ void write_d2d(const glam_projected& proj, long long i, long long n, const float gi[9],
+                                          float* d2d) {
+  const float cA = proj.conic[i], cB = proj.conic[n + i], cC = proj.conic[2 * n + i];
+  d2d[i] = -(cA * gi[0] + cB * gi[1]);
+  d2d[n + i] = -(cB * gi[0] + cC * gi[1]);
+  d2d[2 * n + i] = -0.5f * gi[2];
+  d2d[3 * n + i] = -gi[3];
+  d2d[4 * n + i] = -0.5f * gi[4];
+  for (int k = 5; k < 9; ++k) d2d[k * n + i] = gi[k];
+}
+
 __global__ void __launch_bounds__(256) project_bwd_kernel(glam_gaussians gauss, const glam_projected proj,
                                                           const glam_view_info* views, int n_views,
                                                           long long n_total, const float* g2d,
-                                                          glam_gaussians dg) {
+                                                          glam_gaussians dg, float* d2d) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_total) return;
   const long long n = n_total;
   float gi[9];
   for (int k = 0; k < 9; ++k) gi[k] = g2d[i * 9 + k];
+  if (d2d) write_d2d(proj, i, n, gi, d2d);
   float dmu[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
   if (proj.ntiles[i] > 0) {
     const int vi = find_view(views, n_views, i, [](const glam_view_info& v) { return v.g_begin; });
@@ -147,8 +161,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(glam_gaussians gauss, 
 // the activations (exp, quaternion normalisation, sigmoid).
 __global__ void __launch_bounds__(256) project_bwd_plain_kernel(glam_gaussians gauss, const glam_projected proj,
                                                                 const glam_view_info* views, int n_views,
-                                                                long long G, const float* g2d,
-                                                                glam_gaussians dg) {
+                                                                long long G, long long n_total,
+                                                                const float* g2d, glam_gaussians dg,
+                                                                float* d2d) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   GaussIn gin;
@@ -159,6 +174,7 @@ __global__ void __launch_bounds__(256) project_bwd_plain_kernel(glam_gaussians g
     const long long i = views[v].g_begin + g;
     float gi[9];
     for (int k = 0; k < 9; ++k) gi[k] = g2d[i * 9 + k];
+    if (d2d) write_d2d(proj, i, n_total, gi, d2d);
     dop += gi[5];
     for (int k = 0; k < 3; ++k) drgb[k] += gi[6 + k];
     if (proj.ntiles[i] == 0) continue;
@@ -182,28 +198,28 @@ __global__ void __launch_bounds__(256) project_bwd_plain_kernel(glam_gaussians g
   for (int k = 0; k < 3; ++k) dg.rgb[k * n + g] = drgb[k];
 }
 
-glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain,
+glam_status launch_project(const glam_gaussians& g, const glam_views& v, bool plain, bool sigma3,
                            const glam_projected& out, hipStream_t s) {
   const long long n = v.n_gauss;
   if (n == 0) return GLAM_OK;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, s, g, v.dev, v.n, n, plain ? 1 : 0,
-                     tile_log2(v.tile_w), out);
+                     tile_log2(v.tile_w), sigma3 ? 1 : 0, out);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
 glam_status launch_project_bwd(const glam_gaussians& g, const glam_projected& proj, const glam_views& v,
-                               bool plain, const float* g2d, const glam_gaussians& dg, hipStream_t s) {
+                               bool plain, const float* g2d, const glam_gaussians& dg, float* d2d, hipStream_t s) {
   if (plain) {
     const long long G = g.n;
     if (G == 0) return GLAM_OK;
     hipLaunchKernelGGL(project_bwd_plain_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, g, proj,
-                       v.dev, v.n, G, g2d, dg);
+                       v.dev, v.n, G, (long long)v.n_gauss, g2d, dg, d2d);
   } else {
     const long long n = v.n_gauss;
     if (n == 0) return GLAM_OK;
     hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, proj, v.dev,
-                       v.n, n, g2d, dg);
+                       v.n, n, g2d, dg, d2d);
   }
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }

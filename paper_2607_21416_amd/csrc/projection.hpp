@@ -85,18 +85,29 @@ __device__ __forceinline__ bool project_state(const glam_camera& cam, const floa
 
 // Writes view-Gaussian i's projection: centre, depth, conic, footprint extents, tile
 // count for tiles of edge 2^tl, and the packed render record.  Culls depth <= 0.2 and
-// opacity <= 1/255; the footprint box holds every pixel whose alpha can reach 1/255.
+// opacity <= 1/255.  Default footprint: the box holds every pixel whose alpha can reach
+// 1/255.  sigma3 (the 3-D Gaussian splatting lineage's footprint): the pixel centres
+// within r = ceil(3 sqrt(lambda_max)) of the centre on each axis select the tiles, and
+// the record's box is widened to those tiles' pixels, so the Gaussian is a candidate at
+// every pixel of its tiles; ext then holds r on both axes.
 __device__ __forceinline__ void project_one(const glam_camera& cam, const float mu[3], const float s[3],
                                             const float q[4], float op, const float rgb[3], long long i,
-                                            long long n, int tl, const glam_projected& out) {
+                                            long long n, int tl, bool sigma3, const glam_projected& out) {
   ProjState p;
   bool vis = project_state(cam, mu, s, q, p);
   float ex = -1.f, ey = -1.f;
   int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
   if (vis && 255.f * op > 1.f) {
-    const float kappa = 2.f * logf(255.f * op);
-    ex = sqrtf(kappa * p.a);
-    ey = sqrtf(kappa * p.c);
+    if (sigma3) {
+      // larger eigenvalue of [[a, b], [b, c]]
+      const float hd = 0.5f * (p.a - p.c);
+      const float lmax = 0.5f * (p.a + p.c) + sqrtf(hd * hd + p.b * p.b);
+      ex = ey = ceilf(3.f * sqrtf(lmax));
+    } else {
+      const float kappa = 2.f * logf(255.f * op);
+      ex = sqrtf(kappa * p.a);
+      ey = sqrtf(kappa * p.c);
+    }
     // pixel x is inside when |x + 0.5 - u| <= ex; each bound is two IEEE single adds
     const float lx = fmaxf(ceilf(p.u - (ex + 0.5f)), 0.f);
     const float hx = fminf(floorf(p.u + (ex - 0.5f)), (float)(cam.width - 1));
@@ -127,6 +138,12 @@ __device__ __forceinline__ void project_one(const glam_camera& cam, const float 
   out.ntiles[i] = vis ? ((x1 >> tl) - (x0 >> tl) + 1) * ((y1 >> tl) - (y0 >> tl) + 1) : 0;
   float4* rec = reinterpret_cast<float4*>(out.splat + i * kSplatWords);
   if (vis) {
+    if (sigma3) {  // every pixel of the touched tiles
+      x0 = (x0 >> tl) << tl;
+      y0 = (y0 >> tl) << tl;
+      x1 = min((((x1 >> tl) + 1) << tl) - 1, cam.width - 1);
+      y1 = min((((y1 >> tl) + 1) << tl) - 1, cam.height - 1);
+    }
     const uint32_t bx = (uint32_t)x0 | ((uint32_t)x1 << 16);
     const uint32_t by = (uint32_t)y0 | ((uint32_t)y1 << 16);
     // the conic as a base-2 exponent: -log2(e) (A/2, B, C/2)

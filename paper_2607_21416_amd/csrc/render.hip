@@ -548,8 +548,11 @@ __device__ __forceinline__ int stage_offset(int lane) {
   return off;
 }
 
-// Sums and adds the n staged hits (lane 9 h + c: component c of hit h).  The wave must
-// be fully active.
+// Sums the n staged hits (lane 9 h + c: component c of hit h) and adds them to the
+// Gaussian's nine words with one atomic instruction, or (kDet) stores them to the
+// hit's own partial slot, whose index the hit carries in place of the Gaussian's.  The
+// wave must be fully active.
+template <bool kDet>
 __device__ __forceinline__ void stage_flush(GradStage& G, int n, int off, int lane, float* g2d) {
   __builtin_amdgcn_wave_barrier();
   const int h = lane / 9, c = lane - 9 * (lane / 9);
@@ -558,12 +561,16 @@ __device__ __forceinline__ void stage_flush(GradStage& G, int n, int off, int la
     const float4 a = p[0], b = p[1], d = p[2], e = p[3];
     const float sum = (((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w))) +
                       (((d.x + d.y) + (d.z + d.w)) + ((e.x + e.y) + (e.z + e.w)));
-    atomicAdd(&g2d[(size_t)G.gid[h] * 9 + c], sum);
+    if (kDet)
+      g2d[(size_t)G.gid[h] * 9 + c] = sum;
+    else
+      atomicAdd(&g2d[(size_t)G.gid[h] * 9 + c], sum);
   }
   __builtin_amdgcn_wave_barrier();
 }
 
 // Stages one hit's nine per-lane values (a fully active wave); flushes when full.
+template <bool kDet>
 __device__ __forceinline__ void stage_hit(const float v[9], uint32_t gid, GradStage& G, int& nst, int off, int lane,
                                           float* g2d) {
   const float w0 = swap32_sum(v[0], v[1]), w1 = swap32_sum(v[2], v[3]), w2 = swap32_sum(v[4], v[5]),
@@ -575,9 +582,21 @@ __device__ __forceinline__ void stage_hit(const float v[9], uint32_t gid, GradSt
   sl[128 + lane] = x2;
   G.gid[nst] = gid;  // the same value from every lane
   if (++nst == kFlush) {
-    stage_flush(G, kFlush, off, lane, g2d);
+    stage_flush<kDet>(G, kFlush, off, lane, g2d);
     nst = 0;
   }
+}
+
+// The partial slot of one (range entry, quadrant) of the reproducible backward: the
+// entry's Gaussian gid took its pairs at [pair_begin[gid], pair_begin[gid] + ntiles),
+// one per tile of its box, row-major; this item's tile (tx, ty) picks one, and the
+// quadrant's index within the tile (2^ql of them) the slot within the pair.
+__device__ __forceinline__ uint32_t det_slot(const Rec& r, uint32_t gid, const uint32_t* pair_begin, int tx, int ty,
+                                             int tl, int ql, int quad) {
+  const uint32_t bx = __float_as_uint(r.r2.y), by = __float_as_uint(r.r2.z);
+  const int tx0 = (int)(bx & 0xffffu) >> tl, tx1 = (int)(bx >> 16) >> tl, ty0 = (int)(by & 0xffffu) >> tl;
+  const uint32_t pair = pair_begin[gid] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+  return (pair << ql) | (uint32_t)quad;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -602,6 +621,7 @@ struct BwdState {
 // lo; compacted into L with the Gaussian's index as tag) in reverse order: per hit
 // T_i = T_{i+1} / (1 - alpha_i), the nine gradient terms, one reduction and one atomic
 // per Gaussian, then the colour behind.
+template <bool kDet>
 __device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, float px, float py, int lane,
                                          GradStage& G, int& nst, int off, BwdState& st, float* g2d) {
   const int nhit = __popcll(hm);
@@ -640,15 +660,29 @@ __device__ __forceinline__ void bwd_hits(const WaveLds& L, uint64_t hm, int lo, 
     v[6] = st.g0 * wgt;
     v[7] = st.g1 * wgt;
     v[8] = st.g2 * wgt;
-    stage_hit(v, __float_as_uint(bx.y), G, nst, off, lane, g2d);
+    stage_hit<kDet>(v, __float_as_uint(bx.y), G, nst, off, lane, g2d);
   }
+}
+
+// What the reproducible backward needs to name a hit's partial slot (see det_slot).
+struct DetCtx {
+  const uint32_t* pair_begin;
+  int tx, ty, tl, ql, quad;
+};
+
+// The compaction tag of a gathered entry: its Gaussian, or (kDet) its partial slot.
+template <bool kDet>
+__device__ __forceinline__ float hit_tag(const Rec& r, uint32_t gid, const DetCtx& dc, bool valid) {
+  if (!kDet) return __uint_as_float(gid);
+  return __uint_as_float(valid ? det_slot(r, gid, dc.pair_begin, dc.tx, dc.ty, dc.tl, dc.ql, dc.quad) : 0u);
 }
 
 // The reverse walk over range offsets [lo_end, hi) (from hi - 1 down), relative to the
 // range start s, in batches of 64 with a register prefetch of the next batch.
+template <bool kDet>
 __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, int lo_end, int hi, uint32_t n_gauss,
                          const Item& it, WaveLds& L, int lane, GradStage& G, int& nst, int off, BwdState& st,
-                         float* g2d) {
+                         float* g2d, const DetCtx& dc) {
   if (!it.live || hi <= lo_end) return;
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   Rec nxt;
@@ -659,8 +693,9 @@ __device__ void bwd_walk(const float* splat, const uint32_t* vals, uint32_t s, i
     const Rec cur = nxt;
     const uint32_t cgid = ngid;
     if (lo > lo_end) fetch_batch(splat, vals, s + max(lo_end, lo - 64), s + lo, n_gauss, lane, nxt, ngid);
-    const uint64_t hm = compact_hits(cur, lo + lane < bh, __uint_as_float(cgid), it, L, lane);
-    bwd_hits(L, hm, lo, px, py, lane, G, nst, off, st, g2d);
+    const bool valid = lo + lane < bh;
+    const uint64_t hm = compact_hits(cur, valid, hit_tag<kDet>(cur, cgid, dc, valid), it, L, lane);
+    bwd_hits<kDet>(L, hm, lo, px, py, lane, G, nst, off, st, g2d);
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -718,9 +753,10 @@ __device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const 
 // A long tile's quadrant, by the whole workgroup in rounds of four chunks from the back.
 // A chunk is one gathered batch, compacted once for both passes; the next round's
 // records are fetched while the current round is walked.
+template <bool kDet>
 __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t n_gauss, const Item& it,
                          WaveLds& L, RoundLds& R, int w, int lane, GradStage& G, int& nst, int off, BwdState st,
-                         float* g2d) {
+                         float* g2d, const DetCtx& dc) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int top = it.live ? wave_max(st.last) : 0;  // the same in every wave
   Rec nxt;
@@ -737,7 +773,8 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
       const int n1 = max(0, hi - (kWaves + w) * kChunk);
       fetch_batch(splat, vals, s + max(0, n1 - kChunk), s + n1, n_gauss, lane, nxt, ngid);
     }
-    const uint64_t hm = compact_hits(cur, c0 + lane < c1, __uint_as_float(cgid), it, L, lane);
+    const bool valid = c0 + lane < c1;
+    const uint64_t hm = compact_hits(cur, valid, hit_tag<kDet>(cur, cgid, dc, valid), it, L, lane);
     float P, L0, L1, L2;
     bwd_local_hits(L, hm, c0, st.last, px, py, P, L0, L1, L2);
     R.v[w][0][lane] = P;
@@ -754,7 +791,7 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
       cs.B1 = fmaf(Pj, cs.B1, R.v[j][2][lane]);
       cs.B2 = fmaf(Pj, cs.B2, R.v[j][3][lane]);
     }
-    bwd_hits(L, hm, c0, px, py, lane, G, nst, off, cs, g2d);
+    bwd_hits<kDet>(L, hm, c0, px, py, lane, G, nst, off, cs, g2d);
     // state in front of the round (identical in every wave)
     for (int j = 0; j < kWaves; ++j) {
       const float Pj = R.v[j][0][lane];
@@ -767,11 +804,14 @@ __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
   }
 }
 
+// kDet: g2d is the partial buffer of the reproducible backward ([pairs << ql][9], zeroed
+// by the caller), each (range entry, quadrant) hit storing its own nine sums there.
+template <bool kDet>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBlocksPerCU))) composite_bwd_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
     int n_views, int n_tiles, int tl, const float* bg, const float* T_final, const int32_t* n_contrib,
-    const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss) {
+    const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss, const uint32_t* pair_begin) {
   __shared__ WaveLds lds[kWaves];
   __shared__ RoundLds round;
   __shared__ GradStage stage[kWaves];
@@ -788,25 +828,53 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
   __builtin_amdgcn_s_setprio(2);
   for (uint32_t li = next_long_item(q, &s_item); li < (n_long << ql); li = next_long_item(q, &s_item)) {
     const int tile = (int)min(order[li >> ql], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(li & ((1u << ql) - 1u)), lane, tl);
+    const int quad = (int)(li & ((1u << ql) - 1u));
+    const Item it = make_item(views, n_views, tile, quad, lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
-    bwd_long(splat, vals, s, n_gauss, it, L, round, w, lane, G, nst, off,
-             bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d);
+    const DetCtx dc{pair_begin, it.qx0 >> tl, it.qy0 >> tl, tl, ql, quad};
+    bwd_long<kDet>(splat, vals, s, n_gauss, it, L, round, w, lane, G, nst, off,
+                   bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d, dc);
   }
   __builtin_amdgcn_s_setprio(0);
   const uint32_t n_items = ((uint32_t)n_tiles - n_long) << ql;
   for (uint32_t item = next_item(q, lane, ql); item < n_items; item = next_item(q, lane, ql)) {
     const int tile = (int)min(order[n_long + (item >> ql)], (uint32_t)n_tiles - 1);
-    const Item it = make_item(views, n_views, tile, (int)(item & ((1u << ql) - 1u)), lane, tl);
+    const int quad = (int)(item & ((1u << ql) - 1u));
+    const Item it = make_item(views, n_views, tile, quad, lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     BwdState st = bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage);
     const int top = it.live ? wave_max(st.last) : 0;
-    bwd_walk(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, st, g2d);
+    const DetCtx dc{pair_begin, it.qx0 >> tl, it.qy0 >> tl, tl, ql, quad};
+    bwd_walk<kDet>(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, st, g2d, dc);
   }
-  stage_flush(G, nst, off, lane, g2d);
+  stage_flush<kDet>(G, nst, off, lane, g2d);
   leave_queue(q, gridDim.x * kWaves, lane);
+}
+
+// The reproducible backward's segmented reduction: view-Gaussian g's nine sums are its
+// partials [pair_begin[g] << ql, (pair_begin[g] + ntiles[g]) << ql) added in that order
+// (tiles row-major, then quadrants).
+__global__ void __launch_bounds__(256) det_reduce_kernel(const float* __restrict__ part,
+                                                         const uint32_t* __restrict__ pair_begin,
+                                                         const int32_t* __restrict__ ntiles, long long n_gauss,
+                                                         int ql, uint32_t capacity, float* g2d) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_gauss) return;
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int nt = ntiles[g];
+  if (nt > 0) {
+    const uint32_t b = pair_begin[g];
+    const uint32_t e = min(b + (uint32_t)nt, capacity);
+    for (size_t k = (size_t)b << ql; k < ((size_t)max(b, e) << ql); ++k) {
+      const float* p = part + k * 9;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] += p[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) g2d[g * 9 + c] = acc[c];
 }
 
 __global__ void background_kernel(const glam_view_info* views, int n_views, long long n_pix, const float* bg,
@@ -877,21 +945,39 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
+size_t det_partial_bytes(const glam_views& v, long long capacity) {
+  const int ql = 2 * (tile_log2(v.tile_w) - 3);
+  return (size_t)capacity * ((size_t)1 << ql) * 9 * sizeof(float);
+}
+
+bool det_supported(const glam_views& v, long long capacity) {
+  const int ql = 2 * (tile_log2(v.tile_w) - 3);
+  return ((unsigned long long)capacity << ql) < (1ull << 32);
+}
+
 glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                                  const float* bg, const float* T_final, const int32_t* n_contrib,
-                                 const float* dimage, float* g2d, hipStream_t s) {
-  const long long n = 9 * v.n_gauss;
-  if (n > 0)
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
-                       g2d, n);
+                                 const float* dimage, float* g2d, float* det_part, hipStream_t s) {
   const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
   if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
+  const bool det = det_part != nullptr;
+  if (det && !det_supported(v, bins.capacity)) return GLAM_ERR_UNSUPPORTED;
+  // the atomics add into g2d; the reproducible path stores into its zeroed partials
+  float* acc = det ? det_part : g2d;
+  const long long n = det ? (long long)(det_partial_bytes(v, bins.capacity) / sizeof(float)) : 9 * v.n_gauss;
+  if (n > 0)
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
+                       acc, n);
   const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : kBwdBlocksPerCU;
   if (v.n_tiles > 0 && v.n_gauss > 0)
-    hipLaunchKernelGGL(composite_bwd_kernel, dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)),
-                       dim3(64 * kWaves), 0, s, proj.splat, bins.vals, bins.ranges, bins.order, bins.status,
-                       bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, T_final, n_contrib, dimage, g2d,
-                       (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
+    hipLaunchKernelGGL(det ? composite_bwd_kernel<true> : composite_bwd_kernel<false>,
+                       dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)), dim3(64 * kWaves), 0, s, proj.splat,
+                       bins.vals, bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl,
+                       bg, T_final, n_contrib, dimage, acc, (uint32_t)bins.capacity, (uint32_t)v.n_gauss,
+                       bins.pair_begin);
+  if (det && v.n_gauss > 0)
+    hipLaunchKernelGGL(det_reduce_kernel, dim3((unsigned)((v.n_gauss + 255) / 256)), dim3(256), 0, s, det_part,
+                       bins.pair_begin, proj.ntiles, (long long)v.n_gauss, ql, (uint32_t)bins.capacity, g2d);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

@@ -88,9 +88,14 @@ class Pipeline:
     scene dictionaries)."""
 
     def __init__(self, scene: dict, device="cuda", capacity: int | None = None, bg=(0.0, 0.0, 0.0),
-                 tile: int = TILE, tuning: dict | None = None):
+                 tile: int = TILE, tuning: dict | None = None, footprint: str = "opacity",
+                 deterministic: bool = False, intermediates: bool = False):
         """tile: binning tile edge (8, 16 or 32); tuning: the compositing schedule
-        (long_log2, fwd_blocks_per_cu, bwd_blocks_per_cu; missing or 0 = default)."""
+        (long_log2, fwd_blocks_per_cu, bwd_blocks_per_cu; missing or 0 = default);
+        footprint: "opacity" (the exact alpha >= 1/255 box) or "3sigma" (the lineage's
+        tile-granular 3-sigma square); deterministic: reproducible gradients (no
+        floating-point atomics in the compositing adjoint); intermediates: the backward
+        also writes the 2-D gradients d(u, v, A, B, C, opacity, rgb) to self.d2d."""
         self.device = torch.device(device)
         dev = self.device
         self.scene = scene
@@ -100,6 +105,15 @@ class Pipeline:
         self.flags = B.GLAM_PLAIN if self.plain else 0
         if not self.plain and scene.get("opacity_mode", "tanh") == "sigmoid":
             self.flags |= B.GLAM_OPACITY_SIGMOID
+        if footprint not in ("opacity", "3sigma"):
+            raise ValueError(f"footprint {footprint!r}: 'opacity' or '3sigma'")
+        if footprint == "3sigma":
+            self.flags |= B.GLAM_FOOTPRINT_3SIGMA
+        self.deterministic = bool(deterministic)
+        self.intermediates = bool(intermediates)
+        self.bflags = self.flags | (B.GLAM_DETERMINISTIC_GRADS if self.deterministic else 0) | (
+            B.GLAM_RETURN_INTERMEDIATES if self.intermediates else 0)
+        self.generation = 0  # forward passes run so far (GlamRender checks it)
         self.ssim_weight = float(scene.get("ssim_weight", 0.0))
         cams = scene["cams"]
         self.tile = int(tile)
@@ -124,6 +138,7 @@ class Pipeline:
         self.target = torch.cat([_f32(t, dev).reshape(-1) for t in scene["targets"]])
         self.dimage = torch.empty(3 * npix, device=dev)
         self.loss = torch.empty(self.vt.n, device=dev)
+        self.loss_total = torch.empty(1, device=dev)
         self.bg = torch.zeros(4, device=dev)
         self.bg[:3] = torch.tensor(bg, dtype=torch.float32)
         self.ws_loss = torch.empty(B.glam_loss_workspace_bytes(self.vt.views), device=dev, dtype=torch.uint8)
@@ -156,17 +171,18 @@ class Pipeline:
                            splat=torch.empty((n, 12), device=dev))
         self.proj = B.Projected(*(self.proj_t[k].data_ptr() for k in ("uv", "conic", "depth", "ext", "ntiles",
                                                                      "splat")))
-        self._alloc_bins(capacity if capacity else max(1024, 4 * n))
+        self.pair_begin = torch.empty(max(n, 1), device=dev, dtype=torch.int32) if self.deterministic else None
         # gradients
         self.g2d = torch.empty((n, 9), device=dev)
+        self.d2d = torch.empty((9, n), device=dev) if self.intermediates else None
+        d2d = self.d2d.data_ptr() if self.intermediates else None
         if self.plain:
             G = self.gauss.n
             self.dg = {k: torch.empty((r, G) if r > 1 else (G,), device=dev)
                        for k, r in (("mean", 3), ("log_scale", 3), ("quat", 4), ("logit", 1), ("rgb", 3))}
             dgs = B.Gaussians(*(self.dg[k].data_ptr() for k in ("mean", "log_scale", "quat", "logit", "rgb")), G)
             self.dgs = dgs
-            self.grads = B.Grads(self.g2d.data_ptr(), dgs, None, None, None, None)
-            self.ws_dec = torch.empty(16, device=dev, dtype=torch.uint8)
+            self.grads = B.Grads(self.g2d.data_ptr(), dgs, None, None, None, None, d2d)
         else:
             self.dg = {k: torch.empty((r, n) if r > 1 else (n,), device=dev)
                        for k, r in (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("rgb", 3))}
@@ -176,9 +192,8 @@ class Pipeline:
             self.pgrad = {k: torch.empty_like(p[k]) for k in ("feat", "offs", "log_scale", "mlp")}
             self.grads = B.Grads(self.g2d.data_ptr(), dgs, self.pgrad["feat"].data_ptr(),
                                  self.pgrad["offs"].data_ptr(), self.pgrad["log_scale"].data_ptr(),
-                                 self.pgrad["mlp"].data_ptr())
-            nb = B.glam_decode_bwd_workspace_bytes(self.anchors, self.vt.views, self.n_parts)
-            self.ws_dec = torch.empty(max(16, nb), device=dev, dtype=torch.uint8)
+                                 self.pgrad["mlp"].data_ptr(), d2d)
+        self._alloc_bins(capacity if capacity else max(1024, 4 * n))
 
     # ------------------------------------------------------------------------------
     def grow_anchors(self, centres, n_new: int, partition: int, eps: float, centres_stride: int | None = None):
@@ -239,9 +254,15 @@ class Pipeline:
         self.order = torch.empty(self.vt.n_tiles, device=dev, dtype=torch.int32)
         self.queue = torch.zeros(B.GLAM_QUEUE_WORDS, device=dev, dtype=torch.int32)
         self.bins = B.Bins(self.keys.data_ptr(), self.vals.data_ptr(), self.ranges.data_ptr(), self.capacity,
-                           self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr(), self.tuning)
+                           self.status.data_ptr(), self.order.data_ptr(), self.queue.data_ptr(), self.tuning,
+                           self.pair_begin.data_ptr() if self.pair_begin is not None else None)
         nb = B.glam_bin_sort_workspace_bytes(self.vt.views, self.capacity)
         self.ws_sort = torch.empty(nb, device=dev, dtype=torch.uint8)
+        # the backward's workspace: the decode adjoint's and, when reproducible, the
+        # per-(pair, quadrant) partials, which scale with the pair capacity
+        nb = B.glam_render_bwd_workspace_bytes(None if self.plain else self.anchors, self.vt.views, self.n_parts,
+                                               self.capacity, self.bflags)
+        self.ws_dec = torch.empty(max(256, nb), device=dev, dtype=torch.uint8)
 
     # ------------------------------------------------------------------------------
     def init_optimizer(self):
@@ -332,14 +353,14 @@ class Pipeline:
         self.n_eval = torch.zeros(self.vt.n_pix, device=self.device, dtype=torch.int32) if on else None
 
     def compute_loss(self, s=None):
-        B.glam_loss(self.vt.views, self.image, self.target, self.ssim_weight, self.dimage, self.loss, self.ws_loss,
-                    self.ws_loss.numel(), s or self.stream())
+        B.glam_loss(self.vt.views, self.image, self.target, self.ssim_weight, self.dimage, self.loss, self.loss_total,
+                    self.ws_loss, self.ws_loss.numel(), s or self.stream())
 
     def backward(self, s=None, dimage=None):
         B.glam_render_bwd(self.proj, self.bins, self.vt.views, self.bg, self.T_final, self.n_contrib,
                           self.dimage if dimage is None else dimage, self.gauss,
                           None if self.plain else self.anchors, None if self.plain else self.params["mlp"],
-                          self.n_parts, self.flags, self.grads, self.ws_dec, self.ws_dec.numel(), s or self.stream())
+                          self.n_parts, self.bflags, self.grads, self.ws_dec, self.ws_dec.numel(), s or self.stream())
 
     def composite_bwd(self, s=None, dimage=None):
         B.glam_composite_bwd(self.proj, self.bins, self.vt.views, self.bg, self.T_final, self.n_contrib,
@@ -360,6 +381,7 @@ class Pipeline:
         self.bin_sort(s)
         self.render(s)
         self.compute_loss(s)
+        self.generation += 1
 
     def step(self, s=None):
         self.forward(s)
@@ -402,19 +424,29 @@ class GlamRender(torch.autograd.Function):
     """images = render(params); backward runs the reverse compositing, projection and
     decode adjoints.  params: (feat, offs, log_scale, mlp) in anchor mode or (mean,
     log_scale, quat, logit, rgb) in plain mode; they must be the tensors the Pipeline
-    holds (the kernels read them in place)."""
+    holds (the kernels read them in place), and the backward must run before the
+    Pipeline renders again (it reads the forward's stored per-pixel state)."""
+
+    NAMES = {True: ("mean", "log_scale", "quat", "logit", "rgb"), False: ("feat", "offs", "log_scale", "mlp")}
 
     @staticmethod
     def forward(ctx, pipe: Pipeline, *params):
+        names = GlamRender.NAMES[pipe.plain]
+        if len(params) != len(names) or any(p.data_ptr() != pipe.params[k].data_ptr() for p, k in zip(params, names)):
+            raise ValueError(f"GlamRender takes the Pipeline's own parameter tensors {names}")
         pipe.decode_project()
         pipe.bin_sort()
         pipe.render()
+        pipe.generation += 1
         ctx.pipe = pipe
+        ctx.generation = pipe.generation
         return pipe.image.clone()
 
     @staticmethod
     def backward(ctx, dimage):
         pipe = ctx.pipe
+        if pipe.generation != ctx.generation:
+            raise RuntimeError("the Pipeline rendered again after this forward; its stored state is gone")
         pipe.backward(dimage=dimage.contiguous())
         if pipe.plain:
             g = tuple(pipe.dg[k].clone() for k in ("mean", "log_scale", "quat", "logit", "rgb"))
@@ -431,7 +463,7 @@ class GlamLoss(torch.autograd.Function):
         pipe.image.copy_(image)
         pipe.compute_loss()
         ctx.pipe = pipe
-        return pipe.loss.sum()
+        return pipe.loss_total[0].clone()
 
     @staticmethod
     def backward(ctx, g):

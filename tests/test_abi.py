@@ -198,3 +198,58 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libglam.so"))
     with pytest.raises(ImportError):
         B.load()
+
+
+def test_backward_modes_validated_before_launch():
+    lib = B.load()
+    fake = 0x100000  # aligned, never dereferenced: validation fails first
+    P = C.c_void_p
+    s = synth.plain_scene(1, 10, 32, 32)
+    st, info, views = _build(s["cams"], None, 0, 10)
+    views.host = C.cast(info, C.c_void_p)
+    views.dev = fake
+    g = B.Gaussians(fake, fake, fake, fake, fake, 10)
+    proj = B.Projected(fake, fake, fake, fake, fake, fake)
+    plain = B.GLAM_PLAIN
+    det = plain | B.GLAM_DETERMINISTIC_GRADS
+    inter = plain | B.GLAM_RETURN_INTERMEDIATES
+    # workspace: none in plain mode, the reproducible partials (36 B per pair and 8x8
+    # quadrant) with the flag, unknown flags give 0
+    assert lib.glam_render_bwd_workspace_bytes(None, B.ref(views), 0, 1000, plain) == 0
+    w16 = lib.glam_render_bwd_workspace_bytes(None, B.ref(views), 0, 1000, det)
+    assert w16 >= 1000 * 4 * 36
+    assert lib.glam_render_bwd_workspace_bytes(None, B.ref(views), 0, 1000, det | (1 << 20)) == 0
+    st8, info8, views8 = _build(s["cams"], None, 0, 10, (8, 8))
+    assert lib.glam_render_bwd_workspace_bytes(None, B.ref(views8), 0, 1000, det) < w16
+    # an anchor scene adds the decode adjoint's workspace in front
+    sa = synth.anchor_scene(2, [20], 1, W=32, H=32, fx=30)
+    sta, infoa, viewsa = _build(sa["cams"], sa["part_begin"], sa["K"])
+    an = B.Anchors(fake, fake, fake, fake, 20, 32, 10, 32)
+    # size queries read the host table: none given, no size
+    assert lib.glam_render_bwd_workspace_bytes(B.ref(an), B.ref(viewsa), 1, 1000, 0) == 0
+    assert lib.glam_decode_bwd_workspace_bytes(B.ref(an), B.ref(viewsa), 1) == 0
+    assert lib.glam_loss_workspace_bytes(B.ref(viewsa)) == 0
+    viewsa.host = C.cast(infoa, C.c_void_p)
+    wa = lib.glam_render_bwd_workspace_bytes(B.ref(an), B.ref(viewsa), 1, 1000, 0)
+    assert wa >= lib.glam_decode_bwd_workspace_bytes(B.ref(an), B.ref(viewsa), 1) > 0
+    assert lib.glam_render_bwd_workspace_bytes(B.ref(an), B.ref(viewsa), 1, 1000, B.GLAM_DETERMINISTIC_GRADS) > wa
+    dg = B.Gaussians(fake, fake, fake, fake, fake, 10)
+
+    def call(flags, pair_begin=fake, d2d=fake, ws=fake, wsb=w16):
+        bins = B.Bins(fake, fake, fake, 1000, fake, fake, fake, B.Tuning(0, 0, 0, 0), pair_begin)
+        grads = B.Grads(fake, dg, None, None, None, None, d2d)
+        return lib.glam_render_bwd(B.ref(proj), B.ref(bins), B.ref(views), None, P(fake), P(fake), P(fake), B.ref(g),
+                                   None, None, 0, flags, B.ref(grads), P(ws) if ws else None, wsb, None)
+
+    assert call(det, pair_begin=None) == B.GLAM_ERR_INVALID_ARG   # needs the bin sort's pair offsets
+    assert call(det, pair_begin=fake + 4) == B.GLAM_ERR_INVALID_ARG
+    assert call(det, wsb=w16 - 1) == B.GLAM_ERR_WORKSPACE
+    assert call(inter, d2d=None) == B.GLAM_ERR_INVALID_ARG         # needs the d2d buffer
+    assert call(plain | (1 << 9)) == B.GLAM_ERR_INVALID_ARG       # unknown flag
+    # forward calls take no backward-only flag
+    assert lib.glam_project(B.ref(g), B.ref(views), det, B.ref(proj), None) == B.GLAM_ERR_INVALID_ARG
+    assert lib.glam_project(B.ref(g), B.ref(views), inter, B.ref(proj), None) == B.GLAM_ERR_INVALID_ARG
+    # the loss total, when given, must be aligned
+    ws = lib.glam_loss_workspace_bytes(B.ref(views))
+    assert lib.glam_loss(B.ref(views), P(fake), P(fake), C.c_float(0.0), P(fake), P(fake), P(fake + 4), P(fake), ws,
+                         None) == B.GLAM_ERR_INVALID_ARG

@@ -1,17 +1,19 @@
 """Config 3's gradients against finite differences: 64 parameters of the benchmark's
-workload (anchor features, offsets and log-scales; half the largest gradients of each
-kind, half drawn at random among the non-negligible ones) whose gradient of view 0's
-loss, computed on the GPU in the benchmark's launch configuration (stored tile edge and
-schedule), is compared with the FP64 oracle's central finite difference (h = 1e-6;
-parameters whose +-h perturbation flips a recorded discrete decision of the oracle are
-skipped).
+workload, stratified as 16 MLP weights and biases, 16 anchor features, 16 offsets and
+16 log-scales (half the largest gradients of each kind, half drawn at random among the
+non-negligible ones).  Their gradient of view 0's loss, computed on the GPU in the
+benchmark's launch configuration (stored tile edge and schedule), is compared with the
+FP64 oracle's central finite difference (h = 1e-6, differenced pixel by pixel and
+summed exactly), and the oracle's own analytic gradient with the same difference.
 
-MLP weights are left out at this size: one moves all 500k Gaussians, so between -h and +h
-some pixel's alpha crosses the 1/255 threshold at an entry before its last contributor
-(a decision the oracle's flip record does not hold), a jump of about (1/255) c / (3 W H)
-in the loss, i.e. ~1e-3 in the difference quotient, larger than most of these gradients.
-The MLP gradients are pinned by the oracle's analytic adjoint (stage-wise and end-to-end
-GPU tests) and by finite differences on small scenes."""
+The loss is piecewise smooth: the skip threshold, the stop rule, the depth order and the
+0.99 clamp of Eq. 1, the ReLU gates of Eq. 2 / Eq. 6, the Jacobian clamp and the L1 term
+jump or kink.  The oracle records every one of those decisions at -h and +h.  Where
+none changes, the plain difference is the reference.  Where one does (a weight of an MLP
+moves all 500k Gaussians, and some pixel's alpha then crosses 1/255 somewhere in its
+list), the plain difference straddles a jump and the reference is the difference taken
+with every decision held at the unperturbed point (the derivative of the piece the
+parameters sit on, which the adjoint computes); both counts are printed."""
 import time
 
 import numpy as np
@@ -26,9 +28,10 @@ from paper_2607_21416_amd.pipeline import Pipeline
 
 pytestmark = pytest.mark.gpu
 
-COUNTS = {"feat": 22, "offs": 21, "log_scale": 21}  # 64 parameters
+COUNTS = {"mlp": 16, "feat": 16, "offs": 16, "log_scale": 16}  # 64 parameters
 
 
+@pytest.mark.timeout(900)
 def test_view0_gradients_match_finite_differences():
     scene = synth.config("C3")
     choice = tuning.autotune(scene, device="cuda")
@@ -46,26 +49,39 @@ def test_view0_gradients_match_finite_differences():
     pipe.backward(dimage=dim)
     torch.cuda.synchronize()
     grads = {k: v.cpu().numpy().astype(np.float64) for k, v in pipe.pgrad.items()}
+    # the oracle's analytic gradient of the same loss, and its decision record
+    fwd = oracle.forward(scene, [0])
+    ref = oracle.backward(scene, fwd)
+    _, base = oracle.loss_maps(scene, [0])
     rng = np.random.default_rng(3003)
-    checked = skipped = 0
-    worst = 0.0
+    checked = frozen = 0
+    worst_gpu = worst_orc = 0.0
     t0 = time.time()
     for name, count in COUNTS.items():
         g = grads[name]
         flat = np.abs(g).ravel()
+        gmax = flat.max()
         picks = list(np.argsort(-flat)[: count // 2])
-        nz = np.setdiff1d(np.flatnonzero(flat > 1e-3 * flat.max()), picks)
+        nz = np.setdiff1d(np.flatnonzero(flat > 1e-3 * gmax), picks)
         picks += list(rng.choice(nz, size=min(len(nz), count - len(picks)), replace=False))
+        assert len(picks) == count
         for fi in picks:
             idx = np.unravel_index(int(fi), g.shape)
             fd, flipped = oracle.fd_gradient(scene, name, idx, h=1e-6, views=[0])
             if flipped:
-                skipped += 1
-                continue
-            tol = 1e-3 * abs(fd) + 1e-5 * flat.max()
-            assert abs(g[idx] - fd) <= tol, (name, idx, g[idx], fd)
-            worst = max(worst, abs(g[idx] - fd) / tol)
+                fd = oracle.fd_gradient_frozen(scene, name, idx, h=1e-6, views=[0], decisions=base)
+                frozen += 1
+            # the oracle's adjoint against its own difference (FP64 both)
+            bound_o = 1e-5 * abs(fd) + 1e-9 * np.abs(ref[name]).max()
+            assert abs(ref[name][idx] - fd) <= bound_o, (name, idx, ref[name][idx], fd, flipped)
+            worst_orc = max(worst_orc, abs(ref[name][idx] - fd) / bound_o)
+            # the GPU's gradient against it: 1e-3 relative, with a floor of 1e-6 of the
+            # tensor's largest gradient for elements that are small differences
+            tol = 1e-3 * abs(fd) + 1e-6 * gmax
+            assert abs(g[idx] - fd) <= tol, (name, idx, g[idx], fd, flipped)
+            worst_gpu = max(worst_gpu, abs(g[idx] - fd) / tol)
             checked += 1
-        print(f"fd {name}: {checked} checked, {skipped} skipped so far, largest error / bound {worst:.3f} "
+        print(f"fd {name}: {checked} checked so far ({frozen} with decisions held: a decision flips "
+              f"between -h and +h), largest error / bound: GPU {worst_gpu:.3f}, oracle {worst_orc:.3f} "
               f"({time.time() - t0:.0f} s)", flush=True)
-    assert checked >= 0.75 * sum(COUNTS.values())
+    assert checked == sum(COUNTS.values())

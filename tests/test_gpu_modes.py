@@ -1,0 +1,227 @@
+"""The backward's modes and the loss total, on the GPU through the C ABI.
+
+- Reproducible gradients (GLAM_DETERMINISTIC_GRADS: per-(pair, quadrant) partials and a
+  fixed-order segmented reduction instead of floating-point atomics in the adjoint of
+  Eq. 1): two steps give bit-identical gradients, and so do other compositing schedules
+  at the same tile edge; they match the default path to FP32 rounding and the oracle
+  stage-wise.
+- Intermediates (GLAM_RETURN_INTERMEDIATES): the 2-D gradients d(u, v, A, B, C, opacity,
+  rgb) equal the conversion of the moments the adjoint accumulates, and the oracle's.
+- The loss total (Eq. 3 summed over the step's views) equals the sum of the per-view
+  losses.
+- The 3-sigma footprint of the splatting lineage (GLAM_FOOTPRINT_3SIGMA): radii against
+  the oracle's, binning bit-exact, pixels and 2-D gradients stage-wise, images end to end.
+- The autograd wrapper refuses foreign tensors and a backward after a newer forward.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import AMB_STAGE, AMB_VALUE, gpu_splats, grad_close, host, view_image, view_pixels, view_slices
+from paper_2607_21416_amd.pipeline import GlamLoss, GlamRender, Pipeline
+from test_gpu_parity import g2d_gradients
+
+pytestmark = pytest.mark.gpu
+
+SCENES = {
+    "plain_ragged": lambda: synth.plain_scene(1011, 2000, 70, 45),
+    "plain_dense": lambda: _dense(),
+    "anchor_small": lambda: synth.anchor_scene(1012, [1500, 800], 2, W=200, H=120, fx=140.0, ssim_weight=0.2,
+                                               bias_std=0.2),
+    "C3": lambda: synth.config("C3"),
+}
+
+
+def _dense():
+    # every tile's range long enough for the workgroup path (see test_gpu_parity)
+    s = synth.plain_scene(1015, 20000, 64, 48)
+    s["logit"] = (s["logit"] - 1.8).astype(np.float32)
+    return s
+
+
+def _run(scene, **kw):
+    pipe = Pipeline(scene, device="cuda", **kw)
+    pipe.fit_capacity()
+    pipe.status.zero_()
+    pipe.step()
+    torch.cuda.synchronize()
+    pipe.check_status()
+    return pipe
+
+
+def _grads(pipe):
+    out = {"g2d": pipe.g2d.cpu().numpy().copy()}
+    src = pipe.dg if pipe.plain else pipe.pgrad
+    out.update({k: v.cpu().numpy().copy() for k, v in src.items()})
+    return out
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_deterministic_gradients_repeat_bit_for_bit(name):
+    scene = SCENES[name]()
+    print(f"deterministic gradients: {name}", flush=True)
+    det = _run(scene, deterministic=True)
+    first = _grads(det)
+    det.step()
+    torch.cuda.synchronize()
+    again = _grads(det)
+    for k in first:
+        assert np.array_equal(first[k].view(np.uint32), again[k].view(np.uint32)), k
+    # another compositing schedule (grid sizes, long-tile threshold) at the same tile edge
+    other = _run(scene, deterministic=True, tuning=dict(long_log2=7, fwd_blocks_per_cu=3, bwd_blocks_per_cu=3))
+    third = _grads(other)
+    for k in first:
+        assert np.array_equal(first[k].view(np.uint32), third[k].view(np.uint32)), k
+    # the default path (atomics) agrees to FP32 rounding
+    ref = _grads(_run(scene))
+    for k in first:
+        if k == "g2d":
+            continue
+        grad_close(first[k], ref[k], name=f"{name} d{k} reproducible vs atomics")
+
+
+def test_deterministic_gradients_match_oracle_stagewise():
+    scene = SCENES["anchor_small"]()
+    pipe = _run(scene, deterministic=True, intermediates=True)
+    h = host(pipe)
+    acc = oracle.zero_grads(scene)
+    dims = []
+    for v, sl in enumerate(view_slices(pipe)):
+        pr, gs = gpu_splats(h, sl)
+        vals = h["vals"].astype(np.int64) - sl["g0"]
+        ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
+        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v])
+        _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
+        d[:, (ref["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0] = 0.0
+        dims.append(d)
+    flat = np.concatenate([d.reshape(-1) for d in dims]).astype(np.float32)
+    pipe.backward(dimage=torch.from_numpy(flat).cuda())
+    torch.cuda.synchronize()
+    hb = host(pipe)
+    d2d = pipe.d2d.cpu().numpy()
+    for v, sl in enumerate(view_slices(pipe)):
+        pr, gs = gpu_splats(h, sl)
+        vals = h["vals"].astype(np.int64) - sl["g0"]
+        ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
+        g2d = oracle.render_bwd(pr, gs, vals, ranges, scene["cams"][v], dims[v])
+        got = d2d[:, sl["g0"]:sl["g1"]]
+        conv = g2d_gradients(hb["g2d"][sl["g0"]:sl["g1"]], h["conic"][:, sl["g0"]:sl["g1"]])
+        for k, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
+            grad_close(got[k], g2d[k], name=f"view {v} d{nm} (reproducible, intermediates)")
+            # the intermediates are the moments' conversion, formed in FP32 on the device
+            np.testing.assert_allclose(got[k], conv[k], rtol=1e-6, atol=1e-7 * np.abs(conv[k]).max() + 1e-30)
+        dgv = {k: hb["dg"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dg"]}
+        oracle.decode_bwd(scene, scene["cams"][v]["partition"], scene["cams"][v], dgv, acc)
+    for k in acc:
+        grad_close(hb["pgrad"][k], acc[k], name=f"anchor d{k} (reproducible)")
+
+
+def test_loss_total_is_the_sum_of_the_views():
+    for name in ("plain_ragged", "anchor_small"):
+        pipe = _run(SCENES[name]())
+        per_view = pipe.loss.cpu().numpy().astype(np.float64)
+        total = float(pipe.loss_total.cpu().numpy()[0])
+        assert total == np.float32(per_view.sum())
+        # and GlamLoss returns it
+        img = pipe.image.clone().requires_grad_(True)
+        L = GlamLoss.apply(pipe, img)
+        assert float(L) == total
+
+
+def _r_ambiguous(cov2d):
+    """Gaussians whose 3 sqrt(lambda_max) is within rounding of an integer (their FP32
+    radius may be one more or less than the FP64 one)."""
+    a, b, c = cov2d
+    lam = 0.5 * (a + c) + np.sqrt(0.25 * (a - c) ** 2 + b * b)
+    x = 3 * np.sqrt(lam)
+    return np.abs(x - np.round(x)) < 1e-5 * np.maximum(x, 1.0)
+
+
+@pytest.mark.parametrize("name,tile", [("plain_ragged", 16), ("anchor_small", 8), ("C2", 16)])
+def test_3sigma_footprint(name, tile):
+    scene = synth.config("C2") if name == "C2" else SCENES[name]()
+    print(f"3-sigma footprint: {name}, tile {tile}", flush=True)
+    pipe = _run(scene, footprint="3sigma", tile=tile)
+    pipe.count_evaluations()
+    pipe.step()
+    torch.cuda.synchronize()
+    h = host(pipe)
+    sls = view_slices(pipe)
+    G = h["ntiles"].shape[0]
+    prect = np.zeros((4, G), np.int32)
+    nt = np.zeros(G, np.int32)
+    for v, sl in enumerate(sls):
+        g0, g1 = sl["g0"], sl["g1"]
+        # radius against the oracle's (fed the GPU's Gaussians), off rounding ties
+        if scene["kind"] == "plain":
+            gsv = oracle.view_gaussians(scene, v)
+        else:
+            gsv = {k: h["dec"][k][..., g0:g1].astype(np.float64) for k in h["dec"]}
+        ref = oracle.project(gsv, scene["cams"][v], tile=(tile, tile), footprint="3sigma")
+        vis = (h["ntiles"][g0:g1] > 0) & (ref["ntiles"] > 0)
+        amb = _r_ambiguous(ref["cov2d"])
+        r_gpu = h["ext"][0, g0:g1]
+        assert (r_gpu[vis & ~amb] == ref["ext"][0][vis & ~amb]).all()
+        assert (h["ext"][1, g0:g1] == r_gpu).all()
+        prect[:, g0:g1], nt[g0:g1] = oracle.rect_f32(h["uv"][0, g0:g1], h["uv"][1, g0:g1], r_gpu, r_gpu, sl["W"], sl["H"],
+                                                     (tile, tile))
+    # binning bit-exact from the GPU's centres and radii
+    assert np.array_equal(nt, h["ntiles"])
+    gb = [sl["g0"] for sl in sls] + [sls[-1]["g1"]]
+    ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), gb, scene["cams"], (tile, tile))
+    assert h["P"] == ref["P"] and np.array_equal(h["vals"], ref["vals"]) and np.array_equal(h["ranges"], ref["ranges"])
+    # pixels stage-wise (the record's box is the widened one: every pixel of the tiles)
+    dims = []
+    for v, sl in enumerate(sls):
+        pr, gs = gpu_splats(h, sl)
+        vals = h["vals"].astype(np.int64) - sl["g0"]
+        ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
+        r = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v], tile=(tile, tile))
+        ok = (r["amb"] & AMB_STAGE) == 0
+        img = view_image(h, sl)
+        assert np.abs(img - r["image"])[:, ok].max() <= 1e-4
+        assert np.array_equal(view_pixels(h, sl, "n_contrib")[ok], r["n_contrib"][ok])
+        assert np.array_equal(view_pixels(h, sl, "n_eval")[ok], r["n_eval"][ok])
+        _, _, _, d = oracle.loss(img.astype(np.float64), scene["targets"][v], scene["ssim_weight"])
+        d[:, (r["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0] = 0.0
+        dims.append(d)
+    # the 2-D gradients stage-wise
+    flat = np.concatenate([d.reshape(-1) for d in dims]).astype(np.float32)
+    pipe.backward(dimage=torch.from_numpy(flat).cuda())
+    torch.cuda.synchronize()
+    g2d_gpu = pipe.g2d.cpu().numpy()
+    for v, sl in enumerate(sls):
+        pr, gs = gpu_splats(h, sl)
+        vals = h["vals"].astype(np.int64) - sl["g0"]
+        ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
+        ref2 = oracle.render_bwd(pr, gs, vals, ranges, scene["cams"][v], dims[v], tile=(tile, tile))
+        got = g2d_gradients(g2d_gpu[sl["g0"]:sl["g1"]], h["conic"][:, sl["g0"]:sl["g1"]])
+        for k, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
+            grad_close(got[k], ref2[k], name=f"{name} 3-sigma view {v} d{nm}")
+    # images end to end, where no radius is a rounding tie
+    fwd = oracle.forward(scene, tile=(tile, tile), footprint="3sigma")
+    for v, (sl, r) in enumerate(zip(sls, fwd)):
+        if _r_ambiguous(r["proj"]["cov2d"])[r["proj"]["ntiles"] > 0].any():
+            continue
+        ok = (r["amb"] & AMB_VALUE) == 0
+        assert np.abs(view_image(h, sl) - r["image"])[:, ok].max() <= 1e-4
+
+
+def test_autograd_wrapper_guards():
+    scene = SCENES["anchor_small"]()
+    pipe = _run(scene)
+    params = [pipe.params[k] for k in ("feat", "offs", "log_scale", "mlp")]
+    with pytest.raises(ValueError):
+        GlamRender.apply(pipe, *[p.clone() for p in params])
+    leaves = [p.requires_grad_(True) for p in params]
+    img = GlamRender.apply(pipe, *leaves)
+    L = GlamLoss.apply(pipe, img)
+    pipe.step()  # renders again: the first forward's state is gone
+    with pytest.raises(RuntimeError):
+        L.backward()
+    for p in params:
+        p.requires_grad_(False)
