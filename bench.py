@@ -4,18 +4,23 @@ MI355X: anchor-MLP decode -> projection -> tile bin + depth sort -> compositing 
 L1 + 0.2 (1 - SSIM) loss -> backward to anchor features, offsets, scales and MLP
 weights (Sec. III-A and III-D of the paper).
 
-Workload (the metric's configuration): 50k anchors x 10 offsets = 500k Gaussians on the
-synthetic street corridor, four keyframe views at 1226x370.  One step is the whole
-path for the four views in one batched launch sequence, replayed from a HIP graph; a
-mapping iteration is one keyframe view rendered forward and backward, so
-value = 4 * steps / second.
+Headline (M1): mapping iterations per second at the metric's configuration, 50k anchors
+x 10 offsets = 500k Gaussians on the synthetic street corridor, 1226x370, one keyframe
+view per iteration (the paper samples one keyframe per mapping iteration, Sec. IV-B):
+the whole path for view 0 of config 3, replayed from a HIP graph; value = steps / s.
 
-Also reported: per-stage times, Gaussian-pixel evaluations/s, the roofline of the
-dominant kernel, the batched-vs-plain speedup on 16 partitions x 4 views (one batched
-graph replay against 64 sequential per-view launch sequences), and the FP64 CPU oracle
-timed on this host on the same workload.
+Also reported: M1' (config 3's four views in one batched step: steps/s and view
+iterations/s), per-stage times and Gaussian-pixel evaluations/s, each kernel's
+fraction of its roofline (the work per unit of the hot-path scope table: lane-op slots
+for the compositing kernels, bytes for the HBM-bound stages, matrix-core FLOP for the
+MLPs) against the published peaks and against ceilings measured on this GPU by
+microbenchmarks, the batched-vs-plain speedup on 16 partitions x 4 views (one batched
+graph replay against the 64 per-view launch sequences, eager and replayed from a graph
+at the same tile edge and schedule), and the FP64 CPU oracle timed on this host.
 
-Prints one JSON line on stdout; progress goes to stderr.
+Prints one JSON line on stdout; progress goes to stderr.  --headline-only runs the
+headline workload alone (the profiler runs use it, so that every kernel's average is
+the headline's).
 """
 from __future__ import annotations
 
@@ -28,22 +33,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per Gaussian-pixel evaluation (FP32 operations of the method as built,
-# an FMA counted as two, exp2 as one; the render record holds the conic pre-scaled to a
-# base-2 exponent):
-#   forward:  offset 2, exponent form 7, exp2 1, opacity 1, clamp 1, threshold 1,
-#             transmittance 2, stop test 1, weight 1, colour 6            -> 23
-#   backward: the forward's alpha 13, T_i recovery 2, colour gradient 4, alpha gradient 9,
-#             behind-colour update 6, opacity/power 2, the five moments of dL/dpower
-#             from which the centre and conic gradients follow 5         -> 41
+# Algorithmic work per unit, after the hot-path scope table's roofline rows:
+#   forward compositing: per Gaussian-pixel evaluation about 18 FP32 VALU operations and
+#     one exp, the transcendental issuing at a quarter of the VALU rate: 22 lane-op slots
+#   backward compositing: per evaluation about 45 VALU operations, one exp and one
+#     reciprocal: 53 lane-op slots
+# against the chip's FP32 VALU issue rate, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz =
+# 39.32 T lane-op slots/s (non-packed FP32; an FMA is one slot).  The same work in the
+# FLOP convention of the kernels as built (an FMA counted as two, exp2 as one):
+#   forward: offset 2, exponent form 7, exp2 1, opacity 1, clamp 1, threshold 1,
+#            transmittance 2, stop test 1, weight 1, colour 6 -> 23 FLOP
+#   backward: the forward's alpha 13, T_i recovery 2, colour gradient 4, alpha
+#            gradient 9, behind-colour update 6, opacity/power 2, the five moments of
+#            dL/dpower 5 -> 41 FLOP, against 78.6 TFLOP/s
+SLOTS_FWD = 22
+SLOTS_BWD = 53
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12  # T lane-op slots/s
 FLOP_FWD = 23
 FLOP_BWD = 41
 PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, scalar (non-packed) FP32
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_FP32_TFLOPS = 157.3  # dense FP32 matrix cores
 
-# Algorithmic work per unit of the other stages, for the whole-step roofline fraction
-# (each stage's ideal time is the larger of its compute and HBM times at the peaks):
+# The other stages, for their own fractions and the whole-step one (each stage's ideal
+# time is the larger of its compute and HBM times at the peaks):
 #   decode + projection: 13,952 FLOP per anchor-view (three MLPs 36 -> 32 -> {10, 30, 70},
 #     FMA = 2, on the matrix cores); 264 B read per anchor (position 3, features 32,
 #     log-scale 1, offsets 30 words) once per partition; 96 B written per view-Gaussian
@@ -81,6 +94,14 @@ def split_views(scene):
                    cams=[dict(cam, partition=0)], targets=[scene["targets"][v]])
         out.append(sub)
     return out
+
+
+def one_view(scene, v):
+    """The single-view workload of view v of an anchor scene (the headline iteration):
+    the whole scene's anchors and MLP sets, one camera and its target."""
+    sub = dict(scene)
+    sub.update(cams=[scene["cams"][v]], targets=[scene["targets"][v]])
+    return sub
 
 
 def timed(torch, fn, iters, stream):
@@ -155,27 +176,59 @@ def profiled_traffic(kernel, launch):
     return int(round(k["fetch_bytes"] + k["write_bytes"]))
 
 
-def whole_step_roofline(pipe, ms, pairs, evals_fwd, evals_bwd, st=None):
-    """Sum over the stages of the step of each stage's ideal time (the larger of its
-    compute and HBM times at the peaks, for its algorithmic work counted from the
-    pipeline's own sizes), against the measured step; per stage too when `st` holds the
-    stages' measured times."""
+def stage_work(pipe, pairs, evals_fwd, evals_bwd):
+    """Each stage's algorithmic work, counted from the pipeline's own sizes: matrix-core
+    FLOP, HBM bytes and VALU lane-op slots (see the constants above)."""
     passes = int(pipe.status.cpu()[6].item())
     anchor_views = sum(int(pipe.vt.info[i].anchor_count) for i in range(pipe.vt.n))
     n_anchors = int(pipe.anchors.A) if getattr(pipe, "anchors", None) is not None else 0
     G, npix = int(pipe.vt.n_gauss), int(pipe.vt.n_pix)
-    hbm, alu, mfma = PEAK_HBM_GBS * 1e9, PEAK_FP32_TFLOPS * 1e12, PEAK_MFMA_FP32_TFLOPS * 1e12
-    ideal = {  # seconds, bound
-        "decode_project": max((anchor_views * DECODE_FLOP / mfma, "mfma"),
-                              ((n_anchors * DECODE_READ_B + G * DECODE_WRITE_B) / hbm, "hbm")),
-        "bin_sort": (pairs * (SORT_PAIR_B + passes * SORT_PASS_B) / hbm, "hbm"),
-        "render_fwd": (evals_fwd * FLOP_FWD / alu, "alu"),
-        "loss": (npix * LOSS_PIXEL_B / hbm, "hbm"),
-        "composite_bwd": (evals_bwd * FLOP_BWD / alu, "alu"),
-        "project_bwd": (G * PROJ_BWD_B / hbm, "hbm"),
-        "decode_bwd": max((anchor_views * DECODE_BWD_FLOP / mfma, "mfma"),
-                          ((n_anchors * DECODE_READ_B + G * DECODE_BWD_READ_B) / hbm, "hbm")),
+    work = {
+        "decode_project": {"mfma_flop": anchor_views * DECODE_FLOP,
+                           "hbm_bytes": n_anchors * DECODE_READ_B + G * DECODE_WRITE_B},
+        "bin_sort": {"hbm_bytes": pairs * (SORT_PAIR_B + passes * SORT_PASS_B)},
+        "render_fwd": {"lane_ops": evals_fwd * SLOTS_FWD, "flop": evals_fwd * FLOP_FWD},
+        "loss": {"hbm_bytes": npix * LOSS_PIXEL_B},
+        "composite_bwd": {"lane_ops": evals_bwd * SLOTS_BWD, "flop": evals_bwd * FLOP_BWD},
+        "project_bwd": {"hbm_bytes": G * PROJ_BWD_B},
+        "decode_bwd": {"mfma_flop": anchor_views * DECODE_BWD_FLOP,
+                       "hbm_bytes": n_anchors * DECODE_READ_B + G * DECODE_BWD_READ_B},
     }
+    units = {"anchor_views": anchor_views, "anchors": n_anchors, "view_gaussians": G, "pairs": int(pairs),
+             "radix_passes": passes, "pixels": npix, "evaluations_fwd": evals_fwd, "evaluations_bwd": evals_bwd}
+    return work, units
+
+
+def peaks(ceil=None):
+    """Ceilings in units per second: the published ones, or those measured on this GPU."""
+    if ceil is None:
+        return {"hbm": PEAK_HBM_GBS * 1e9, "alu": PEAK_LANE_OPS * 1e12, "mfma": PEAK_MFMA_FP32_TFLOPS * 1e12}
+    return {"hbm": ceil["hbm_copy_TBs"] * 1e12, "alu": ceil["fma_TFLOPs"] / 2 * 1e12,
+            "mfma": ceil["mfma_fp32_TFLOPs"] * 1e12}
+
+
+def ideal_times(work, pk):
+    """Each stage's ideal time (s) and bound: the largest of its compute and HBM times."""
+    out = {}
+    for k, w in work.items():
+        cands = []
+        if "mfma_flop" in w:
+            cands.append((w["mfma_flop"] / pk["mfma"], "mfma"))
+        if "hbm_bytes" in w:
+            cands.append((w["hbm_bytes"] / pk["hbm"], "hbm"))
+        if "lane_ops" in w:
+            cands.append((w["lane_ops"] / pk["alu"], "alu"))
+        out[k] = max(cands)
+    return out
+
+
+def whole_step_roofline(pipe, ms, pairs, evals_fwd, evals_bwd, st=None, ceil=None):
+    """Sum over the stages of the step of each stage's ideal time (the larger of its
+    compute and HBM times at the peaks, for its algorithmic work counted from the
+    pipeline's own sizes), against the measured step; per stage too when `st` holds the
+    stages' measured times.  ceil: measured ceilings in place of the published ones."""
+    work, units = stage_work(pipe, pairs, evals_fwd, evals_bwd)
+    ideal = ideal_times(work, peaks(ceil))
     t_ideal = sum(t for t, _ in ideal.values())
     out = {"frac": round(t_ideal * 1e3 / ms, 4), "ideal_ms": round(t_ideal * 1e3, 4), "measured_ms": round(ms, 4)}
     if st is not None:
@@ -183,23 +236,207 @@ def whole_step_roofline(pipe, ms, pairs, evals_fwd, evals_bwd, st=None):
                          for k, (t, b) in ideal.items()}
     else:
         out["stages_ideal_ms"] = {k: round(t * 1e3, 4) for k, (t, _) in ideal.items()}
-    out["units"] = {"anchor_views": anchor_views, "anchors": n_anchors, "view_gaussians": G, "pairs": int(pairs),
-                    "radix_passes": passes, "pixels": npix, "evaluations_fwd": evals_fwd,
-                    "evaluations_bwd": evals_bwd}
+    out["units"] = units
     return out
 
 
-def cpu_baseline(scene, views):
+def measure_ceilings():
+    """The chip's ceilings measured by the microbenchmarks of libglam_ceilings.so (run
+    outside any timed region)."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2607_21416_amd", "libglam_ceilings.so"))
+    for f in ("glamc_fma_tflops", "glamc_exp_trate", "glamc_lds_read_tbs", "glamc_hbm_copy_tbs",
+              "glamc_hbm_triad_tbs", "glamc_mfma_fp32_tflops", "glamc_atomic_grate"):
+        getattr(lib, f).restype = C.c_double
+    lib.glamc_hbm_copy_tbs.argtypes = [C.c_longlong]
+    lib.glamc_hbm_triad_tbs.argtypes = [C.c_longlong]
+    lib.glamc_atomic_grate.argtypes = [C.c_int]
+    gib = 1 << 30
+    out = {"fma_TFLOPs": lib.glamc_fma_tflops(), "exp_Tper_s": lib.glamc_exp_trate(),
+           "lds_read_TBs": lib.glamc_lds_read_tbs(), "hbm_copy_TBs": lib.glamc_hbm_copy_tbs(gib),
+           "hbm_triad_TBs": lib.glamc_hbm_triad_tbs(gib), "mfma_fp32_TFLOPs": lib.glamc_mfma_fp32_tflops(),
+           "atomic_distinct_Gper_s": lib.glamc_atomic_grate(0), "atomic_one_word_Gper_s": lib.glamc_atomic_grate(1)}
+    out = {k: round(v, 3) for k, v in out.items()}
+    out["published"] = {"fma_TFLOPs": PEAK_FP32_TFLOPS, "exp_Tper_s": round(PEAK_LANE_OPS / 4, 3),
+                        "hbm_TBs": PEAK_HBM_GBS / 1e3, "mfma_fp32_TFLOPs": PEAK_MFMA_FP32_TFLOPS,
+                        "lds_read_TBs": round(256 * 128 * 2.4e9 / 1e12, 2)}
+    return out
+
+
+def kernel_rooflines(pipe, st, pairs, evals_fwd, evals_bwd, ceil):
+    """Every stage's fraction of its roofline from its algorithmic work and its measured
+    average duration, against the published peaks and against the measured ceilings."""
+    work, _ = stage_work(pipe, pairs, evals_fwd, evals_bwd)
+    pub, mea = ideal_times(work, peaks()), ideal_times(work, peaks(ceil))
+    out = {}
+    for k in work:
+        t = st[k] * 1e-3
+        b = pub[k][1]
+        rate = {"hbm": work[k].get("hbm_bytes", 0) / t / 1e9, "alu": work[k].get("lane_ops", 0) / t / 1e12,
+                "mfma": work[k].get("mfma_flop", 0) / t / 1e12}[b]
+        out[k] = {"bound": b, "achieved": round(rate, 3),
+                  "unit": {"hbm": "GB/s", "alu": "Tlane-op/s", "mfma": "TFLOP/s"}[b],
+                  "frac": round(pub[k][0] / t, 4), "frac_measured_ceiling": round(mea[k][0] / t, 4),
+                  "ms": round(st[k], 4)}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    """Threads of the oracle: the host CPUs this process may use, at most 16 (one GPU's
+    share of a GPU node's cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def time_oracle(scene, views, threads, min_s=0.0):
+    """Seconds per view iteration of the FP64 oracle (forward + loss + backward), over
+    `views`, repeated until min_s has passed."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
     oracle.set_num_threads(threads)
     t0 = time.perf_counter()
-    fwd = oracle.forward(scene, views=views)
-    oracle.backward(scene, fwd)
-    dt = time.perf_counter() - t0
-    return dict(value=len(views) / dt, unit="iterations/s", cores=threads, kind="oracle",
-                sample=f"config-3 views {list(views)}: one FP64 forward + loss + backward pass each "
-                       f"({len(views)} view iterations, {dt:.1f} s)")
+    n = 0
+    while True:
+        fwd = oracle.forward(scene, views=views)
+        oracle.backward(scene, fwd)
+        n += len(views)
+        if time.perf_counter() - t0 >= min_s:
+            break
+    return (time.perf_counter() - t0) / n, n
+
+
+def cpu_baseline(scene, view, threads):
+    """The oracle on the headline workload (one view of config 3) on this host."""
+    per, n = time_oracle(scene, [view], threads, min_s=10.0)
+    return dict(value=1.0 / per, unit="iterations/s", cores=threads, kind="oracle",
+                sample=f"config-3 view {view}: one FP64 forward + loss + backward pass per iteration, "
+                       f"{n} iterations in {n * per:.1f} s on {threads} threads ({cpu_model()}, "
+                       f"os.cpu_count() {os.cpu_count()})")
+
+
+def cpu_baselines(threads, evals4_per_view=None):
+    """The oracle at the smaller configurations on 1 thread and on `threads`, and a
+    sample of config 4 extrapolated by Gaussian-pixel evaluations."""
+    import synth
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads": threads}
+    for name in ("C1", "C2"):
+        sc = synth.config(name)
+        one, _ = time_oracle(sc, [0], 1, min_s=0.5)
+        allc, _ = time_oracle(sc, [0], threads, min_s=0.5)
+        out[name] = {"iterations_per_s_1_thread": round(1.0 / one, 4),
+                     f"iterations_per_s_{threads}_threads": round(1.0 / allc, 4)}
+    if evals4_per_view is not None:
+        s4 = synth.config("C4")
+        sample = list(range(0, len(s4["cams"]), len(s4["cams"]) // 8))[:8]
+        per, n = time_oracle(s4, sample, threads)
+        ev_sample = sum(evals4_per_view[v] for v in sample)
+        ev_all = sum(evals4_per_view)
+        step_s = per * len(sample) * ev_all / max(ev_sample, 1)
+        out["C4_extrapolated"] = {"views_timed": sample, "seconds_per_timed_view": round(per, 3),
+                                  "step_s_extrapolated": round(step_s, 2),
+                                  "view_iterations_per_s_extrapolated": round(len(evals4_per_view) / step_s, 4),
+                                  "note": "extrapolated linearly by the step's Gaussian-pixel evaluations"}
+    return out
+
+
+def run_workload(torch, scene, choice, args, dev, label):
+    """Builds the pipeline of one workload at the tuner's choice, times args.steps graph
+    replays of its step (the timed region: HIP events on the stream, synchronised on
+    both sides), then, outside that region, the spread of single replays, each stage's
+    average duration and the Gaussian-pixel evaluations (over 16x16 tile ranges, the
+    workload's definition of the work, whatever tile edge the tuner chose)."""
+    import numpy as np
+    from paper_2607_21416_amd import tuning
+    from paper_2607_21416_amd.pipeline import Pipeline
+
+    pipe = Pipeline(scene, device=dev, tile=choice["tile"], tuning=tuning.schedule(choice))
+    need = pipe.fit_capacity()
+    pipe.status.zero_()
+    log(f"bench: {label}: {pipe.vt.n} view(s), {pipe.vt.n_gauss} view-Gaussians, {need} pairs, capacity "
+        f"{pipe.capacity}")
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    step, graph = make_step(torch, pipe, not args.no_graph)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: {label}: timing {args.steps} steps ({'graph' if graph else 'eager'})")
+    t0 = time.perf_counter()
+    ms = timed(torch, step, args.steps, stream)
+    wall = time.perf_counter() - t0
+    pipe.check_status()
+    log(f"bench: {label}: {ms:.3f} ms/step, {1000.0 / ms:.1f} steps/s (wall {wall:.2f} s)")
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for a, b in rev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    rt = np.array([a.elapsed_time(b) for a, b in rev])
+    replay = {"n": len(rt), "median_ms": round(float(np.median(rt)), 4),
+              "p10_ms": round(float(np.percentile(rt, 10)), 4), "p90_ms": round(float(np.percentile(rt, 90)), 4)}
+    pipe.check_status()
+    st = stage_times(torch, pipe, args.stage_iters)
+    pipe.check_status()
+    ref = pipe if pipe.vt.tile == 16 else Pipeline(scene, device=dev)
+    if ref is not pipe:
+        ref.fit_capacity()
+        ref.status.zero_()
+        ref.forward()
+    ref.count_evaluations()
+    ref.render()
+    torch.cuda.synchronize()
+    evals_fwd = int(ref.n_eval.to(torch.int64).sum().item())
+    evals_bwd = int(ref.n_contrib.to(torch.int64).sum().item())
+    per_view = [int(t.to(torch.int64).sum().item()) for t in ref.per_pixel(ref.n_eval)]
+    ref.count_evaluations(False)
+    ref.check_status()
+    del ref
+    log(f"bench: {label}: stages " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    return dict(pipe=pipe, ms=ms, wall=wall, replay=replay, st=st, need=need, evals_fwd=evals_fwd,
+                evals_bwd=evals_bwd, evals_per_view=per_view, graph=graph, step=step)
+
+
+def dominant_roofline(w, choice, ceil):
+    """The roofline object of the workload's dominant kernel (the slower compositing
+    kernel), in the scope table's work units, with the FLOP convention and the measured
+    ceiling beside it."""
+    from paper_2607_21416_amd import tuning
+    st = w["st"]
+    dom = max(("render_fwd", "composite_bwd"), key=lambda k: st[k])
+    evals = w["evals_fwd"] if dom == "render_fwd" else w["evals_bwd"]
+    slots = SLOTS_FWD if dom == "render_fwd" else SLOTS_BWD
+    flop = FLOP_FWD if dom == "render_fwd" else FLOP_BWD
+    t = st[dom] * 1e-3
+    achieved = evals * slots / t / 1e12
+    achieved_flop = evals * flop / t / 1e12
+    measured_peak = ceil["fma_TFLOPs"] / 2 if ceil else None
+    return {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_LANE_OPS, 2),
+            "unit": "Tlane-op/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
+            "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)}),
+            "work": f"{evals} Gaussian-pixel evaluations x {slots} FP32 VALU lane-op slots per launch "
+                    f"(exp and reciprocal at a quarter of the VALU rate); peak = 256 CU x 4 SIMD x 16 lanes "
+                    f"x 2.4 GHz",
+            "avg_ms": round(st[dom], 4),
+            "measured_peak": round(measured_peak, 3) if measured_peak else None,
+            "frac_measured_peak": round(achieved / measured_peak, 4) if measured_peak else None,
+            "flop_convention": {"achieved": round(achieved_flop, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(achieved_flop / PEAK_FP32_TFLOPS, 4),
+                                "work": f"{evals} evaluations x {flop} FLOP (FMA = 2, exp2 = 1)"}}
 
 
 def main():
@@ -208,8 +445,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of a HIP graph replay")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched-vs-plain comparison")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline workload alone (no ceilings, four-view step, next rows, config 4, CPU)")
     ap.add_argument("--stage-iters", type=int, default=10)
     ap.add_argument("--config5", action="store_true",
                     help="also run config 5 (2 km path, 64 partitions x 8 views, mixed resolutions) once")
@@ -235,81 +474,90 @@ def main():
     binding.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ceil = None
+    if not args.headline_only:
+        log("bench: ceilings of this GPU (microbenchmarks, outside any timed region)")
+        ceil = measure_ceilings()
+        log("bench: ceilings " + ", ".join(f"{k} {v}" for k, v in ceil.items() if k != "published"))
+
+    def choose(sc):
+        if args.no_tune:
+            return dict(tuning.DEFAULT, source="built-in default")
+        return tuning.autotune(sc, device=dev, log=log, use_cache=not args.retune)
+
     log("bench: generating config 3 (50k anchors, 4 views 1226x370)")
     scene = synth.config("C3")
-    if args.no_tune:
-        choice = dict(tuning.DEFAULT, source="built-in default")
-    else:
-        log("bench: tuner choice of tile edge and compositing schedule (any measuring is outside the timed region)")
-        choice = tuning.autotune(scene, device=dev, log=log, use_cache=not args.retune)
-    log("bench: tile %d, long tiles >= 2^%d, grids %d/%d workgroups per CU" % (
-        choice["tile"], choice["long_log2"], choice["fwd_blocks_per_cu"], choice["bwd_blocks_per_cu"]))
-    pipe = Pipeline(scene, device=dev, tile=choice["tile"], tuning=tuning.schedule(choice))
-    need = pipe.fit_capacity()
-    pipe.status.zero_()
-    log(f"bench: {pipe.vt.n_gauss} view-Gaussians, {need} pairs, capacity {pipe.capacity}")
-    for _ in range(args.warmup):
-        pipe.step()
-    torch.cuda.synchronize()
-    step, graph = make_step(torch, pipe, not args.no_graph)
-    stream = torch.cuda.current_stream()
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps ({'graph' if graph else 'eager'})")
-    t0 = time.perf_counter()
-    ms = timed(torch, step, args.steps, stream)
-    wall = time.perf_counter() - t0
-    pipe.check_status()
+    scene1 = one_view(scene, 0)
+    choice1 = choose(scene1)
+    log("bench: headline (one view): tile %d, long tiles >= 2^%d, grids %d/%d workgroups per CU (%s)" % (
+        choice1["tile"], choice1["long_log2"], choice1["fwd_blocks_per_cu"], choice1["bwd_blocks_per_cu"],
+        choice1["source"]))
+    w1 = run_workload(torch, scene1, choice1, args, dev, "config 3, view 0")
+    ms = w1["ms"]
+    value = 1000.0 / ms
+    roofline = dominant_roofline(w1, choice1, ceil)
+    step_roofline = whole_step_roofline(w1["pipe"], ms, w1["need"], w1["evals_fwd"], w1["evals_bwd"], w1["st"])
+    log(f"bench: M1 {value:.1f} iterations/s; dominant kernel {roofline['kernel']} at {roofline['frac']:.3f} of "
+        f"its roofline; whole step {step_roofline['frac']:.3f}")
+    out = {
+        "metric": "mapping iters/s fwd+bwd (500k Gaussians, 1226x370); batched vs plain speedup",
+        "value": round(value, 2), "unit": "iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config 3 scale: 50k anchors x 10 offsets = 500k Gaussians, street corridor, "
+                               "1226x370; one mapping iteration = one keyframe view (view 0) decoded, projected, "
+                               "binned, composited, L1 + 0.2 (1 - SSIM), backward to anchors and MLPs",
+                   "views_per_step": 1, "view_gaussians": int(w1["pipe"].vt.n_gauss), "pairs": int(w1["need"]),
+                   "launch": "hip graph" if w1["graph"] else "eager",
+                   "tile": choice1["tile"], "schedule": tuning.schedule(choice1), "tuning": choice1["source"]},
+        "stages_ms": {k: round(v, 4) for k, v in w1["st"].items()},
+        "evaluations_per_s": {"fwd": round(w1["evals_fwd"] / (w1["st"]["render_fwd"] * 1e-3), 1),
+                              "bwd": round(w1["evals_bwd"] / (w1["st"]["composite_bwd"] * 1e-3), 1)},
+        "roofline": roofline,
+        "step_roofline": step_roofline,
+        "replays": w1["replay"],
+    }
+    if ceil is not None:
+        out["ceilings"] = ceil
+        out["kernel_rooflines"] = kernel_rooflines(w1["pipe"], w1["st"], w1["need"], w1["evals_fwd"],
+                                                   w1["evals_bwd"], ceil)
+        out["step_roofline"]["frac_measured_ceilings"] = whole_step_roofline(
+            w1["pipe"], ms, w1["need"], w1["evals_fwd"], w1["evals_bwd"], ceil=ceil)["frac"]
+    if "ms" in choice1:
+        out["autotune_ms"] = choice1["ms"]
+    del w1["graph"], w1["step"]
+    if args.headline_only:
+        if args.copy_mib > 0:
+            src = torch.ones(args.copy_mib * 262144, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps(out), flush=True)
+        return
+    del w1
+
+    # M1': config 3's four views in one batched step
+    choice = choose(scene)
+    w4 = run_workload(torch, scene, choice, args, dev, "config 3, four views")
+    pipe = w4["pipe"]
     n_views = pipe.vt.n
-    value = n_views * 1000.0 / ms
-    log(f"bench: {ms:.3f} ms/step, {value:.1f} iterations/s (wall {wall:.2f} s)")
-    # the spread of single replays (after the timed region)
-    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
-    for a, b in rev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    rt = np.array([a.elapsed_time(b) for a, b in rev])
-    replay = {"n": len(rt), "median_ms": round(float(np.median(rt)), 4),
-              "p10_ms": round(float(np.percentile(rt, 10)), 4), "p90_ms": round(float(np.percentile(rt, 90)), 4)}
-    pipe.check_status()
-    log("bench: single replays median %.3f ms, p10 %.3f, p90 %.3f" % (replay["median_ms"], replay["p10_ms"],
-                                                                    replay["p90_ms"]))
-
-    # per-stage times and evaluation counts (eager, outside the timed region)
-    st = stage_times(torch, pipe, args.stage_iters)
-    pipe.check_status()
-    # evaluations are counted over 16x16 tile ranges (the workload's definition of the
-    # work, independent of the tile edge the tuner chose for the timed kernels)
-    ref = pipe if pipe.vt.tile == 16 else Pipeline(scene, device=dev)
-    if ref is not pipe:
-        ref.fit_capacity()
-        ref.status.zero_()
-        ref.forward()
-    ref.count_evaluations()
-    ref.render()
-    torch.cuda.synchronize()
-    evals_fwd = int(ref.n_eval.to(torch.int64).sum().item())
-    evals_bwd = int(ref.n_contrib.to(torch.int64).sum().item())
-    ref.count_evaluations(False)
-    ref.check_status()
-    del ref
-    log("bench: stages " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
-    dom = max(("render_fwd", "composite_bwd"), key=lambda k: st[k])
-    flops = evals_fwd * FLOP_FWD if dom == "render_fwd" else evals_bwd * FLOP_BWD
-    achieved = flops / (st[dom] * 1e-3) / 1e12
-    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)}),
-                "work": f"{evals_fwd if dom == 'render_fwd' else evals_bwd} evaluations x "
-                        f"{FLOP_FWD if dom == 'render_fwd' else FLOP_BWD} FLOP per launch"}
-
-    # whole-step roofline: every stage's ideal time at its own bound, summed, over the
-    # measured step (the optimiser excluded, as in the headline rate)
-    step_roofline = whole_step_roofline(pipe, ms, need, evals_fwd, evals_bwd, st)
-    t_ideal = step_roofline["ideal_ms"] * 1e-3
-    log(f"bench: whole-step roofline {t_ideal * 1e3:.3f} ms ideal / {ms:.3f} ms = {t_ideal * 1e3 / ms:.3f}")
+    out["m1_prime"] = {"workload": "config 3: the four keyframe views in one batched step", "views": n_views,
+                       "ms_per_step": round(w4["ms"], 4), "steps_per_s": round(1000.0 / w4["ms"], 2),
+                       "view_iterations_per_s": round(n_views * 1000.0 / w4["ms"], 2),
+                       "tile": choice["tile"], "schedule": tuning.schedule(choice), "tuning": choice["source"],
+                       "stages_ms": {k: round(v, 4) for k, v in w4["st"].items()},
+                       "roofline": dominant_roofline(w4, choice, ceil),
+                       "kernel_rooflines": kernel_rooflines(pipe, w4["st"], w4["need"], w4["evals_fwd"],
+                                                            w4["evals_bwd"], ceil),
+                       "step_roofline": whole_step_roofline(pipe, w4["ms"], w4["need"], w4["evals_fwd"],
+                                                            w4["evals_bwd"], w4["st"]),
+                       "replays": w4["replay"]}
+    if "ms" in choice:
+        out["m1_prime"]["autotune_ms"] = choice["ms"]
+    del w4["graph"], w4["step"]
+    stream = torch.cuda.current_stream()
 
     # the optimiser step that closes the mapping iteration (Adam over the anchors'
     # features, offsets, log-scales and the MLP sets); the headline rate excludes it.
@@ -345,8 +593,8 @@ def main():
     del og
     restore()
     n_opt = sum(int(pipe.opt_m[k].numel()) for k in pipe.opt_m)
-    st["adam"] = t_adam
-    log(f"bench: with the optimiser step {t_opt:.3f} ms/step ({n_views * 1000.0 / t_opt:.1f} iterations/s), "
+    out["m1_prime"]["stages_ms"]["adam"] = round(t_adam, 4)
+    log(f"bench: with the optimiser step {t_opt:.3f} ms/step ({n_views * 1000.0 / t_opt:.1f} view iterations/s), "
         f"Adam {t_adam:.3f} ms over {n_opt} parameters")
 
     # loop-closure deformation of config 3's anchors by 40 corrected keyframes (on
@@ -448,31 +696,7 @@ def main():
     log(f"bench: growth bookkeeping {t_ins * 1e3:.1f} us ({len(lay)} arrays, {A3} + {n_new} anchors, "
         f"{ins_bytes / (t_ins * 1e-3) / 1e12:.2f} TB/s)")
 
-    if args.copy_mib > 0:
-        src = torch.ones(args.copy_mib * 262144, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    out = {
-        "metric": "mapping iters/s fwd+bwd (500k Gaussians, 1226x370); batched vs plain speedup",
-        "value": round(value, 2), "unit": "iterations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "config 3: 50k anchors x 10 offsets = 500k Gaussians, street corridor, "
-                               "4 keyframe views 1226x370, L1 + 0.2 (1 - SSIM), fwd + bwd to anchors and MLPs",
-                   "views_per_step": n_views, "view_gaussians": int(pipe.vt.n_gauss), "pairs": int(need),
-                   "launch": "hip graph" if graph else "eager",
-                   "tile": choice["tile"], "schedule": tuning.schedule(choice),
-                   "tuning": choice["source"]},
-        "stages_ms": {k: round(v, 4) for k, v in st.items()},
-        "evaluations_per_s": {"fwd": round(evals_fwd / (st["render_fwd"] * 1e-3), 1),
-                              "bwd": round(evals_bwd / (st["composite_bwd"] * 1e-3), 1)},
-        "roofline": roofline,
-        "step_roofline": step_roofline,
-        "replays": replay,
+    out.update({
         "flow_densification": {"workload": f"{npx} correspondences between two 1226x370 keyframes 1 m apart "
                                            "(0.5 px noise, 20% outliers)",
                                "us": round(t_epi * 1e3, 2), "kept": kept,
@@ -485,20 +709,20 @@ def main():
                           "bookkeeping_hbm_TBs": round(ins_bytes / (t_ins * 1e-3) / 1e12, 2)},
         "loop_closure": {"workload": f"{A3} anchors (K = {K3} offsets), {len(fixes)} corrected keyframes",
                          "us": round(t_def * 1e3, 2), "anchors_in_a_frustum": moved},
-        "with_optimizer": {"ms_per_step": round(t_opt, 4), "iterations_per_s": round(n_views * 1000.0 / t_opt, 2),
+        "with_optimizer": {"workload": "config 3's four-view step followed by the Adam update",
+                           "ms_per_step": round(t_opt, 4), "view_iterations_per_s": round(n_views * 1000.0 / t_opt, 2),
                            "adam_ms": round(t_adam, 4), "parameters": n_opt,
                            "adam_hbm_GBs": round(28.0 * n_opt / (t_adam * 1e-3) / 1e9, 1)},
-    }
-    if "ms" in choice:
-        out["autotune_ms"] = choice["ms"]
-    del graph
+    })
+    del pipe, w4
 
+    evals4 = None
     if not args.no_batched:
         log("bench: config 4 (16 partitions x 4 views), batched vs plain")
         s4 = synth.config("C4")
-        c4 = dict(tuning.DEFAULT) if args.no_tune else tuning.autotune(s4, device=dev, log=log,
-                                                                        use_cache=not args.retune)
-        bp = Pipeline(s4, device=dev, tile=c4["tile"], tuning=tuning.schedule(c4))
+        c4 = choose(s4)
+        sched4 = tuning.schedule(c4)
+        bp = Pipeline(s4, device=dev, tile=c4["tile"], tuning=sched4)
         bp.fit_capacity()
         bp.status.zero_()
         for _ in range(2):
@@ -506,9 +730,16 @@ def main():
         bstep, bg = make_step(torch, bp, True)
         tb = timed(torch, bstep, max(3, args.steps // 4), stream)
         bp.check_status()
+        bp.count_evaluations()
+        bp.render()
+        torch.cuda.synchronize()
+        evals4 = [int(t.to(torch.int64).sum().item()) for t in bp.per_pixel(bp.n_eval)]
+        bp.count_evaluations(False)
+        # the plain form: each view its own launch sequence (one view's anchors and MLP
+        # set, its own bins), at the batched tile edge and schedule
         plains = []
         for sub in split_views(s4):
-            p = Pipeline(sub, device=dev)
+            p = Pipeline(sub, device=dev, tile=c4["tile"], tuning=sched4)
             p.fit_capacity()
             p.status.zero_()
             plains.append(p)
@@ -519,18 +750,28 @@ def main():
 
         plain_all()
         tp = timed(torch, plain_all, max(2, args.steps // 8), stream)
+        # the same 64 launch sequences replayed from one graph: no host launch cost, so
+        # the difference to the batched step is the batching itself
+        pstep, pg = make_graph(torch, plain_all, True)
+        tpg = timed(torch, pstep, max(2, args.steps // 8), stream)
         for p in plains:
             p.check_status()
         out["batched_vs_plain"] = {"workload": "config 4: 16 partitions (log-uniform 20k-400k Gaussians) x 4 views "
                                                "1226x370, own MLPs",
                                    "views": bp.vt.n, "view_gaussians": int(bp.vt.n_gauss),
-                                   "batched_tile": c4["tile"], "batched_schedule": tuning.schedule(c4),
+                                   "tile": c4["tile"], "schedule": sched4, "tuning": c4["source"],
                                    "batched_ms": round(tb, 3), "plain_ms": round(tp, 3),
-                                   "speedup": round(tp / tb, 3),
-                                   "batched_iterations_per_s": round(bp.vt.n * 1000.0 / tb, 1),
-                                   "plain_iterations_per_s": round(bp.vt.n * 1000.0 / tp, 1)}
-        log(f"bench: batched {tb:.2f} ms, plain {tp:.2f} ms, speedup {tp / tb:.2f}")
-        del bg, bp, plains
+                                   "plain_graph_ms": round(tpg, 3),
+                                   "speedup": round(tp / tb, 3), "speedup_vs_plain_graph": round(tpg / tb, 3),
+                                   "batched_view_iterations_per_s": round(bp.vt.n * 1000.0 / tb, 1),
+                                   "plain_view_iterations_per_s": round(bp.vt.n * 1000.0 / tp, 1),
+                                   "plain_graph_view_iterations_per_s": round(bp.vt.n * 1000.0 / tpg, 1),
+                                   "note": "speedup: 64 per-view launch sequences launched eagerly from the host, "
+                                           "against one batched graph replay; speedup_vs_plain_graph: the same 64 "
+                                           "sequences replayed from one graph"}
+        log(f"bench: batched {tb:.2f} ms, plain {tp:.2f} ms eager / {tpg:.2f} ms graph, speedup {tp / tb:.2f} / "
+            f"{tpg / tb:.2f}")
+        del bg, pg, bp, plains
 
     if args.config5:
         log("bench: config 5 (2 km path, 64 partitions x 8 views)")
@@ -566,9 +807,20 @@ def main():
             f"{out['config5']['step_roofline']['frac']:.3f}")
         del p5, s5
 
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * 262144, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if not args.no_cpu:
-        log("bench: CPU oracle baseline (the 4 views of config 3, three times over)")
-        out["cpu_baseline"] = cpu_baseline(scene, list(range(n_views)) * 3)
+        threads = oracle_threads()
+        log(f"bench: CPU oracle baseline (config 3 view 0, {threads} threads)")
+        out["cpu_baseline"] = cpu_baseline(scene, 0, threads)
+        log("bench: CPU oracle at configs 1 and 2 (1 thread and all), config 4 sampled")
+        out["cpu_baselines"] = cpu_baselines(threads, evals4)
     print(json.dumps(out), flush=True)
 
 

@@ -93,7 +93,9 @@ enum {
      (tile, Gaussian) pair and 8x8 quadrant stores its partial sums in a workspace, and
      a segmented reduction adds each Gaussian's partials in a fixed order (its tiles
      row-major, then quadrants).  Results are bit-identical from run to run and across
-     schedules with the same tile edge.  Needs glam_bins.pair_begin from the
+     persistent grid sizes (glam_tuning's blocks per CU); the tile edge and the long-tile
+     threshold choose the arithmetic path of each tile, so they must stay the same.
+     Needs glam_bins.pair_begin from the
      glam_bin_sort call and glam_render_bwd_workspace_bytes with this flag. */
   GLAM_DETERMINISTIC_GRADS = 1u << 3,
   /* Backward only: also write the 2-D gradients d(u, v, A, B, C, opacity, r, g, b) of

@@ -18,6 +18,20 @@ FLAGS = [
 ]
 
 
+CEIL_LIB = os.path.join(HERE, "libglam_ceilings.so")
+
+
+def build_ceilings(verbose: bool = False) -> str:
+    """The ceiling microbenchmarks (include/glam_ceilings.h) as their own library."""
+    tmp = CEIL_LIB + ".tmp"
+    cmd = ["hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "ceilings.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, CEIL_LIB)
+    return CEIL_LIB
+
+
 def build(verbose: bool = False, jobs: int = 6) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -41,6 +55,7 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_ceilings(verbose)
     return LIB
 
 
