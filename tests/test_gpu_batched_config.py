@@ -15,7 +15,8 @@ import torch
 
 import oracle
 import synth
-from gpu_util import AMB_STAGE, gpu_splats, grad_close, host, view_image, view_pixels, view_slices
+from gpu_util import (AMB_STAGE, check_anchor_grads, check_dgauss, check_pixels, gpu_splats, grad_close, host,
+                      stage_render, view_image, view_pixels, view_slices)
 from paper_2607_21416_amd import tuning
 from paper_2607_21416_amd.pipeline import Pipeline
 from test_gpu_parity import g2d_gradients
@@ -95,12 +96,9 @@ def test_sampled_views_forward_and_backward(batched_case):
     for v in SAMPLE:
         sl = sls[v]
         pr, gs, vals, ranges = _view_inputs(h, sl)
-        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v], tile=(tile, tile))
-        ok = (ref["amb"] & AMB_STAGE) == 0
-        assert ok.mean() > 0.95
-        assert np.abs(view_image(h, sl) - ref["image"])[:, ok].max() <= 1e-4, f"view {v}"
-        assert np.abs(view_pixels(h, sl, "T_final") - ref["T_final"])[ok].max() <= 1e-4, f"view {v}"
-        assert np.array_equal(view_pixels(h, sl, "n_contrib")[ok], ref["n_contrib"][ok]), f"view {v}"
+        ref = stage_render(pr, gs, vals, ranges, scene["cams"][v], tile=(tile, tile))
+        check_pixels(view_image(h, sl), view_pixels(h, sl, "T_final"), view_pixels(h, sl, "n_contrib"), ref,
+                     f"config 4 view {v}")
         _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
         d[:, (ref["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0] = 0.0
         dims[v] = d
@@ -109,6 +107,7 @@ def test_sampled_views_forward_and_backward(batched_case):
     torch.cuda.synchronize()
     hb = host(pipe)
     acc = oracle.zero_grads(scene)
+    dgs, scales = {}, {}
     for v in SAMPLE:
         sl = sls[v]
         pr, gs, vals, ranges = _view_inputs(h, sl)
@@ -118,14 +117,13 @@ def test_sampled_views_forward_and_backward(batched_case):
             grad_close(got[k], g2d[k], name=f"config 4 view {v} d{nm}")
         gin = {k: hb["dec"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dec"]}
         dgp = oracle.project_bwd(gin, scene["cams"][v], h["ntiles"][sl["g0"]:sl["g1"]], got.astype(np.float64))
-        for k in ("mean", "scale", "quat", "opacity", "rgb"):
-            grad_close(hb["dg"][k][..., sl["g0"]:sl["g1"]], dgp[k], name=f"config 4 view {v} dgauss {k}")
         dgv = {k: hb["dg"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dg"]}
+        check_dgauss(dgv, dgp, gin, scene["cams"][v], h["ntiles"][sl["g0"]:sl["g1"]], got, f"config 4 view {v}")
         oracle.decode_bwd(scene, scene["cams"][v]["partition"], scene["cams"][v], dgv, acc)
+        dgs[v], scales[v] = dgv, gin["scale"]
     # views outside the sample got dL/dC = 0: their 2-D gradients vanish exactly
     others = np.ones(hb["g2d"].shape[0], bool)
     for v in SAMPLE:
         others[sls[v]["g0"]:sls[v]["g1"]] = False
     assert not hb["g2d"][others].any()
-    for k in acc:
-        grad_close(hb["pgrad"][k], acc[k], name=f"config 4 anchor d{k}")
+    check_anchor_grads(hb["pgrad"], acc, scene, dgs, scales, "config 4 anchor")

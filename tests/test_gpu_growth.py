@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import AMB_VALUE, grad_close, host, run, view_image, view_slices
+from gpu_util import check_e2e_pixels, grad_close, host, run, view_image, view_slices
 from oracle import voxel as V
 from paper_2607_21416_amd import binding as B
 from paper_2607_21416_amd.pipeline import Pipeline
@@ -96,12 +96,11 @@ def test_growth_end_to_end(part):
     for k in fresh["pgrad"]:
         grad_close(h["pgrad"][k], fresh["pgrad"][k], rel=1e-5, floor=1e-6, norm_rel=1e-5, name=f"grown d{k}")
     fwd = oracle.forward(grown)
-    for sl, r in zip(view_slices(pipe), fwd):
+    for v, (sl, r) in enumerate(zip(view_slices(pipe), fwd)):
         # a new anchor's K Gaussians all start at its centre (zero offsets): exact depth
-        # ties, whose order the oracle flags as ambiguous, cover much of the image
-        ok = (r["amb"] & AMB_VALUE) == 0
-        assert ok.mean() > 0.3
-        assert np.abs(view_image(h, sl) - r["image"])[:, ok].max() <= 1e-4
+        # ties, whose order the oracle flags as ambiguous, cover much of the image; the
+        # GPU's order is checked on them instead
+        check_e2e_pixels(view_image(h, sl), r, h, sl, grown["cams"][v], f"grown view {v}", depth_max=0.7)
     # the optimiser's groups follow the grown tensors
     before = pipe.params["feat"].clone()
     pipe.adam_step()

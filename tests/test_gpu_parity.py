@@ -3,11 +3,15 @@
 Stage-wise: each GPU stage's output is compared with the oracle's same stage fed the
 GPU's own inputs to that stage, so that FP32-vs-FP64 differences upstream cannot move
 a discrete decision: tile assignment, sort order and ranges bit-exact; pixels within
-1e-4 absolute; gradients within 1e-3 relative (plus a floor of 1e-5 of the tensor's
-largest entry for cancelling sums); decode within 1e-5 relative (plus 1e-5 of the
-field's largest entry for cancelling dot products).
-End to end: raw inputs -> pixels within 1e-4 and gradients within 1e-3, on pixels the
-oracle does not flag as ambiguous (a threshold, stop or depth order within rounding).
+1e-4 absolute off the pixels whose skip or stop decision lies within FP32 rounding of
+its threshold (at most 0.5% of a view's pixels, each within 0.02); gradients within
+1e-3 relative plus 1e-6 of the tensor's largest element; decoded values within 1e-5
+relative plus the FP32 rounding bound of the MLP sums behind them; projected centres
+and conics within the rounding bound of their own arithmetic.
+End to end: raw inputs -> pixels within 1e-4 off the flagged pixels (a threshold, stop
+or depth order within rounding), and every pixel, depth near-ties included, within 1e-4
+of the oracle composited in the GPU's order off threshold and stop ambiguities;
+gradients within 1e-3 relative plus 1e-6 of the largest.
 """
 import numpy as np
 import pytest
@@ -15,8 +19,9 @@ import torch
 
 import oracle
 import synth
-from gpu_util import (AMB_STAGE, AMB_VALUE, gpu_splats, grad_close, host, run, unpack_box, view_image, view_pixels,
-                      view_slices)
+from gpu_util import (AMB_STAGE, AMB_VALUE, DECODE_GAMMA, GAMMA_E2E, U32, check_anchor_grads, check_dgauss,
+                      check_e2e_pixels, check_pixels, decode_magnitude, e2e_grad_magnitude, gpu_splats, grad_close,
+                      host, projection_bounds, run, stage_render, unpack_box, view_image, view_pixels, view_slices)
 
 pytestmark = pytest.mark.gpu
 
@@ -113,16 +118,26 @@ def test_project(case):
         near = (np.abs(255 * gs["opacity"] - 1) < 1e-4) | (np.abs(ref["depth"] - 0.2) < 1e-5)
         assert not (diff & ~near).any()
         both = vis_g & vis_o
-        for key in ("uv", "conic"):
-            a = h[key][:, g0:g1][:, both].astype(np.float64)
-            b = ref[key][:, both]
-            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-5 * np.abs(b).max(), err_msg=key)
+        uvs, kappa = projection_bounds(gs, cam, ref)
+        # centres: a few roundings (R mu + t, the division, fx x + cx) of their scale
+        duv = np.abs(h["uv"][:, g0:g1][:, both].astype(np.float64) - ref["uv"][:, both])
+        assert (duv <= 16 * U32 * uvs[:, both]).all(), np.max(duv / (16 * U32 * uvs[:, both]))
+        # conics per element: A and C relative to themselves, B relative to sqrt(A C),
+        # within 1e-5, widened by the determinant's condition where a c ~ b^2
+        a = h["conic"][:, g0:g1][:, both].astype(np.float64)
+        b = ref["conic"][:, both]
+        scale = np.stack([np.abs(b[0]), np.sqrt(np.abs(b[0] * b[2])), np.abs(b[2])])
+        rel = np.abs(a - b) / scale
+        lim = 1e-5 + 64 * U32 * kappa[both]
+        print(f"{name} view {v}: centre error / bound {np.max(duv / (16 * U32 * uvs[:, both])):.3f}, conic error / "
+              f"bound {np.max(rel / lim):.3f} (largest relative {rel.max():.2e})", flush=True)
+        assert (rel <= lim).all(), np.max(rel / lim)
         # the extent scales with sqrt(ln(255 opacity)): its relative rounding error grows
         # like (ulp of 255 opacity) / (2 ln(255 opacity)) as the opacity nears 1/255
         a = h["ext"][:, g0:g1][:, both].astype(np.float64)
         b = ref["ext"][:, both]
         lg = np.log(255.0 * gs["opacity"][both])
-        tol = 1e-5 * np.abs(b) + 1e-5 * np.abs(b).max() + np.abs(b) * 1e-6 / np.maximum(lg, 1e-12)
+        tol = 1e-5 * np.abs(b) + np.abs(b) * 1e-6 / np.maximum(lg, 1e-12)
         assert (np.abs(a - b) <= tol).all(), np.abs(a - b).max()
         np.testing.assert_allclose(h["depth"][g0:g1][both], ref["depth"][both], rtol=1e-6)
         # tile assignment bit-exact given the GPU's single-precision centre and extents
@@ -168,17 +183,9 @@ def test_render_fwd_stagewise(case):
         pr, gs = gpu_splats(h, sl)
         vals = h["vals"].astype(np.int64) - sl["g0"]
         ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
-        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v])
-        ok = (ref["amb"] & AMB_STAGE) == 0
-        assert ok.mean() > 0.95
-        img = view_image(h, sl)
-        err = np.abs(img - ref["image"])[:, ok]
-        assert err.max() <= 1e-4, err.max()
-        assert np.abs(view_pixels(h, sl, "T_final") - ref["T_final"])[ok].max() <= 1e-4
-        assert np.array_equal(view_pixels(h, sl, "n_contrib")[ok], ref["n_contrib"][ok])
-        assert np.array_equal(view_pixels(h, sl, "n_eval")[ok], ref["n_eval"][ok])
-        # ambiguous pixels stay within the loose bound
-        assert np.abs(img - ref["image"]).max() <= 0.02 or (~ok).sum() > 0
+        ref = stage_render(pr, gs, vals, ranges, scene["cams"][v])
+        check_pixels(view_image(h, sl), view_pixels(h, sl, "T_final"), view_pixels(h, sl, "n_contrib"), ref,
+                     f"{name} view {v}", n_eval=view_pixels(h, sl, "n_eval"))
 
 
 def test_loss_kernel(case):
@@ -190,7 +197,7 @@ def test_loss_kernel(case):
         got = view_image(h, sl, "dimage")
         # L1 sign flips only where the FP32 image equals the target to rounding
         tie = np.abs(img - scene["targets"][v]) < 1e-6
-        grad_close(got[~tie], dimg[~tie], rel=1e-3, floor=1e-4, name="dL/dC")
+        grad_close(got[~tie], dimg[~tie], name="dL/dC")
 
 
 def _masked_dimage(h, scene, pipe):
@@ -200,7 +207,7 @@ def _masked_dimage(h, scene, pipe):
         pr, gs = gpu_splats(h, sl)
         vals = h["vals"].astype(np.int64) - sl["g0"]
         ranges = h["ranges"][sl["t0"]:sl["t0"] + sl["nt"]]
-        ref = oracle.render_fwd(pr, gs, vals, ranges, scene["cams"][v])
+        ref = stage_render(pr, gs, vals, ranges, scene["cams"][v])
         _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
         amb = (ref["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0
         d[:, amb] = 0.0
@@ -218,6 +225,7 @@ def test_backward_stagewise(case):
     hb = host(pipe)
     sls = view_slices(pipe)
     acc = oracle.zero_grads(scene)
+    dgs, scales = {}, {}
     for v, sl in enumerate(sls):
         pr, gs = gpu_splats(h, sl)
         vals = h["vals"].astype(np.int64) - sl["g0"]
@@ -237,17 +245,15 @@ def test_backward_stagewise(case):
             for k in acc:
                 acc[k] += d[k]
         else:
-            for k, gk in (("mean", "mean"), ("scale", "scale"), ("quat", "quat"), ("opacity", "opacity"),
-                          ("rgb", "rgb")):
-                grad_close(hb["dg"][gk][..., sl["g0"]:sl["g1"]], dgp[k], name=f"{name} view {v} dgauss {k}")
             dgv = {k: hb["dg"][k][..., sl["g0"]:sl["g1"]].astype(np.float64) for k in hb["dg"]}
+            check_dgauss(dgv, dgp, gin, scene["cams"][v], h["ntiles"][sl["g0"]:sl["g1"]], got, f"{name} view {v}")
             oracle.decode_bwd(scene, scene["cams"][v]["partition"], scene["cams"][v], dgv, acc)
+            dgs[v], scales[v] = dgv, gin["scale"]
     if scene["kind"] == "plain":
         for k in acc:
             grad_close(hb["dg"][k], acc[k], name=f"{name} plain d{k}")
     else:
-        for k in acc:
-            grad_close(hb["pgrad"][k], acc[k], name=f"{name} anchor d{k}")
+        check_anchor_grads(hb["pgrad"], acc, scene, dgs, scales, f"{name} anchor")
 
 
 def test_decode_stagewise(case):
@@ -259,10 +265,13 @@ def test_decode_stagewise(case):
         assert ref["opacity"].shape[-1] == sl["g1"] - sl["g0"]
         if sl["g1"] == sl["g0"]:
             continue
+        mag = decode_magnitude(scene, v)
         for k in ("mean", "scale", "quat", "opacity", "rgb"):
-            got = h["dec"][k][..., sl["g0"]:sl["g1"]]
-            np.testing.assert_allclose(got, ref[k], rtol=1e-5, atol=1e-5 * max(np.abs(ref[k]).max(), 1e-30),
-                                       err_msg=k)
+            got = h["dec"][k][..., sl["g0"]:sl["g1"]].astype(np.float64)
+            lim = 1e-5 * np.abs(ref[k]) + DECODE_GAMMA * U32 * mag[k]
+            err = np.abs(got - ref[k])
+            print(f"{name} view {v} decode {k}: error / bound {np.max(err / lim):.3f}", flush=True)
+            assert (err <= lim).all(), (k, np.max(err / lim))
 
 
 def test_end_to_end(case):
@@ -270,10 +279,7 @@ def test_end_to_end(case):
     fwd = oracle.forward(scene)
     dims = []
     for v, (sl, r) in enumerate(zip(view_slices(pipe), fwd)):
-        ok = (r["amb"] & AMB_VALUE) == 0
-        assert ok.mean() > 0.85
-        img = view_image(h, sl)
-        assert np.abs(img - r["image"])[:, ok].max() <= 1e-4
+        check_e2e_pixels(view_image(h, sl), r, h, sl, scene["cams"][v], f"{name} view {v}")
         assert h["loss"][v] == pytest.approx(r["loss"], rel=1e-4)
         d = r["dimage"].copy()
         d[:, (r["amb"] & (AMB_VALUE | oracle.AMB_CLAMP)) != 0] = 0.0
@@ -284,8 +290,10 @@ def test_end_to_end(case):
     torch.cuda.synchronize()
     hb = host(pipe)
     got = hb["dg"] if scene["kind"] == "plain" else hb["pgrad"]
+    mag = None if scene["kind"] == "plain" else e2e_grad_magnitude(scene, fwd, dims)
     for k in ref:
-        grad_close(got[k], ref[k], rel=1e-3, floor=1e-5, name=f"{name} end-to-end d{k}")
+        grad_close(got[k], ref[k], name=f"{name} end-to-end d{k}", mag=None if mag is None else mag[k],
+                   gamma=GAMMA_E2E)
 
 
 def test_empty_and_overflow():
