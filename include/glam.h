@@ -25,8 +25,8 @@
  *  - "[3][n]" is structure-of-arrays: three contiguous rows of n values.  Pointers
  *    must be 16-byte aligned.
  *  - Calls are asynchronous on the given stream and never synchronise, so a sequence
- *    of calls can be captured into a HIP graph.  They are reentrant; the library has no
- *    global mutable state.
+ *    of calls can be captured into a HIP graph.  They are reentrant; the library's only
+ *    global state is glam_loss_noalloc's per-device scratch (see there).
  *  - Arguments are validated on the host before anything is launched; a rejected call
  *    returns GLAM_ERR_INVALID_ARG (or GLAM_ERR_WORKSPACE) and launches nothing.
  *  - Data-dependent overflow (more (tile, Gaussian) pairs than the caller's capacity)
@@ -301,6 +301,24 @@ size_t glam_loss_workspace_bytes(const glam_views* views);
 glam_status glam_loss(const glam_views* views, const float* image, const float* target,
                       float w_ssim, float* dimage, float* loss, float* total, void* workspace,
                       size_t workspace_bytes, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): glam_loss without a workspace
+   argument.  Its per-(32x32 tile, channel) partial sums live in a scratch array the
+   library holds on each device for the life of the process, GLAM_LOSS_SCRATCH_BYTES
+   bytes (glam_loss_workspace_bytes(views) <= that: up to about 1,490 views of 1226x370
+   per call); larger view tables are rejected with GLAM_ERR_WORKSPACE before anything
+   is launched.  Same arguments otherwise, same kernels and results as glam_loss.  The
+   call allocates nothing.  The scratch's device address is resolved on the call's first
+   use on a device (make one call there before capturing a graph if the capture mode
+   forbids that query).  All calls on one device share its scratch: each call
+   overwrites every partial sum it reads, so nothing needs clearing, but calls that
+   overlap in time on one device (other streams, other host threads) race on it and
+   must be serialised by the caller. */
+#define GLAM_LOSS_SCRATCH_BYTES (16u << 20)
+glam_status glam_loss_noalloc(const glam_views* views, const float* image, const float* target,
+                              float w_ssim, float* dimage, float* loss, float* total,
+                              hipStream_t stream);
 
 /* --- backward ------------------------------------------------------------------- */
 

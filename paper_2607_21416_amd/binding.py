@@ -28,8 +28,9 @@ EXPORTS = [
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
     "glam_epipolar_triangulate", "glam_voxelize_workspace_bytes", "glam_voxelize",
-    "glam_insert_rows", "glam_decode_project", "glam_render_bwd_workspace_bytes",
+    "glam_insert_rows", "glam_decode_project", "glam_render_bwd_workspace_bytes", "glam_loss_noalloc",
 ]
+GLAM_LOSS_SCRATCH_BYTES = 16 << 20
 GLAM_ADAM_MAX_GROUPS = 16
 
 
@@ -136,6 +137,7 @@ def load():
         "glam_insert_rows": (I32, [P, P, I32, I64, I32, I64, I64, P, I64, F32, P]),
         "glam_decode_project": (I32, [P, P, I32, P, U32, P, P, P]),
         "glam_render_bwd_workspace_bytes": (SZ, [P, P, I32, I64, U32]),
+        "glam_loss_noalloc": (I32, [P, P, P, F32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -223,6 +225,11 @@ def glam_loss_workspace_bytes(views):
 def glam_loss(views, image, target, w_ssim, dimage, loss, total, ws, ws_bytes, stream):
     return _check("glam_loss", load().glam_loss(ref(views), ref(image), ref(target), float(w_ssim), ref(dimage),
                                                 ref(loss), ref(total), ref(ws), ws_bytes, _stream(stream)))
+
+
+def glam_loss_noalloc(views, image, target, w_ssim, dimage, loss, total, stream):
+    return _check("glam_loss_noalloc", load().glam_loss_noalloc(ref(views), ref(image), ref(target), float(w_ssim),
+                                                                ref(dimage), ref(loss), ref(total), _stream(stream)))
 
 
 def glam_composite_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, g2d, stream):

@@ -229,6 +229,15 @@ glam_status glam_loss(const glam_views* views, const float* image, const float* 
   return glam::launch_loss(*views, image, target, w_ssim, dimage, loss, total, workspace, stream);
 }
 
+glam_status glam_loss_noalloc(const glam_views* views, const float* image, const float* target, float w_ssim,
+                              float* dimage, float* loss, float* total, hipStream_t stream) {
+  if (!views_ok(views) || !ok_ptr(image) || !ok_ptr(target) || !ok_ptr(dimage) || !ok_ptr(loss) ||
+      !(w_ssim >= 0.f) || (total && !aligned16(total)))
+    return GLAM_ERR_INVALID_ARG;
+  if (glam::loss_workspace(*views) > GLAM_LOSS_SCRATCH_BYTES) return GLAM_ERR_WORKSPACE;
+  return glam::launch_loss_noalloc(*views, image, target, w_ssim, dimage, loss, total, stream);
+}
+
 glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
                                const float* bg, const float* T_final, const int32_t* n_contrib, const float* dimage,
                                float* g2d, hipStream_t stream) {

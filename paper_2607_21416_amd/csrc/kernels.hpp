@@ -47,6 +47,8 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
 size_t loss_workspace(const glam_views& v);
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
                         float* dimage, float* loss, float* total, void* ws, hipStream_t s);
+glam_status launch_loss_noalloc(const glam_views& v, const float* image, const float* target, float w_ssim,
+                                float* dimage, float* loss, float* total, hipStream_t s);
 
 glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sigmoid_opacity,
                           bool sigma3, const glam_gaussians& out, const glam_projected* proj, hipStream_t s);

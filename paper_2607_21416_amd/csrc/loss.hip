@@ -16,12 +16,40 @@
 // subtract the leaving one).  Per-(tile, channel) sums of |x - y| and SSIM go to a
 // small workspace; a last kernel reduces each view's sums in double precision.
 // Nothing but the image, the target and dL/dC touches HBM.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace glam {
 
 namespace {
+
+// The scratch of glam_loss_noalloc (the per-(tile, channel) partial sums that
+// glam_loss keeps in its caller's workspace): one array per device, for the life of
+// the process.  Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in); it passes the device address hipGetSymbolAddress resolves, once
+// per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[GLAM_LOSS_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// The current device's scratch address (resolved on its first use).
+glam_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GLAM_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return GLAM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GLAM_ERR_HIP;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return GLAM_OK;
+}
 
 constexpr int kR = 5, kWin = 2 * kR + 1;
 constexpr int kT = 32;               // output tile edge
@@ -290,6 +318,15 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 size_t loss_workspace(const glam_views& v) { return align256(8ull * 3 * (size_t)max_tiles32(v) * (size_t)v.n); }
+
+glam_status launch_loss_noalloc(const glam_views& v, const float* image, const float* target, float w_ssim,
+                                float* dimage, float* loss, float* total, hipStream_t s) {
+  if (loss_workspace(v) > GLAM_LOSS_SCRATCH_BYTES) return GLAM_ERR_WORKSPACE;
+  void* ws = nullptr;
+  const glam_status st = scratch_address(&ws);
+  if (st != GLAM_OK) return st;
+  return launch_loss(v, image, target, w_ssim, dimage, loss, total, ws, s);
+}
 
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
                         float* dimage, float* loss, float* total, void* ws, hipStream_t s) {
