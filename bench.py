@@ -489,9 +489,11 @@ def main():
     scene = synth.config("C3")
     scene1 = one_view(scene, 0)
     choice1 = choose(scene1)
-    log("bench: headline (one view): tile %d, long tiles >= 2^%d, grids %d/%d workgroups per CU (%s)" % (
-        choice1["tile"], choice1["long_log2"], choice1["fwd_blocks_per_cu"], choice1["bwd_blocks_per_cu"],
-        choice1["source"]))
+    sc1 = tuning.schedule(choice1)
+    log("bench: headline (one view): tile %d, long tiles >= 2^%d, grids %dx%d / %dx%d (waves x workgroups per CU, "
+        "forward / backward) (%s)" % (choice1["tile"], sc1["long_log2"], sc1["fwd_group_waves"],
+                                      sc1["fwd_blocks_per_cu"], sc1["bwd_group_waves"], sc1["bwd_blocks_per_cu"],
+                                      choice1["source"]))
     w1 = run_workload(torch, scene1, choice1, args, dev, "config 3, view 0")
     ms = w1["ms"]
     value = 1000.0 / ms

@@ -93,8 +93,9 @@ enum {
      (tile, Gaussian) pair and 8x8 quadrant stores its partial sums in a workspace, and
      a segmented reduction adds each Gaussian's partials in a fixed order (its tiles
      row-major, then quadrants).  Results are bit-identical from run to run and across
-     persistent grid sizes (glam_tuning's blocks per CU); the tile edge and the long-tile
-     threshold choose the arithmetic path of each tile, so they must stay the same.
+     persistent grid sizes (glam_tuning's blocks per CU); the tile edge, the long-tile
+     threshold and the group widths choose the arithmetic path of each tile (where a
+     long range is cut into chunks), so they must stay the same.
      Needs glam_bins.pair_begin from the
      glam_bin_sort call and glam_render_bwd_workspace_bytes with this flag. */
   GLAM_DETERMINISTIC_GRADS = 1u << 3,
@@ -200,18 +201,28 @@ typedef struct {
 #define GLAM_QUEUE_WORDS 1088
 
 /* Schedule of the compositing over a binning (all fields 0 = the built-in default;
-   the results never depend on them, only the time does):
+   the results never depend on the grid sizes, only the time does; the long-tile
+   threshold and the group widths fix where a long range is cut into chunks, and so
+   the FP32 rounding order there):
    long_log2         tiles whose range holds at least 2^long_log2 entries are listed
                      first in the work order and composited by whole workgroups
                      (default 10; 6..24)
+   fwd_group_waves   waves per workgroup of the forward compositing grid: 4 (default),
+                     8 or 16; a long tile's quadrant is split over that many waves
    fwd_blocks_per_cu persistent workgroups per CU of the forward compositing grid
-                     (default and maximum 5)
-   bwd_blocks_per_cu the same for the backward compositing grid (default and maximum 6) */
+                     (groups of 4: default and maximum 5; of 8: default and maximum 2;
+                     of 16: 1)
+   bwd_group_waves   the same for the backward compositing grid
+   bwd_blocks_per_cu the same for the backward grid (groups of 4: default and maximum
+                     6; of 8: 2; of 16: 1)
+   reserved          must be 0 */
 typedef struct {
   int32_t long_log2;
   int32_t fwd_blocks_per_cu;
   int32_t bwd_blocks_per_cu;
-  int32_t reserved;
+  int32_t fwd_group_waves;
+  int32_t bwd_group_waves;
+  int32_t reserved[3];
 } glam_tuning;
 
 /* Sorted (tile, Gaussian) pairs, per-tile ranges and the compositing work order. */

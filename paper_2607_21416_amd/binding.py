@@ -75,7 +75,15 @@ class Projected(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("long_log2", C.c_int32), ("fwd_blocks_per_cu", C.c_int32), ("bwd_blocks_per_cu", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("fwd_group_waves", C.c_int32), ("bwd_group_waves", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+SCHEDULE_KEYS = ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu", "fwd_group_waves", "bwd_group_waves")
+
+
+def make_tuning(schedule: dict | None) -> Tuning:
+    """glam_tuning from a schedule dict (missing keys: 0, the built-in default)."""
+    return Tuning(*(int((schedule or {}).get(k, 0)) for k in SCHEDULE_KEYS))
 
 
 class Bins(C.Structure):

@@ -13,12 +13,20 @@ inline bool tile_edge_supported(int e) { return e == 8 || e == 16 || e == 32; }
 inline int tile_log2(int e) { return e == 8 ? 3 : (e == 16 ? 4 : 5); }
 
 // Compositing schedule defaults and limits (glam_tuning).
+// Workgroups of 4 waves: up to 5 (forward) and 6 (backward) per CU; of 8 waves: up to
+// 2 per CU; of 16: one.
 constexpr int kDefaultLongLog2 = 10;
 constexpr int kMaxFwdBlocksPerCU = 5, kMaxBwdBlocksPerCU = 6;
+inline bool group_ok(int waves, int blocks, int max4) {
+  if (waves == 0 || waves == 4) return blocks >= 0 && blocks <= max4;
+  if (waves == 8 || waves == 16) return blocks >= 0 && blocks * waves <= 16;
+  return false;
+}
 inline bool tuning_ok(const glam_tuning& t) {
-  return (t.long_log2 == 0 || (t.long_log2 >= 6 && t.long_log2 <= 24)) && t.fwd_blocks_per_cu >= 0 &&
-         t.fwd_blocks_per_cu <= kMaxFwdBlocksPerCU && t.bwd_blocks_per_cu >= 0 &&
-         t.bwd_blocks_per_cu <= kMaxBwdBlocksPerCU;
+  return (t.long_log2 == 0 || (t.long_log2 >= 6 && t.long_log2 <= 24)) &&
+         group_ok(t.fwd_group_waves, t.fwd_blocks_per_cu, kMaxFwdBlocksPerCU) &&
+         group_ok(t.bwd_group_waves, t.bwd_blocks_per_cu, kMaxBwdBlocksPerCU) && t.reserved[0] == 0 &&
+         t.reserved[1] == 0 && t.reserved[2] == 0;
 }
 
 // Compute units of the current device (256 if the runtime cannot say).

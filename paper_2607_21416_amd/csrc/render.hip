@@ -16,8 +16,9 @@
 //
 // Long tiles.  A few tiles near the horizon hold thousands of entries whose pixels
 // never saturate; walked by one wave they would set the kernel's length.  Their
-// quadrants are taken first, each by a whole workgroup: the range is cut into rounds
-// of four chunks, one chunk per wave.  Compositing over a chunk is an affine map of
+// quadrants are taken first, each by a whole workgroup (4, 8 or 16 waves, a schedule
+// choice): the range is cut into the fewest rounds of at most 64 entries per wave, and
+// each round into equal chunks, one per wave.  Compositing over a chunk is an affine map of
 // the state in front of it -- the colour grows by T times the chunk's own colour L
 // and T is scaled by the chunk's own transmittance P, both computed from T = 1 -- so
 // each wave first composites its chunk locally (no stop rule), the waves exchange
@@ -33,10 +34,12 @@
 // from which the projection adjoint forms the centre and conic gradients) of the
 // wave's pixels are summed with a reduce-scatter (two gfx950
 // lane-swap stages, then DPP within 16-lane rows) and nine lanes add the totals to HBM
-// with one atomic instruction.  For long tiles the workgroup takes rounds of four
-// chunks from the back: each wave composites its chunk locally, and the state behind
+// with one atomic instruction.  For long tiles the workgroup takes rounds of chunks
+// from the back: each wave composites its chunk locally, and the state behind
 // a chunk follows from the chunks behind it in the round (T divided by their P, B
-// mapped through their affine maps B -> L + P B).
+// mapped through their affine maps B -> L + P B).  The longest tile's critical path is
+// its length over the workgroup's width, which is why wide workgroups pay on single
+// views, whose few horizon tiles would otherwise outlast the rest of the grid.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -44,13 +47,28 @@ namespace glam {
 
 namespace {
 
-constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kIlp = 4;          // hits whose alphas a wave evaluates side by side
-// persistent workgroups per CU at most (the register-limited occupancy the kernels are
-// compiled for); the schedule may ask for fewer
-constexpr int kFwdBlocksPerCU = kMaxFwdBlocksPerCU;
-constexpr int kBwdBlocksPerCU = kMaxBwdBlocksPerCU;
-constexpr int kChunk = 64;       // entries per wave and round of a long tile
+// Waves per SIMD the kernels are compiled for (the register budget): with workgroups
+// of four waves, the most workgroups per CU the schedule may ask for; wider workgroups
+// are compiled for four waves per SIMD (one workgroup of 16 or two of 8 per CU).
+constexpr int kFwdWavesPerEU = kMaxFwdBlocksPerCU;
+constexpr int kBwdWavesPerEU = kMaxBwdBlocksPerCU;
+constexpr int kWideWavesPerEU = 4;
+constexpr int kChunk = 64;       // entries per wave and round of a long tile, at most
+
+// Rounds of a long range of n entries walked by kW waves: the fewest rounds of at most
+// kChunk entries per wave, each cut into kW equal chunks (the last ones may be short or
+// empty).
+struct Rounds {
+  int span;  // entries per round (the last round may hold fewer)
+  int ch;    // entries per wave and round
+};
+template <int kW>
+__device__ __forceinline__ Rounds long_rounds(int n) {
+  const int rounds = max(1, (n + kW * kChunk - 1) / (kW * kChunk));
+  const int span = (n + rounds - 1) / rounds;
+  return Rounds{span, (span + kW - 1) / kW};
+}
 
 // alpha of one record at pixel centre (px, py), shared by both passes so that their
 // skip and stop decisions are bit-identical.  The record holds the conic as a base-2
@@ -212,9 +230,20 @@ struct WaveLds {
   float2 bx[64 + kIlp];
 };
 
-// Exchange of a long-tile round: per wave and lane, up to eight values.
-struct RoundLds {
-  float v[kWaves][8][64];
+// Exchange of a forward long-tile round: per wave and lane, its chunk's local
+// transmittance P, then (T after, weighted colour) and (last, stop entry, state).
+template <int kW>
+struct FwdRound {
+  float p[kW][64];
+  float4 a[kW][64];
+  float4 b[kW][64];
+};
+
+// Exchange of a backward long-tile round, double-buffered (one barrier per round): per
+// wave and lane, the chunk's local (P, L0, L1, L2).
+template <int kW>
+struct BwdRound {
+  float4 a[2][kW][64];
 };
 
 // Gathers the records of entries [c0, c1) (absolute positions in vals, at most 64),
@@ -379,45 +408,48 @@ __device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, co
   if (n_eval) n_eval[it.pix] = st.stop;
 }
 
-// A long tile's quadrant, composited by the whole workgroup in rounds of four chunks.
+// A long tile's quadrant, composited by the whole workgroup in rounds of kW chunks.
 // A chunk is one gathered batch: its hits stay in L for the exact pass, and the next
 // round's records are fetched while the current round is composited.
 static_assert(kChunk == 64, "a long-tile chunk is one gathered batch");
-template <bool kStop>
+template <bool kStop, int kW>
 __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
-                         const Item& it, WaveLds& L, RoundLds& R, int w, int lane, const float* bgc, float* image,
-                         float* T_final, int32_t* n_contrib, int32_t* n_eval) {
+                         const Item& it, WaveLds& L, FwdRound<kW>& R, int w, int lane, const float* bgc,
+                         float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int n = (int)(e - s);
+  const Rounds rd = long_rounds<kW>(n);
   FwdState st{1.f, 0.f, 0.f, 0.f, 0, n, !it.inside};
   Rec nxt;
   uint32_t gid;
   {
-    const uint32_t c0 = s + min((uint32_t)n, (uint32_t)(w * kChunk));
-    fetch_batch(splat, vals, c0, min(c0 + kChunk, e), n_gauss, lane, nxt, gid);
+    const int c0 = min(rd.span, w * rd.ch);
+    fetch_batch(splat, vals, s + c0, s + min(c0 + rd.ch, rd.span), n_gauss, lane, nxt, gid);
   }
-  for (uint32_t r0 = s; r0 < e; r0 += kWaves * kChunk) {
-    const uint32_t c0 = r0 + min(e - r0, (uint32_t)(w * kChunk)), c1 = min(c0 + kChunk, e);
+  for (int r0 = 0; r0 < n; r0 += rd.span) {
+    const int r1 = min(n, r0 + rd.span);
+    const int c0 = min(r1, r0 + w * rd.ch), c1 = min(r1, c0 + rd.ch);
     const Rec cur = nxt;
-    if (e - r0 > (uint32_t)(kWaves * kChunk)) {
-      const uint32_t n0 = r0 + min(e - r0, (uint32_t)((kWaves + w) * kChunk));
-      fetch_batch(splat, vals, n0, min(n0 + kChunk, e), n_gauss, lane, nxt, gid);
+    if (r1 < n) {
+      const int q1 = min(n, r1 + rd.span);
+      const int n0 = min(q1, r1 + w * rd.ch);
+      fetch_batch(splat, vals, s + n0, s + min(q1, n0 + rd.ch), n_gauss, lane, nxt, gid);
     }
     // 1. this wave's chunk, locally (st.done is the same in every wave)
-    const int tag = (int)(c0 - s) + 1 + lane;  // entry number
+    const int tag = c0 + 1 + lane;  // entry number
     const uint64_t hm = __ballot(!st.done) ? compact_hits(cur, c0 + lane < c1, __int_as_float(tag), it, L, lane) : 0ull;
     const int nhit = __popcll(hm);
     float P, L0, L1, L2;
     int llast;
     fwd_local_hits(L, nhit, px, py, st.done, P, L0, L1, L2, llast);
-    R.v[w][0][lane] = P;
+    R.p[w][lane] = P;
     __syncthreads();
     // 2. transmittance in front of the chunk; the chunk where the pixel stops is redone
     //    exactly from it
     float Tin = st.T;
     bool before = st.done;
     for (int j = 0; j < w; ++j) {
-      const float Pj = R.v[j][0][lane];
+      const float Pj = R.p[j][lane];
       if (!before) {
         if (Tin * Pj < kTMin) before = true;
         else Tin *= Pj;
@@ -426,47 +458,46 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
     const bool here = !before && Tin * P < kTMin;
     FwdState ex{Tin, 0.f, 0.f, 0.f, 0, n, !here};
     if (__ballot(here)) fwd_exact_hits<kStop>(L, nhit, px, py, ex);
-    __syncthreads();  // every wave has read the P values
     const int state = before ? 0 : (here ? 2 : 1);
-    R.v[w][0][lane] = here ? ex.T : Tin * P;
-    R.v[w][1][lane] = here ? ex.C0 : Tin * L0;
-    R.v[w][2][lane] = here ? ex.C1 : Tin * L1;
-    R.v[w][3][lane] = here ? ex.C2 : Tin * L2;
-    R.v[w][4][lane] = __int_as_float(here ? ex.last : llast);
-    R.v[w][5][lane] = __int_as_float(here ? ex.stop : n);
-    R.v[w][6][lane] = __int_as_float(state);
+    R.a[w][lane] = here ? make_float4(ex.T, ex.C0, ex.C1, ex.C2) : make_float4(Tin * P, Tin * L0, Tin * L1, Tin * L2);
+    R.b[w][lane] = make_float4(__int_as_float(here ? ex.last : llast), __int_as_float(here ? ex.stop : n),
+                               __int_as_float(state), 0.f);
     __syncthreads();
-    // 3. every wave merges the four chunks in order (identically)
-    for (int j = 0; j < kWaves; ++j) {
-      const int sj = __float_as_int(R.v[j][6][lane]);
+    // 3. every wave merges the round's chunks in order (identically).  The next round
+    //    writes p only after this barrier, and a and b only after its first one, which
+    //    every wave reaches after this merge.
+    for (int j = 0; j < kW; ++j) {
+      const float4 bj = R.b[j][lane];
+      const int sj = __float_as_int(bj.z);
       if (sj == 0) continue;
-      st.T = R.v[j][0][lane];
-      st.C0 += R.v[j][1][lane];
-      st.C1 += R.v[j][2][lane];
-      st.C2 += R.v[j][3][lane];
-      const int lj = __float_as_int(R.v[j][4][lane]);
+      const float4 aj = R.a[j][lane];
+      st.T = aj.x;
+      st.C0 += aj.y;
+      st.C1 += aj.z;
+      st.C2 += aj.w;
+      const int lj = __float_as_int(bj.x);
       st.last = lj > 0 ? lj : st.last;
       if (sj == 2) {
-        st.stop = __float_as_int(R.v[j][5][lane]);
+        st.stop = __float_as_int(bj.y);
         st.done = true;
       }
     }
     if (__ballot(!st.done) == 0) break;  // the same decision in every wave
-    __syncthreads();                      // R is rewritten by the next round
   }
   if (w == 0) fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
 }
 
 // kCount: also record per pixel the entry that stopped the walk (n_eval).
-template <bool kCount>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdBlocksPerCU)))
+template <bool kCount, int kW>
+__global__ void __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(kW == 4 ? kFwdWavesPerEU
+                                                                                      : kWideWavesPerEU)))
 render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
                   uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, int tl,
                   const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
                   uint32_t capacity, uint32_t n_gauss) {
-  __shared__ WaveLds lds[kWaves];
-  __shared__ RoundLds round;
+  __shared__ WaveLds lds[kW];
+  __shared__ FwdRound<kW> round;
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveLds& L = lds[w];
@@ -480,7 +511,7 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
     const Item it = make_item(views, n_views, tile, (int)(li & ((1u << ql) - 1u)), lane, tl);
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
-    fwd_long<kCount>(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
+    fwd_long<kCount, kW>(splat, vals, s, e, n_gauss, it, L, round, w, lane, bgc, image, T_final, n_contrib, n_eval);
   }
   __builtin_amdgcn_s_setprio(0);
   // the other tiles, one quadrant per wave
@@ -494,7 +525,7 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
     fwd_exact<kCount>(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
     fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
   }
-  leave_queue(queue, gridDim.x * kWaves, lane);
+  leave_queue(queue, gridDim.x * kW, lane);
 }
 
 // ---------------------------------------------------------------------------------
@@ -750,71 +781,76 @@ __device__ __forceinline__ BwdState bwd_begin(const Item& it, uint32_t n, const 
   return st;
 }
 
-// A long tile's quadrant, by the whole workgroup in rounds of four chunks from the back.
+// A long tile's quadrant, by the whole workgroup in rounds of kW chunks from the back.
 // A chunk is one gathered batch, compacted once for both passes; the next round's
 // records are fetched while the current round is walked.
-template <bool kDet>
+template <bool kDet, int kW>
 __device__ void bwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t n_gauss, const Item& it,
-                         WaveLds& L, RoundLds& R, int w, int lane, GradStage& G, int& nst, int off, BwdState st,
+                         WaveLds& L, BwdRound<kW>& R, int w, int lane, GradStage& G, int& nst, int off, BwdState st,
                          float* g2d, const DetCtx& dc) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
   const int top = it.live ? wave_max(st.last) : 0;  // the same in every wave
+  const Rounds rd = long_rounds<kW>(top);
   Rec nxt;
   uint32_t ngid = 0;
   {
-    const int c1 = max(0, top - w * kChunk);
-    fetch_batch(splat, vals, s + max(0, c1 - kChunk), s + c1, n_gauss, lane, nxt, ngid);
+    const int lo = max(0, top - rd.span), c1 = max(lo, top - w * rd.ch);
+    fetch_batch(splat, vals, s + max(lo, c1 - rd.ch), s + c1, n_gauss, lane, nxt, ngid);
   }
-  for (int hi = top; hi > 0; hi -= kWaves * kChunk) {
-    const int c1 = max(0, hi - w * kChunk), c0 = max(0, c1 - kChunk);
+  int buf = 0;
+  for (int hi = top; hi > 0; hi -= rd.span, buf ^= 1) {
+    const int lo = max(0, hi - rd.span);
+    const int c1 = max(lo, hi - w * rd.ch), c0 = max(lo, c1 - rd.ch);
     const Rec cur = nxt;
     const uint32_t cgid = ngid;
-    if (hi > kWaves * kChunk) {
-      const int n1 = max(0, hi - (kWaves + w) * kChunk);
-      fetch_batch(splat, vals, s + max(0, n1 - kChunk), s + n1, n_gauss, lane, nxt, ngid);
+    if (lo > 0) {
+      const int nlo = max(0, lo - rd.span), n1 = max(nlo, lo - w * rd.ch);
+      fetch_batch(splat, vals, s + max(nlo, n1 - rd.ch), s + n1, n_gauss, lane, nxt, ngid);
     }
     const bool valid = c0 + lane < c1;
     const uint64_t hm = compact_hits(cur, valid, hit_tag<kDet>(cur, cgid, dc, valid), it, L, lane);
     float P, L0, L1, L2;
     bwd_local_hits(L, hm, c0, st.last, px, py, P, L0, L1, L2);
-    R.v[w][0][lane] = P;
-    R.v[w][1][lane] = L0;
-    R.v[w][2][lane] = L1;
-    R.v[w][3][lane] = L2;
+    R.a[buf][w][lane] = make_float4(P, L0, L1, L2);
+    // One barrier per round: the buffer written here is next written two rounds on,
+    // after the next round's barrier, which every wave reaches after reading this one.
     __syncthreads();
     // state behind this wave's chunk, from the chunks behind it in the round
     BwdState cs = st;
     for (int j = 0; j < w; ++j) {
-      const float Pj = R.v[j][0][lane];
-      cs.T = cs.T / Pj;
-      cs.B0 = fmaf(Pj, cs.B0, R.v[j][1][lane]);
-      cs.B1 = fmaf(Pj, cs.B1, R.v[j][2][lane]);
-      cs.B2 = fmaf(Pj, cs.B2, R.v[j][3][lane]);
+      const float4 pj = R.a[buf][j][lane];
+      cs.T = cs.T / pj.x;
+      cs.B0 = fmaf(pj.x, cs.B0, pj.y);
+      cs.B1 = fmaf(pj.x, cs.B1, pj.z);
+      cs.B2 = fmaf(pj.x, cs.B2, pj.w);
     }
     bwd_hits<kDet>(L, hm, c0, px, py, lane, G, nst, off, cs, g2d);
     // state in front of the round (identical in every wave)
-    for (int j = 0; j < kWaves; ++j) {
-      const float Pj = R.v[j][0][lane];
-      st.T = st.T / Pj;
-      st.B0 = fmaf(Pj, st.B0, R.v[j][1][lane]);
-      st.B1 = fmaf(Pj, st.B1, R.v[j][2][lane]);
-      st.B2 = fmaf(Pj, st.B2, R.v[j][3][lane]);
+    for (int j = 0; j < kW; ++j) {
+      const float4 pj = R.a[buf][j][lane];
+      st.T = st.T / pj.x;
+      st.B0 = fmaf(pj.x, st.B0, pj.y);
+      st.B1 = fmaf(pj.x, st.B1, pj.z);
+      st.B2 = fmaf(pj.x, st.B2, pj.w);
     }
-    __syncthreads();  // R is rewritten by the next round
   }
+  // the workgroup's next item rewrites the exchange buffers only after the barrier in
+  // next_long_item, which every wave reaches after its last read here
 }
 
 // kDet: g2d is the partial buffer of the reproducible backward ([pairs << ql][9], zeroed
 // by the caller), each (range entry, quadrant) hit storing its own nine sums there.
-template <bool kDet>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBlocksPerCU))) composite_bwd_kernel(
+template <bool kDet, int kW>
+__global__ void __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(kW == 4 ? kBwdWavesPerEU
+                                                                                      : kWideWavesPerEU)))
+composite_bwd_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
     int n_views, int n_tiles, int tl, const float* bg, const float* T_final, const int32_t* n_contrib,
     const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss, const uint32_t* pair_begin) {
-  __shared__ WaveLds lds[kWaves];
-  __shared__ RoundLds round;
-  __shared__ GradStage stage[kWaves];
+  __shared__ WaveLds lds[kW];
+  __shared__ BwdRound<kW> round;
+  __shared__ GradStage stage[kW];
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveLds& L = lds[w];
@@ -833,7 +869,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
     const uint32_t e = min(ranges[2 * tile + 1], capacity);
     const uint32_t s = min(ranges[2 * tile], e);
     const DetCtx dc{pair_begin, it.qx0 >> tl, it.qy0 >> tl, tl, ql, quad};
-    bwd_long<kDet>(splat, vals, s, n_gauss, it, L, round, w, lane, G, nst, off,
+    bwd_long<kDet, kW>(splat, vals, s, n_gauss, it, L, round, w, lane, G, nst, off,
                    bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage), g2d, dc);
   }
   __builtin_amdgcn_s_setprio(0);
@@ -850,7 +886,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdBl
     bwd_walk<kDet>(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, st, g2d, dc);
   }
   stage_flush<kDet>(G, nst, off, lane, g2d);
-  leave_queue(q, gridDim.x * kWaves, lane);
+  leave_queue(q, gridDim.x * kW, lane);
 }
 
 // The reproducible backward's segmented reduction: view-Gaussian g's nine sums are its
@@ -927,6 +963,13 @@ unsigned persistent_blocks(long long n_items, int waves_per_block, int blocks_pe
   return (unsigned)(need < want ? (need > 0 ? need : 1) : want);
 }
 
+// The compiled (waves per workgroup, workgroups per CU) of a schedule: group 0 is the
+// default four; blocks 0 is the default for the group (the compiled occupancy).
+template <int kW, bool kFwd>
+constexpr int default_blocks() {
+  return kW == 4 ? (kFwd ? kFwdWavesPerEU : kBwdWavesPerEU) : 4 * kWideWavesPerEU / kW;
+}
+
 glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins, const glam_views& v,
                               const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
                               hipStream_t s) {
@@ -936,12 +979,20 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
   }
   const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
   if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
-  const int bpc = bins.tuning.fwd_blocks_per_cu > 0 ? bins.tuning.fwd_blocks_per_cu : kFwdBlocksPerCU;
-  const auto kernel = n_eval ? render_fwd_kernel<true> : render_fwd_kernel<false>;
-  hipLaunchKernelGGL(kernel, dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)), dim3(64 * kWaves), 0, s,
-                     proj.splat, bins.vals, bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n,
-                     (int)v.n_tiles, tl, bg, image, T_final, n_contrib, n_eval, (uint32_t)bins.capacity,
-                     (uint32_t)v.n_gauss);
+  const int gw = bins.tuning.fwd_group_waves > 0 ? bins.tuning.fwd_group_waves : 4;
+  const long long items = v.n_tiles << ql;
+  auto launch = [&](auto kernel, int kw, int dflt) {
+    const int bpc = bins.tuning.fwd_blocks_per_cu > 0 ? bins.tuning.fwd_blocks_per_cu : dflt;
+    hipLaunchKernelGGL(kernel, dim3(persistent_blocks(items, kw, bpc)), dim3(64 * kw), 0, s, proj.splat, bins.vals,
+                       bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, image,
+                       T_final, n_contrib, n_eval, (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
+  };
+  if (gw == 16)
+    launch(n_eval ? render_fwd_kernel<true, 16> : render_fwd_kernel<false, 16>, 16, default_blocks<16, true>());
+  else if (gw == 8)
+    launch(n_eval ? render_fwd_kernel<true, 8> : render_fwd_kernel<false, 8>, 8, default_blocks<8, true>());
+  else
+    launch(n_eval ? render_fwd_kernel<true, 4> : render_fwd_kernel<false, 4>, 4, default_blocks<4, true>());
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -968,13 +1019,22 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
   if (n > 0)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
                        acc, n);
-  const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : kBwdBlocksPerCU;
-  if (v.n_tiles > 0 && v.n_gauss > 0)
-    hipLaunchKernelGGL(det ? composite_bwd_kernel<true> : composite_bwd_kernel<false>,
-                       dim3(persistent_blocks(v.n_tiles << ql, kWaves, bpc)), dim3(64 * kWaves), 0, s, proj.splat,
-                       bins.vals, bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl,
-                       bg, T_final, n_contrib, dimage, acc, (uint32_t)bins.capacity, (uint32_t)v.n_gauss,
-                       bins.pair_begin);
+  const int gw = bins.tuning.bwd_group_waves > 0 ? bins.tuning.bwd_group_waves : 4;
+  const long long items = v.n_tiles << ql;
+  auto launch = [&](auto kernel, int kw, int dflt) {
+    const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : dflt;
+    hipLaunchKernelGGL(kernel, dim3(persistent_blocks(items, kw, bpc)), dim3(64 * kw), 0, s, proj.splat, bins.vals,
+                       bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, T_final,
+                       n_contrib, dimage, acc, (uint32_t)bins.capacity, (uint32_t)v.n_gauss, bins.pair_begin);
+  };
+  if (v.n_tiles > 0 && v.n_gauss > 0) {
+    if (gw == 16)
+      launch(det ? composite_bwd_kernel<true, 16> : composite_bwd_kernel<false, 16>, 16, default_blocks<16, false>());
+    else if (gw == 8)
+      launch(det ? composite_bwd_kernel<true, 8> : composite_bwd_kernel<false, 8>, 8, default_blocks<8, false>());
+    else
+      launch(det ? composite_bwd_kernel<true, 4> : composite_bwd_kernel<false, 4>, 4, default_blocks<4, false>());
+  }
   if (det && v.n_gauss > 0)
     hipLaunchKernelGGL(det_reduce_kernel, dim3((unsigned)((v.n_gauss + 255) / 256)), dim3(256), 0, s, det_part,
                        bins.pair_begin, proj.ntiles, (long long)v.n_gauss, ql, (uint32_t)bins.capacity, g2d);

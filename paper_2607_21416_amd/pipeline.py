@@ -99,8 +99,7 @@ class Pipeline:
         self.device = torch.device(device)
         dev = self.device
         self.scene = scene
-        self.tuning = B.Tuning(*(int((tuning or {}).get(k, 0)) for k in ("long_log2", "fwd_blocks_per_cu",
-                                                                          "bwd_blocks_per_cu")), 0)
+        self.tuning = B.make_tuning(tuning)
         self.plain = scene["kind"] == "plain"
         self.flags = B.GLAM_PLAIN if self.plain else 0
         if not self.plain and scene.get("opacity_mode", "tanh") == "sigmoid":
@@ -317,8 +316,7 @@ class Pipeline:
 
     def set_tuning(self, tuning: dict | None):
         """Changes the compositing schedule (takes effect from the next bin_sort)."""
-        self.tuning = B.Tuning(*(int((tuning or {}).get(k, 0)) for k in ("long_log2", "fwd_blocks_per_cu",
-                                                                          "bwd_blocks_per_cu")), 0)
+        self.tuning = B.make_tuning(tuning)
         self.bins.tuning = self.tuning
 
     def stream(self):

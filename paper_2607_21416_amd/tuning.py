@@ -1,15 +1,17 @@
 """Autotuner of the work decomposition: the binning tile edge and the compositing
-schedule (long-tile threshold, persistent grid sizes).  None of these change a result,
-only the time, so the tuner times candidates on the caller's own workload and keeps the
-fastest.
+schedule (long-tile threshold, workgroup widths, persistent grid sizes).  None of these
+change a result beyond the FP32 rounding order of the compositing sums, only the time,
+so the tuner times candidates on the caller's own workload and keeps the fastest.
 
 Search, by coordinate descent on the measured time:
   1. tile edge in {8, 16, 32}: the whole step (decode .. backward), since the edge moves
      work between the bin sort (more pairs for smaller tiles) and the compositing
      (each 8x8 quadrant walks its whole tile's range, so larger tiles cull more);
-  2. long-tile threshold 2^k: the two compositing kernels (the bin sort re-run once per
+  2. forward and backward grids (waves per workgroup, which is also how many waves
+     share a long tile's quadrant, and workgroups per CU), each on its own kernel;
+  3. long-tile threshold 2^k: the two compositing kernels (the bin sort re-run once per
      candidate to rebuild the work order);
-  3. forward and backward grid sizes (workgroups per CU), each on its own kernel.
+  4. the grids again, under the chosen threshold.
 Choices are cached per workload signature (scene kind, views and their resolutions,
 Gaussian and anchor counts, loss); set GLAM_TUNE_CACHE to a file path to keep them
 across processes.  Choices measured earlier ship in tune_choices.json beside this file
@@ -29,9 +31,12 @@ from .pipeline import TILE, Pipeline
 
 TILES = (8, 16, 32)
 LONG_LOG2 = (8, 9, 10, 11, 12)
-FWD_BLOCKS = (3, 4, 5)
-BWD_BLOCKS = (4, 5, 6)
-DEFAULT = {"tile": TILE, "long_log2": 10, "fwd_blocks_per_cu": 5, "bwd_blocks_per_cu": 6}
+# (waves per workgroup, workgroups per CU) of the two compositing grids
+FWD_GRIDS = ((4, 3), (4, 4), (4, 5), (8, 1), (8, 2), (16, 1))
+BWD_GRIDS = ((4, 4), (4, 5), (4, 6), (8, 1), (8, 2), (16, 1))
+DEFAULT = {"tile": TILE, "long_log2": 10, "fwd_blocks_per_cu": 5, "bwd_blocks_per_cu": 6, "fwd_group_waves": 4,
+           "bwd_group_waves": 4}
+SCHEDULE = ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu", "fwd_group_waves", "bwd_group_waves")
 
 _cache: dict = {}
 STORED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_choices.json")
@@ -86,8 +91,8 @@ def _time(fn, iters: int) -> float:
 
 
 def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bool = True) -> dict:
-    """Returns {tile, long_log2, fwd_blocks_per_cu, bwd_blocks_per_cu} for this workload,
-    and the measured times in ms under key "ms"."""
+    """Returns {tile, long_log2, fwd/bwd_blocks_per_cu, fwd/bwd_group_waves} for this
+    workload, and the measured times in ms under key "ms"."""
     key = workload_key(scene)
     if use_cache:
         if key in _cache:
@@ -119,7 +124,7 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
         torch.cuda.empty_cache()
     best["tile"] = min(step_ms, key=step_ms.get)
     ms["step_by_tile"] = step_ms
-    # 2-3. the schedule, on the chosen tile edge
+    # 2-4. the schedule, on the chosen tile edge
     pipe = Pipeline(scene, device=device, tile=best["tile"])
     pipe.fit_capacity()
     pipe.status.zero_()
@@ -128,8 +133,27 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
     torch.cuda.synchronize()
 
     def sched(**kw):
-        return {k: best[k] for k in ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu")} | kw
+        return {k: best[k] for k in SCHEDULE} | kw
 
+    def grids(tag):
+        fwd_ms, bwd_ms = {}, {}
+        for gw, b in FWD_GRIDS:
+            pipe.set_tuning(sched(fwd_group_waves=gw, fwd_blocks_per_cu=b))
+            fwd_ms[f"{gw}x{b}"] = _time(pipe.render, iters)
+        for gw, b in BWD_GRIDS:
+            pipe.set_tuning(sched(bwd_group_waves=gw, bwd_blocks_per_cu=b))
+            bwd_ms[f"{gw}x{b}"] = _time(pipe.composite_bwd, iters)
+        f = min(fwd_ms, key=fwd_ms.get)
+        g = min(bwd_ms, key=bwd_ms.get)
+        best["fwd_group_waves"], best["fwd_blocks_per_cu"] = (int(x) for x in f.split("x"))
+        best["bwd_group_waves"], best["bwd_blocks_per_cu"] = (int(x) for x in g.split("x"))
+        say(f"tune: grids ({tag}): forward {f} ({fwd_ms[f]:.3f} ms), backward {g} ({bwd_ms[g]:.3f} ms) "
+            "(waves x workgroups per CU)")
+        return fwd_ms, bwd_ms
+
+    pipe.forward()
+    pipe.backward()
+    grids("default threshold")
     long_ms = {}
     for k in LONG_LOG2:
         pipe.set_tuning(sched(long_log2=k))
@@ -141,18 +165,7 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
     best["long_log2"] = min(long_ms, key=long_ms.get)
     pipe.set_tuning(sched())
     pipe.bin_sort()
-    fwd_ms = {}
-    for b in FWD_BLOCKS:
-        pipe.set_tuning(sched(fwd_blocks_per_cu=b))
-        fwd_ms[b] = _time(pipe.render, iters)
-        say(f"tune: forward grid {b}/CU: {fwd_ms[b]:.3f} ms")
-    best["fwd_blocks_per_cu"] = min(fwd_ms, key=fwd_ms.get)
-    bwd_ms = {}
-    for b in BWD_BLOCKS:
-        pipe.set_tuning(sched(bwd_blocks_per_cu=b))
-        bwd_ms[b] = _time(pipe.composite_bwd, iters)
-        say(f"tune: backward grid {b}/CU: {bwd_ms[b]:.3f} ms")
-    best["bwd_blocks_per_cu"] = min(bwd_ms, key=bwd_ms.get)
+    fwd_ms, bwd_ms = grids(f"threshold 2^{best['long_log2']}")
     pipe.check_status()
     del pipe
     torch.cuda.empty_cache()
@@ -167,5 +180,6 @@ def autotune(scene: dict, device="cuda", iters: int = 5, log=None, use_cache: bo
 
 
 def schedule(choice: dict) -> dict:
-    """The compositing-schedule part of a tuner choice (for Pipeline(tuning=...))."""
-    return {k: choice[k] for k in ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu")}
+    """The compositing-schedule part of a tuner choice (for Pipeline(tuning=...)); a
+    choice without group widths takes the default four waves."""
+    return {k: int(choice.get(k, DEFAULT[k])) for k in SCHEDULE}

@@ -65,8 +65,13 @@ def test_schedule_out_of_range_is_rejected():
     views.dev = fake
     proj = B.Projected(fake, fake, fake, fake, fake, fake)
     need = lib.glam_bin_sort_workspace_bytes(B.ref(views), 1000)
-    for bad in (B.Tuning(5, 0, 0, 0), B.Tuning(25, 0, 0, 0), B.Tuning(0, 6, 0, 0), B.Tuning(0, 0, 7, 0),
-                B.Tuning(0, -1, 0, 0)):
+    bad_sched = [dict(long_log2=5), dict(long_log2=25), dict(fwd_blocks_per_cu=6), dict(bwd_blocks_per_cu=7),
+                 dict(fwd_blocks_per_cu=-1), dict(fwd_group_waves=12), dict(bwd_group_waves=2),
+                 dict(fwd_group_waves=16, fwd_blocks_per_cu=2), dict(bwd_group_waves=8, bwd_blocks_per_cu=3),
+                 dict(fwd_group_waves=-4)]
+    reserved = B.make_tuning(None)
+    reserved.reserved[1] = 1
+    for bad in [B.make_tuning(d) for d in bad_sched] + [reserved]:
         bins = B.Bins(fake, fake, fake, 1000, fake, fake, fake, bad)
         assert lib.glam_bin_sort(B.ref(proj), B.ref(views), B.ref(bins), C.c_void_p(fake), need,
                                  None) == B.GLAM_ERR_INVALID_ARG

@@ -78,6 +78,12 @@ def test_deterministic_gradients_repeat_bit_for_bit(name):
     third = _grads(other)
     for k in first:
         assert np.array_equal(first[k].view(np.uint32), third[k].view(np.uint32)), k
+    # the same with long tiles shared by workgroups of 8 waves, one and two per CU
+    wide = dict(long_log2=8, fwd_group_waves=8, bwd_group_waves=8)
+    w1 = _grads(_run(scene, deterministic=True, tuning=dict(wide, fwd_blocks_per_cu=1, bwd_blocks_per_cu=1)))
+    w2 = _grads(_run(scene, deterministic=True, tuning=dict(wide, fwd_blocks_per_cu=2, bwd_blocks_per_cu=2)))
+    for k in first:
+        assert np.array_equal(w1[k].view(np.uint32), w2[k].view(np.uint32)), k
     # the default path (atomics) agrees to FP32 rounding
     ref = _grads(_run(scene))
     for k in first:

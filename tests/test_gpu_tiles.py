@@ -1,9 +1,10 @@
 """The binning tile edge and the compositing schedule change the work decomposition,
 never the result: with 8x8 and 32x32 tiles (one and sixteen 8x8 compositing quadrants
-per tile) and a non-default schedule (a low long-tile threshold, smaller persistent
-grids), the tile assignment, sort order and ranges match the oracle's at that tile edge
-bit for bit, the long tiles are counted and listed first, and the pixels and the 2-D
-gradients match the oracle stage-wise (same bars as the 16x16 parity tests)."""
+per tile) and non-default schedules (a low long-tile threshold, smaller persistent
+grids, long tiles shared by workgroups of 8 and 16 waves), the tile assignment, sort
+order and ranges match the oracle's at that tile edge bit for bit, the long tiles are
+counted and listed first, and the pixels and the 2-D gradients match the oracle
+stage-wise (same bars as the 16x16 parity tests)."""
 import numpy as np
 import pytest
 import torch
@@ -17,19 +18,29 @@ from test_gpu_parity import _masked_dimage, anchor_small, g2d_gradients, plain_d
 pytestmark = pytest.mark.gpu
 
 SCENES = {"plain_ragged": plain_ragged, "anchor_small": anchor_small, "plain_dense": plain_dense}
-SCHEDULE = {"long_log2": 8, "fwd_blocks_per_cu": 3, "bwd_blocks_per_cu": 4}
+SCHEDULES = {
+    "narrow": {"long_log2": 8, "fwd_blocks_per_cu": 3, "bwd_blocks_per_cu": 4},
+    # every range of 128 entries or more walked by 16 waves: a round of up to 1024 entries,
+    # chunks of 8..64, pixels that stop inside a round (plain_dense)
+    "wide16": {"long_log2": 7, "fwd_group_waves": 16, "bwd_group_waves": 16},
+    "wide8": {"long_log2": 8, "fwd_group_waves": 8, "fwd_blocks_per_cu": 1, "bwd_group_waves": 8,
+              "bwd_blocks_per_cu": 2},
+}
+CASES = ([(t, n, "narrow") for t in (8, 32) for n in SCENES] + [(16, n, "wide16") for n in SCENES]
+         + [(t, "plain_dense", "wide8") for t in (8, 32)])
 
 
-@pytest.fixture(scope="module", params=[(t, n) for t in (8, 32) for n in SCENES], ids=lambda p: f"tile{p[0]}-{p[1]}")
+@pytest.fixture(scope="module", params=CASES, ids=lambda p: f"tile{p[0]}-{p[1]}-{p[2]}")
 def case(request):
-    tile, name = request.param
+    tile, name, sched = request.param
     scene = SCENES[name]()
-    pipe = run(scene, tile=tile, tuning=SCHEDULE)
-    return tile, name, scene, pipe, host(pipe)
+    print(f"tile {tile}, {name}, schedule {SCHEDULES[sched]}", flush=True)
+    pipe = run(scene, tile=tile, tuning=SCHEDULES[sched])
+    return tile, name, scene, pipe, host(pipe), SCHEDULES[sched]
 
 
 def test_bin_sort_bit_exact(case):
-    tile, name, scene, pipe, h = case
+    tile, name, scene, pipe, h, sched = case
     sls = view_slices(pipe)
     G = h["ntiles"].shape[0]
     prect = np.zeros((4, G), np.int32)
@@ -46,16 +57,16 @@ def test_bin_sort_bit_exact(case):
     assert np.array_equal((h["keys"] >> np.uint64(h["dbits"])).astype(np.int64), ref["tiles"].astype(np.int64))
     assert np.array_equal(h["ranges"], ref["ranges"])
     lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
-    n_long = int((lens >= 1 << SCHEDULE["long_log2"]).sum())
+    n_long = int((lens >= 1 << sched["long_log2"]).sum())
     assert int(pipe.status.cpu().numpy()[7]) == n_long
     order = pipe.order.cpu().numpy().astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(len(lens)))
-    assert (lens[order[:n_long]] >= 1 << SCHEDULE["long_log2"]).all()
-    assert (lens[order[n_long:]] < 1 << SCHEDULE["long_log2"]).all()
+    assert (lens[order[:n_long]] >= 1 << sched["long_log2"]).all()
+    assert (lens[order[n_long:]] < 1 << sched["long_log2"]).all()
 
 
 def test_render_fwd_stagewise(case):
-    tile, name, scene, pipe, h = case
+    tile, name, scene, pipe, h, sched = case
     for v, sl in enumerate(view_slices(pipe)):
         pr, gs = gpu_splats(h, sl)
         vals = h["vals"].astype(np.int64) - sl["g0"]
@@ -66,7 +77,7 @@ def test_render_fwd_stagewise(case):
 
 
 def test_composite_bwd_stagewise(case):
-    tile, name, scene, pipe, h = case
+    tile, name, scene, pipe, h, sched = case
     dims = []
     for v, sl in enumerate(view_slices(pipe)):
         pr, gs = gpu_splats(h, sl)
@@ -93,7 +104,7 @@ def test_composite_bwd_stagewise(case):
 def test_images_agree_across_tile_edges(case):
     # the image does not depend on the tile edge (opacity-aware footprints): the 16x16
     # default reproduces the same pixels except where a decision sits within rounding
-    tile, name, scene, pipe, h = case
+    tile, name, scene, pipe, h, sched = case
     ref_pipe = run(scene)
     hr = host(ref_pipe)
     for v, sl in enumerate(view_slices(pipe)):
@@ -108,7 +119,9 @@ def test_autotuner_choice_is_valid_and_harmless():
     scene = anchor_small()
     choice = tuning.autotune(scene, iters=2, use_cache=False)
     assert choice["tile"] in tuning.TILES and choice["long_log2"] in tuning.LONG_LOG2
-    assert choice["fwd_blocks_per_cu"] in tuning.FWD_BLOCKS and choice["bwd_blocks_per_cu"] in tuning.BWD_BLOCKS
+    s = tuning.schedule(choice)
+    assert (s["fwd_group_waves"], s["fwd_blocks_per_cu"]) in tuning.FWD_GRIDS
+    assert (s["bwd_group_waves"], s["bwd_blocks_per_cu"]) in tuning.BWD_GRIDS
     a = host(run(scene, tile=choice["tile"], tuning=tuning.schedule(choice)))
     b = host(run(scene))
     np.testing.assert_allclose(a["loss"], b["loss"], rtol=1e-5)

@@ -16,9 +16,25 @@ def test_workload_key_separates_workloads_and_rounds_sizes():
 def test_schedule_and_defaults():
     assert tuning.DEFAULT["tile"] in tuning.TILES
     s = tuning.schedule(tuning.DEFAULT)
-    assert set(s) == {"long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu"}
-    assert s["long_log2"] in tuning.LONG_LOG2 and s["fwd_blocks_per_cu"] == max(tuning.FWD_BLOCKS)
-    assert s["bwd_blocks_per_cu"] == max(tuning.BWD_BLOCKS)
+    assert set(s) == {"long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu", "fwd_group_waves", "bwd_group_waves"}
+    assert s["long_log2"] in tuning.LONG_LOG2
+    assert (s["fwd_group_waves"], s["fwd_blocks_per_cu"]) == max(g for g in tuning.FWD_GRIDS if g[0] == 4)
+    assert (s["bwd_group_waves"], s["bwd_blocks_per_cu"]) == max(g for g in tuning.BWD_GRIDS if g[0] == 4)
+    # a choice stored before the group widths existed takes four waves
+    old = {"tile": 16, "long_log2": 10, "fwd_blocks_per_cu": 3, "bwd_blocks_per_cu": 4}
+    assert tuning.schedule(old)["fwd_group_waves"] == 4 and tuning.schedule(old)["bwd_group_waves"] == 4
+
+
+def test_every_grid_candidate_is_a_valid_schedule():
+    # the library accepts every (waves, workgroups per CU) the tuner tries, and the
+    # built-in defaults
+    from paper_2607_21416_amd import binding as B
+    for gw, b in tuning.FWD_GRIDS:
+        assert gw * b <= (20 if gw == 4 else 16)
+    for gw, b in tuning.BWD_GRIDS:
+        assert gw * b <= (24 if gw == 4 else 16)
+    t = B.make_tuning(tuning.schedule(tuning.DEFAULT))
+    assert (t.fwd_group_waves, t.bwd_group_waves, list(t.reserved)) == (4, 4, [0, 0, 0])
 
 
 def test_stored_choices_are_valid_and_used():
@@ -26,7 +42,9 @@ def test_stored_choices_are_valid_and_used():
     assert stored
     for key, c in stored.items():
         assert c["tile"] in tuning.TILES and c["long_log2"] in tuning.LONG_LOG2
-        assert c["fwd_blocks_per_cu"] in tuning.FWD_BLOCKS and c["bwd_blocks_per_cu"] in tuning.BWD_BLOCKS
+        s = tuning.schedule(c)
+        assert (s["fwd_group_waves"], s["fwd_blocks_per_cu"]) in tuning.FWD_GRIDS
+        assert (s["bwd_group_waves"], s["bwd_blocks_per_cu"]) in tuning.BWD_GRIDS
     # the benchmark workloads have a stored choice, returned without measuring (no GPU here)
     for name in ("C3", "C4"):
         scene = synth.config(name)
