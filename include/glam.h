@@ -159,7 +159,8 @@ typedef struct {
   const float* feat;       /* [A][F] row-major                                      */
   const float* log_scale;  /* [A]                                                   */
   const float* offs;       /* [3][A*K], Gaussian j of anchor a at a*K + j           */
-  int32_t A, F, K;         /* F == 32, K <= 16 are built                            */
+  int32_t A, F, K;         /* built (F, K): (8, 10), (16, 4), (32, 10), (64, 10);
+                              others: GLAM_ERR_UNSUPPORTED                          */
   int32_t hidden;          /* MLP hidden width, 32                                  */
 } glam_anchors;
 
@@ -252,6 +253,7 @@ typedef struct {
 /* Workspace bytes glam_bin_sort needs for this view table and pair capacity. */
 size_t glam_bin_sort_workspace_bytes(const glam_views* views, int64_t capacity);
 
+
 /* --- forward -------------------------------------------------------------------- */
 
 /* Eq. 2 + Eq. 6: for every view v, decode the anchors of partition cam.partition with
@@ -271,7 +273,10 @@ glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, i
                                 const glam_views* views, uint32_t flags, glam_gaussians* out,
                                 glam_projected* proj, hipStream_t stream);
 
-/* Projection and footprint of every view-Gaussian.  Culls depth <= 0.2 and opacity
+/* Projection and footprint of every view-Gaussian: the step of the differentiable 3-D
+   Gaussian rasteriser of Sec. III-A that maps each Gaussian onto the image plane, where
+   Eq. 1 evaluates its alpha (EWA splatting, as in the 3DGS lineage the paper builds
+   on).  Culls depth <= 0.2 and opacity
    <= 1/255; Jacobian x/z, y/z clamped to 1.15x the image (beyond a 0.15-image border);
    2-D covariance dilated by 0.3 px^2; footprint box: |x + 0.5 - u| <= ext_x with
    ext = sqrt(2 ln(255 opacity) Sigma2D_xx) (likewise y), outside of which the
@@ -279,7 +284,9 @@ glam_status glam_decode_project(const glam_anchors* anchors, const float* mlp, i
 glam_status glam_project(const glam_gaussians* gauss, const glam_views* views, uint32_t flags,
                          glam_projected* out, hipStream_t stream);
 
-/* Tile binning and device LSD radix sort by (global tile, depth): pairs emitted per
+/* The depth order Eq. 1 composites in (front to back, Sec. III-A), per tile of the
+   lineage's tile-based rasteriser: tile binning and device LSD radix sort by (global
+   tile, depth): pairs emitted per
    view-Gaussian in index order (row-major over its tiles), stable sort, so equal
    depths keep index order.  ranges of empty tiles are [0, 0).  Also writes order
    (longest ranges first) for the compositing work queue. */
@@ -353,7 +360,8 @@ typedef struct {
                   d(u, v, A, B, C, opacity, r, g, b) per view-Gaussian, zero when culled */
 } glam_grads;
 
-/* Reverse compositing from (T_final, n_contrib): T_i recovered by division by
+/* Adjoint of Eq. 1 (the rasteriser of Sec. III-A is differentiated to minimise Eq. 3):
+   reverse compositing from (T_final, n_contrib): T_i recovered by division by
    (1 - alpha_i), per-Gaussian gradients reduced across each wavefront before FP32
    atomics.  Overwrites g2d [n_gauss][9] (zeroes it first). */
 glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins,
@@ -361,14 +369,16 @@ glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins
                                const int32_t* n_contrib, const float* dimage, float* g2d,
                                hipStream_t stream);
 
-/* Projection adjoint: g2d -> dgauss (anchor mode: per view-Gaussian; plain mode:
+/* Adjoint of the projection of Sec. III-A (see glam_project): g2d -> dgauss (anchor
+   mode: per view-Gaussian; plain mode:
    summed over views into the plain parameter gradients).  Overwrites dgauss. */
 glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* proj,
                              const glam_views* views, uint32_t flags, const float* g2d,
                              glam_gaussians* dgauss, hipStream_t stream);
 
-/* Decode adjoint: dgauss -> dfeat, doffs, dlog_scale, dmlp, summed over the views of
-   each partition.  Overwrites them.  workspace: glam_decode_bwd_workspace_bytes. */
+/* Adjoint of Eq. 2 with Eq. 6's per-partition MLPs (Sec. III-A, III-D): dgauss ->
+   dfeat, doffs, dlog_scale, dmlp, summed over the views of each partition.  Overwrites
+   them.  workspace: glam_decode_bwd_workspace_bytes. */
 size_t glam_decode_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views,
                                        int32_t n_parts);
 glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32_t n_parts,
@@ -384,7 +394,9 @@ glam_status glam_decode_bwd(const glam_anchors* anchors, const float* mlp, int32
 size_t glam_render_bwd_workspace_bytes(const glam_anchors* anchors, const glam_views* views,
                                        int32_t n_parts, int64_t capacity, uint32_t flags);
 
-/* The whole backward, the adjoint of Eq. 1 -> projection -> Eq. 2 / Eq. 6 for the
+/* The whole backward of a mapping iteration (the gradient of Eq. 3 with respect to
+   the anchors and MLPs, Sec. III-A, III-B), the adjoint of Eq. 1 -> projection ->
+   Eq. 2 / Eq. 6 for the
    image gradient dimage (the loss gradient of glam_loss, or any other): composite
    adjoint (g2d), projection adjoint (dgauss), then in anchor mode the decode adjoint
    (dfeat, doffs, dlog_scale, dmlp), each overwritten.  flags: those of the forward calls
@@ -425,8 +437,9 @@ typedef struct {
 
 #define GLAM_ADAM_MAX_GROUPS 16
 
-/* The mapping iteration's optimiser step (the update that follows the backward):
-   Adam (Kingma & Ba) over all groups in one launch, step t >= 1 (bias corrections
+/* The mapping iteration's optimiser step (the update that follows the backward; the
+   Gaussian optimisation of Sec. III-B minimises Eq. 3, with Adam as in the 3DGS and
+   Scaffold-GS lineage): Adam (Kingma & Ba) over all groups in one launch, step t >= 1 (bias corrections
    1 - beta^t), per element
      m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
      param -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
@@ -435,7 +448,8 @@ typedef struct {
 glam_status glam_adam_step(const glam_adam_group* groups, int32_t n_groups, int32_t step,
                            float beta1, float beta2, float eps, hipStream_t stream);
 
-/* Keyframe sampler of a mapping iteration: count keyframe indices drawn from n_keyframes
+/* Keyframe sampler of a mapping iteration (Sec. IV-B: the k most recent keyframes with
+   probability p, the older ones otherwise): count keyframe indices drawn from n_keyframes
    (0 = oldest): with probability p_recent uniformly among the k_recent most recent,
    otherwise uniformly among the older ones (all keyframes are recent when n_keyframes
    <= k_recent).  Draws come from Philox4x32-10 (Salmon et al., SC 2011) keyed by seed,
@@ -456,7 +470,8 @@ typedef struct {
   float t_new[3];
 } glam_keyframe_fix;
 
-/* Eq. 7: each corrected keyframe i moves the anchors of its view frustum by
+/* Eq. 7 (loop closures, Sec. III-E): each corrected keyframe i moves the anchors of its
+   view frustum by
    dT_i = T_new,i^-1 T_old,i (T = world->camera), so they keep their coordinates in the
    keyframe's camera frame.  An anchor lies in the frustum when its depth in the old
    camera frame is in [near, far] and it projects inside the image; an anchor in several
@@ -471,7 +486,8 @@ glam_status glam_deform_anchors(float* pos, float* offs, int32_t A, int32_t K,
 
 /* --- flow densification ------------------------------------------------------------ */
 
-/* Eq. 5: filters N correspondences x1 <-> x2 between two keyframes with known cameras by
+/* Eq. 5 (flow densification, Sec. III-C): filters N correspondences x1 <-> x2 between
+   two keyframes with known cameras by
    the epipolar residual |x2^T F x1| < tau (x homogeneous pixel coordinates [u, v, 1]) and
    triangulates the retained ones.  F = [e2]x P2 P1^+ with P = K [R | t], e2 = P2 C1 (C1
    the first camera's centre) and P1^+ the pseudo-inverse of P1, scaled to unit Frobenius
@@ -492,7 +508,7 @@ glam_status glam_epipolar_triangulate(const glam_camera* cam1, const glam_camera
    range). */
 size_t glam_voxelize_workspace_bytes(int64_t n_points);
 
-/* Eq. 4: the fused point cloud (tracked points and triangulated flow points, Sec. III-A)
+/* Eq. 4 (Sec. III-B): the fused point cloud (tracked points and triangulated flow points)
    snapped to the voxel grid of size eps, keeping unique voxels, and of those the ones
    not already anchors (the incremental growth of the anchor set).  Per point and axis
    k = round(p / eps), the FP32 quotient rounded to the nearest integer with ties to
@@ -520,7 +536,7 @@ glam_status glam_voxelize(const float* points, int64_t n_points, float eps,
                           int64_t* counts, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 
-/* The bookkeeping of anchor growth (Sec. III-A): anchors are stored grouped by
+/* The bookkeeping of anchor growth (Sec. III-B, Eq. 4): anchors are stored grouped by
    partition (Eq. 6), so the anchors a keyframe adds are inserted at the end of its
    partition's range in every per-anchor array (and in the optimiser's moments), and the
    later partitions' ranges shift by n_new.  Copies rows rows of n_old * width floats

@@ -1,6 +1,6 @@
 // Tile binning and depth sort.
 //
-//  1. scan_reduce      per 2048 view-Gaussians: sum of tile counts, max depth bits
+//  1. scan_reduce      per 1024 view-Gaussians: sum of tile counts, max depth bits
 //  2. scan_plan        one block: exclusive scan of the block sums, pair count P,
 //                      capacity check, lossless key width (tile bits + depth bits) and
 //                      the number of 8-bit radix passes
@@ -10,6 +10,8 @@
 //                      histogram per block, per-digit scan across blocks, downsweep
 //                      scatter with a stable in-block rank from wave ballots
 //  5. ranges           [start, end) of every tile (cleared by the plan kernel)
+//  6. order            the compositing work order, longest ranges first (one workgroup
+//                      when the tiles are few)
 //
 // Every kernel reads P and the key layout from the device-side plan, so the whole
 // sequence runs without a host round trip (and can be captured in a graph).  Passes
@@ -21,7 +23,7 @@ namespace glam {
 
 namespace {
 
-constexpr int kScanThreads = 256, kScanItems = 8, kScanBlock = kScanThreads * kScanItems;
+constexpr int kScanThreads = 256, kScanItems = 4, kScanBlock = kScanThreads * kScanItems;
 constexpr int kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
 constexpr int kMaxSortBlocks = 4096;
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
   }
 }
 
-// Pairs of every view-Gaussian.  A workgroup takes the pairs of 2048 consecutive
+// Pairs of every view-Gaussian.  A workgroup takes the pairs of 1024 consecutive
 // view-Gaussians: it stages their tile boxes in LDS with the exclusive prefix of their
 // pair counts (the first-level scan redone in LDS), then each thread emits pairs
 // k = t, t + 256, ... of the workgroup's range, finding its Gaussian by binary search
@@ -497,6 +499,31 @@ __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t* ranges
   }
 }
 
+// Up to kLptOneBlock tiles: the whole work order in one workgroup (class counts and
+// slots in LDS), in one launch.
+constexpr int kLptOneBlock = 16384;
+__global__ void __launch_bounds__(1024) lpt_one_block_kernel(const uint32_t* ranges, long long n_tiles, int long_log2,
+                                                             uint32_t* order, int32_t* status) {
+  __shared__ uint32_t h[kLptBuckets], base[kLptBuckets];
+  if (threadIdx.x < kLptBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (long long t = threadIdx.x; t < n_tiles; t += 1024) atomicAdd(&h[lpt_bucket(ranges, t)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kLptBuckets; ++b) {
+      base[b] = run;
+      run += h[b];
+      if (b == kLptBuckets - 1 - long_log2) status[7] = (int32_t)run;
+    }
+  }
+  __syncthreads();
+  for (long long t = threadIdx.x; t < n_tiles; t += 1024) {
+    const uint32_t pos = atomicAdd(&base[lpt_bucket(ranges, t)], 1u);
+    if (pos < (uint64_t)n_tiles) order[pos] = (uint32_t)t;
+  }
+}
+
 __global__ void ranges_mark_kernel(const Plan* plan, const uint64_t* keys, uint32_t* ranges, long long n_tiles) {
   const Plan pl = *plan;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -548,11 +575,16 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
   if (bins.capacity > 0)
     hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,
                        bins.keys, bins.ranges, (long long)v.n_tiles);
-  const unsigned tb = (unsigned)((v.n_tiles + 255) / 256);
-  hipLaunchKernelGGL(lpt_count_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt);
   const int long_log2 = bins.tuning.long_log2 > 0 ? bins.tuning.long_log2 : kDefaultLongLog2;
-  hipLaunchKernelGGL(lpt_scatter_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt,
-                     long_log2, bins.order, bins.status);
+  if (v.n_tiles <= kLptOneBlock) {
+    hipLaunchKernelGGL(lpt_one_block_kernel, dim3(1), dim3(1024), 0, s, bins.ranges, (long long)v.n_tiles, long_log2,
+                       bins.order, bins.status);
+  } else {
+    const unsigned tb = (unsigned)((v.n_tiles + 255) / 256);
+    hipLaunchKernelGGL(lpt_count_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt);
+    hipLaunchKernelGGL(lpt_scatter_kernel, dim3(tb), dim3(256), 0, s, bins.ranges, (long long)v.n_tiles, lpt,
+                       long_log2, bins.order, bins.status);
+  }
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

@@ -330,24 +330,32 @@ constexpr int align4(int x) { return (x + 3) & ~3; }
 // four consecutive K-steps are four consecutive words, with transposed copies where a
 // product runs over the other index (W2^T, W1^T; Y and H are kept output-major).  Row
 // strides are multiples of four words whose 16 rows fall in distinct banks.
+// Feature widths that are not a multiple of 16 are zero-padded to one inside the
+// adjoint (FP columns): padded weight columns and inputs are zero, and their gradients
+// are dropped, so the packed layout in HBM keeps the width F.
 template <int F, int K, int ML>
 struct MCfg {
-  static constexpr int NIN = F + 4;
+  static constexpr int FP = (F + 15) / 16 * 16;  // feature columns inside the adjoint
+  static constexpr int NIN = FP + 4;             // layer-1 inputs inside the adjoint
+  static constexpr int NINP = F + 4;             // layer-1 inputs in the packed layout
   static constexpr int OUT = ML == 0 ? K : (ML == 1 ? 3 * K : 7 * K);
   static constexpr int OUTP = (OUT + 15) / 16 * 16;  // outputs padded to 16-row tiles
   static constexpr int OT = OUTP / 16;
-  static constexpr int KF = F / 4;             // feature columns per lane group in layer 1
+  static constexpr int KF = FP / 4;            // feature columns per lane group in layer 1
   static constexpr int NC1 = (NIN + 15) / 16;  // 16-column tiles of W1
   static constexpr int W1S = NIN, W2S = kHid + 4, W2TS = OUTP + 4, W1TS = kHid + 4;
   static constexpr int LW1 = 0, LB1 = kHid * W1S, LW2 = align4(LB1 + kHid), LB2 = LW2 + OUT * W2S;
   static constexpr int LW2T = align4(LB2 + OUT), LW1T = LW2T + kHid * W2TS;
-  static constexpr int PW = align4(LW1T + F * W1TS);
-  static constexpr int PM = kHid * NIN + kHid + OUT * kHid + OUT;  // packed parameters
+  static constexpr int PW = align4(LW1T + FP * W1TS);
+  static constexpr int PM = kHid * NINP + kHid + OUT * kHid + OUT;  // packed parameters
   static constexpr int ZS = NIN, YTS = 20, HTS = 20;
   // per wave: Z [16][NIN] anchor-major; Y^T [OUTP][20] and H^T [32][20] output-major
   static constexpr int WAVE_WORDS = align4(16 * ZS + OUTP * YTS + kHid * HTS + 16);
   static constexpr int SMEM = PW + kBwdWaves * WAVE_WORDS;
-  static_assert(NIN % 4 == 0 && F % 16 == 0, "layout");
+  static_assert(NIN % 4 == 0 && FP % 16 == 0 && F % 4 == 0, "layout");
+  // internal layer-1 column of packed column c, and back (-1: a padding column)
+  static constexpr __host__ __device__ int col_in(int c) { return c < F ? c : c + (FP - F); }
+  static constexpr __host__ __device__ int col_packed(int c) { return c < F ? c : (c < FP ? -1 : c - (FP - F)); }
 };
 
 template <int F, int K>
@@ -391,19 +399,24 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
     const float* pm = mlp + (size_t)lead.cam.partition * O.total + O.w1[ML];
     for (int i = t; i < C::PM; i += 64 * kBwdWaves) {
       const float v = pm[i];
-      if (i < kHid * C::NIN) {
-        const int h = i / C::NIN, c = i % C::NIN;
-        s_p[C::LW1 + h * C::W1S + c] = v;
+      if (i < kHid * C::NINP) {
+        const int h = i / C::NINP, c = i % C::NINP;
+        s_p[C::LW1 + h * C::W1S + C::col_in(c)] = v;
         if (c < F) s_p[C::LW1T + c * C::W1TS + h] = v;
-      } else if (i < kHid * C::NIN + kHid) {
-        s_p[C::LB1 + (i - kHid * C::NIN)] = v;
-      } else if (i < kHid * C::NIN + kHid + OUT * kHid) {
-        const int j = i - kHid * C::NIN - kHid, o = j / kHid, h = j % kHid;
+      } else if (i < kHid * C::NINP + kHid) {
+        s_p[C::LB1 + (i - kHid * C::NINP)] = v;
+      } else if (i < kHid * C::NINP + kHid + OUT * kHid) {
+        const int j = i - kHid * C::NINP - kHid, o = j / kHid, h = j % kHid;
         s_p[C::LW2 + o * C::W2S + h] = v;
         s_p[C::LW2T + h * C::W2TS + o] = v;
       } else {
-        s_p[C::LB2 + (i - kHid * C::NIN - kHid - OUT * kHid)] = v;
+        s_p[C::LB2 + (i - kHid * C::NINP - kHid - OUT * kHid)] = v;
       }
+    }
+    if (C::FP > F) {  // padding columns of W1 and rows of W1^T
+      for (int i = t; i < kHid * (C::FP - F); i += 64 * kBwdWaves)
+        s_p[C::LW1 + (i / (C::FP - F)) * C::W1S + F + i % (C::FP - F)] = 0.f;
+      for (int i = t; i < (C::FP - F) * C::W1TS; i += 64 * kBwdWaves) s_p[C::LW1T + F * C::W1TS + i] = 0.f;
     }
     for (int i = t; i < kHid * (C::OUTP - OUT); i += 64 * kBwdWaves)
       s_p[C::LW2T + (i / (C::OUTP - OUT)) * C::W2TS + OUT + i % (C::OUTP - OUT)] = 0.f;
@@ -445,6 +458,8 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         const int idx = l + 64 * k;
         s_z[(idx / F) * C::ZS + idx % F] = fv[k];
       }
+      if (C::FP > F)  // zero padding features
+        for (int i = l; i < 16 * (C::FP - F); i += 64) s_z[(i / (C::FP - F)) * C::ZS + F + i % (C::FP - F)] = 0.f;
     }
     float apos[3] = {0.f, 0.f, 0.f};
     if (l < 16 && a0 + l < A)
@@ -509,17 +524,17 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
           const float inv = 1.f / delta;
           for (int i = 0; i < 3; ++i) d[i] *= inv;
         }
-        s_z[l * C::ZS + F + 0] = d[0];
-        s_z[l * C::ZS + F + 1] = d[1];
-        s_z[l * C::ZS + F + 2] = d[2];
-        s_z[l * C::ZS + F + 3] = delta;
+        s_z[l * C::ZS + C::FP + 0] = d[0];
+        s_z[l * C::ZS + C::FP + 1] = d[1];
+        s_z[l * C::ZS + C::FP + 2] = d[2];
+        s_z[l * C::ZS + C::FP + 3] = delta;
       }
       wave_sync();
-      // layer 1 completed with the d, delta columns (lane group g: column F + g)
+      // layer 1 completed with the d, delta columns (lane group g: column FP + g)
       f4 H[2];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        f4 acc = mfma(W1[(mt * 16 + li) * C::W1S + F + lg], s_z[li * C::ZS + F + lg], PF[mt]);
+        f4 acc = mfma(W1[(mt * 16 + li) * C::W1S + C::FP + lg], s_z[li * C::ZS + C::FP + lg], PF[mt]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = fmaxf(acc[r] + s_p[C::LB1 + mt * 16 + 4 * lg + r], 0.f);
         H[mt] = acc;
@@ -655,7 +670,7 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
       wave_sync();
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        constexpr int ct = F / 16;
+        constexpr int ct = C::FP / 16;
         const int col = ct * 16 + li;
         const float* zc = s_z + 4 * lg * C::ZS + col;
         const float4 b = col < C::NIN ? make_float4(zc[0], zc[C::ZS], zc[2 * C::ZS], zc[3 * C::ZS])
@@ -675,7 +690,7 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
     for (int mt = 0; mt < 2; ++mt) {
       const float4 a = lds4(s_ht + (mt * 16 + li) * C::HTS + 4 * lg);
 #pragma unroll
-      for (int ct = 0; ct < F / 16; ++ct) {
+      for (int ct = 0; ct < C::FP / 16; ++ct) {
         const float* zc = s_z + 4 * lg * C::ZS + ct * 16 + li;
         dW1[mt * C::NC1 + ct] =
             mfma4(a, make_float4(zc[0], zc[C::ZS], zc[2 * C::ZS], zc[3 * C::ZS]), dW1[mt * C::NC1 + ct]);
@@ -689,9 +704,9 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         db1 += (h4.x + h4.y) + (h4.z + h4.w);
       }
     }
-    f4 dZ[F / 16];
+    f4 dZ[C::FP / 16];
 #pragma unroll
-    for (int ft = 0; ft < F / 16; ++ft) {
+    for (int ft = 0; ft < C::FP / 16; ++ft) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
       const float* wr = W1T + (ft * 16 + li) * C::W1TS + 4 * lg;
 #pragma unroll
@@ -700,11 +715,11 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
     }
     // this MLP's share of the anchor gradients (all views summed)
 #pragma unroll
-    for (int ft = 0; ft < F / 16; ++ft)
+    for (int ft = 0; ft < C::FP / 16; ++ft)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = a0 + li;
-        if (a < A) dfeat_part[(size_t)(lead.anchor_begin + a) * F + ft * 16 + 4 * lg + r] = dZ[ft][r];
+        const int a = a0 + li, f = ft * 16 + 4 * lg + r;
+        if (a < A && f < F) dfeat_part[(size_t)(lead.anchor_begin + a) * F + f] = dZ[ft][r];
       }
     if (ML != 1 && l < 16 && a0 + l < A) dls_part[lead.anchor_begin + a0 + l] = s_ds[l];
     if (ML == 0)
@@ -723,7 +738,7 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   float* red = s_p;  // packed offsets relative to this MLP's first parameter
   for (int i = t; i < C::PM; i += 64 * kBwdWaves) red[i] = 0.f;
   __syncthreads();
-  constexpr int RW2 = kHid * C::NIN + kHid, RB2 = RW2 + OUT * kHid, RB1 = kHid * C::NIN;
+  constexpr int RW2 = kHid * C::NINP + kHid, RB2 = RW2 + OUT * kHid, RB1 = kHid * C::NINP;
   // the waves add their shares one after another (every address takes one add per wave),
   // so the sums are formed in wave order and the gradients are reproducible
   for (int ww = 0; ww < kBwdWaves; ++ww) {
@@ -748,8 +763,8 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
         for (int ct = 0; ct < C::NC1; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int h = mt * 16 + 4 * lg + r, col = ct * 16 + li;
-            if (col < C::NIN) red[h * C::NIN + col] += dW1[mt * C::NC1 + ct][r];
+            const int h = mt * 16 + 4 * lg + r, col = C::col_packed(ct * 16 + li);
+            if (col >= 0 && col < C::NINP) red[h * C::NINP + col] += dW1[mt * C::NC1 + ct][r];
           }
       if (l < kHid) red[RB1 + l] += db1;
     }
@@ -786,12 +801,11 @@ decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
 
 // dmlp[m] = sum of partition m's workgroup partials (plane 1 only holds covariance
 // parameters).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
-__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* partial, BwdGrid grid, int P, int cov0,
-                                                              int n_units, float* dmlp) {
+__device__ void mlp_grad_reduce(const float* partial, const BwdGrid& grid, int P, int cov0, int n_units,
+                                float* dmlp, int bx, int slot) {
   __shared__ float s[16][17];
   const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
-  const int i = blockIdx.x * 16 + c;
-  const int slot = blockIdx.y;  // index into grid (partitions with views)
+  const int i = bx * 16 + c;  // slot: index into grid (partitions with views)
   float acc = 0.f;
   if (i < P) {
     for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16) acc += partial[(size_t)b * P + i];
@@ -818,10 +832,9 @@ struct Covered {
 // dfeat = sum of the three MLPs' parts, dlog_scale = mean part + scale part; anchors of
 // partitions without views get zero gradients (offsets included).
 template <int F, int K>
-__global__ void __launch_bounds__(256) anchor_grad_combine_kernel(const float* dfeat_part, const float* dls_part,
-                                                                  int A, Covered cov, float* dfeat, float* doffs,
-                                                                  float* dls) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void anchor_grad_combine(const float* dfeat_part, const float* dls_part, int A, const Covered& cov,
+                                    float* dfeat, float* doffs, float* dls, long long block) {
+  const long long i = block * blockDim.x + threadIdx.x;
   const long long AF = (long long)A * F;
   if (i >= AF) return;
   const int a = (int)(i / F);
@@ -837,6 +850,21 @@ __global__ void __launch_bounds__(256) anchor_grad_combine_kernel(const float* d
     if (!in)
       for (int k = 0; k < 3 * K; ++k) doffs[(size_t)(k / K) * A * K + (size_t)a * K + k % K] = 0.f;
   }
+}
+
+// The two reductions after the decode adjoint in one launch: blocks [0, n_red) sum the
+// weight-gradient partials (16 parameters x one partition each), the rest combine the
+// anchor gradients.
+template <int F, int K>
+__global__ void __launch_bounds__(256) decode_bwd_finish_kernel(const float* partial, BwdGrid grid, int P, int cov0,
+                                                                int n_units, float* dmlp, int red_x, int n_red,
+                                                                const float* dfeat_part, const float* dls_part, int A,
+                                                                Covered cov, float* dfeat, float* doffs, float* dls) {
+  const int b = (int)blockIdx.x;
+  if (b < n_red)
+    mlp_grad_reduce(partial, grid, P, cov0, n_units, dmlp, b % red_x, b / red_x);
+  else
+    anchor_grad_combine<F, K>(dfeat_part, dls_part, A, cov, dfeat, doffs, dls, (long long)(b - n_red));
 }
 
 __global__ void zero_f32_kernel(float* p, long long n) {
@@ -943,45 +971,47 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
   float* partial = reinterpret_cast<float*>(w + W.partial);
   float* dfp = reinterpret_cast<float*>(w + W.dfeat);
   float* dlp = reinterpret_cast<float*>(w + W.dls);
-  // partitions without views get zero gradients
-  const long long nm = (long long)n_parts * P;
-  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, dmlp, nm);
+  // partitions without views get zero gradients (the views' partitions are distinct runs,
+  // so every partition has one when there are as many runs as partitions)
+  if (g.n_parts < n_parts) {
+    const long long nm = (long long)n_parts * P;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, dmlp, nm);
+  }
   if (units > 0) {
     const size_t sm = sizeof(float) * bwd_smem_words<F, K>();
     if (!set_smem_limit((const void*)decode_bwd_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
     hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(units, 4), dim3(64 * kBwdWaves), sm, s, a, mlp, v.dev,
                        sig ? 1 : 0, dg, g, doffs, dfp, dlp, partial);
-    // the reduction writes dmlp[partition of slot k]: pass partitions in place of leaders
-    BwdGrid r = g;
-    for (int k = 0; k < g.n_parts; ++k) r.leader[k] = v.host[g.leader[k]].cam.partition;
-    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((P + 15) / 16, g.n_parts), dim3(256), 0, s, partial, r, P,
-                       mlp_offsets(F, K).w1[2], units, dmlp);
   }
-  if (a.A > 0) {
-    Covered cov;
-    cov.n = 0;
-    for (int k = 0; k < g.n_parts; ++k) {
-      const glam_view_info& vi = v.host[g.leader[k]];
-      if (vi.anchor_count == 0) continue;
-      int pos = cov.n++;
-      while (pos > 0 && cov.begin[pos - 1] > vi.anchor_begin) {
-        cov.begin[pos] = cov.begin[pos - 1];
-        cov.end[pos] = cov.end[pos - 1];
-        --pos;
-      }
-      cov.begin[pos] = vi.anchor_begin;
-      cov.end[pos] = vi.anchor_begin + vi.anchor_count;
+  // the reduction writes dmlp[partition of slot k]: pass partitions in place of leaders
+  BwdGrid r = g;
+  for (int k = 0; k < g.n_parts; ++k) r.leader[k] = v.host[g.leader[k]].cam.partition;
+  const int red_x = (P + 15) / 16, n_red = units > 0 ? red_x * g.n_parts : 0;
+  Covered cov;
+  cov.n = 0;
+  for (int k = 0; k < g.n_parts; ++k) {
+    const glam_view_info& vi = v.host[g.leader[k]];
+    if (vi.anchor_count == 0) continue;
+    int pos = cov.n++;
+    while (pos > 0 && cov.begin[pos - 1] > vi.anchor_begin) {
+      cov.begin[pos] = cov.begin[pos - 1];
+      cov.end[pos] = cov.end[pos - 1];
+      --pos;
     }
-    const long long AF = (long long)a.A * F;
-    hipLaunchKernelGGL((anchor_grad_combine_kernel<F, K>), dim3((unsigned)((AF + 255) / 256)), dim3(256), 0, s, dfp,
-                       dlp, a.A, cov, dfeat, doffs, dls);
+    cov.begin[pos] = vi.anchor_begin;
+    cov.end[pos] = vi.anchor_begin + vi.anchor_count;
   }
+  const long long AF = (long long)a.A * F;
+  const long long n_comb = a.A > 0 ? (AF + 255) / 256 : 0;
+  if (n_red + n_comb > 0)
+    hipLaunchKernelGGL((decode_bwd_finish_kernel<F, K>), dim3((unsigned)(n_red + n_comb)), dim3(256), 0, s, partial, r,
+                       P, mlp_offsets(F, K).w1[2], units, dmlp, red_x, n_red, dfp, dlp, a.A, cov, dfeat, doffs, dls);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
 }  // namespace
 
-#define GLAM_DECODE_CASES(X) X(32, 10) X(16, 4)
+#define GLAM_DECODE_CASES(X) X(32, 10) X(16, 4) X(8, 10) X(64, 10)
 
 glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_views& v, bool sig, bool sigma3,
                           const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {

@@ -14,7 +14,8 @@
 //      dL/dC, written once.
 // Row and column sums slide along short register-held runs (add the entering term,
 // subtract the leaving one).  Per-(tile, channel) sums of |x - y| and SSIM go to a
-// small workspace; a last kernel reduces each view's sums in double precision.
+// small workspace; a last kernel reduces each view's sums in double precision (one
+// workgroup for all views when they are few, which also adds up the step's total).
 // Nothing but the image, the target and dL/dC touches HBM.
 #include <mutex>
 
@@ -269,12 +270,13 @@ __global__ void __launch_bounds__(kThreads) loss_kernel(const glam_view_info* vi
   }
 }
 
-__global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* views, int max_t32,
-                                                          const float* partial, float w_ssim, float* loss) {
-  __shared__ double s_a[256], s_b[256];
-  const glam_view_info& vw = views[blockIdx.x];
+// View v's loss from its per-(tile, channel) sums, in double precision and a fixed
+// order (thread k adds k, k + 256, ...; then a tree).  Every thread of the workgroup
+// calls it.
+__device__ void reduce_view(const glam_view_info& vw, int v, int max_t32, const float* partial, float w_ssim,
+                            float* loss, double* s_a, double* s_b) {
   const int n = 3 * ((vw.cam.width + kT - 1) / kT) * ((vw.cam.height + kT - 1) / kT);
-  const float* pv = partial + 2 * 3 * (long long)blockIdx.x * max_t32;
+  const float* pv = partial + 2 * 3 * (long long)v * max_t32;
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < n; k += 256) {
     a += pv[2 * k];
@@ -291,7 +293,30 @@ __global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* 
     const double cnt = 3.0 * (double)vw.cam.width * (double)vw.cam.height;
     double L = s_a[0] / cnt;
     if (w_ssim != 0.f) L += (double)w_ssim * (1.0 - s_b[0] / cnt);
-    loss[blockIdx.x] = (float)L;
+    loss[v] = (float)L;
+  }
+  __syncthreads();  // s_a and s_b are reused
+}
+
+// One workgroup per view.
+__global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* views, int max_t32,
+                                                          const float* partial, float w_ssim, float* loss) {
+  __shared__ double s_a[256], s_b[256];
+  reduce_view(views[blockIdx.x], blockIdx.x, max_t32, partial, w_ssim, loss, s_a, s_b);
+}
+
+// A few views: one workgroup reduces them in view order and then adds their losses
+// (the step's total), in one launch.
+constexpr int kOneBlockViews = 64;
+__global__ void __launch_bounds__(256) loss_reduce_total_kernel(const glam_view_info* views, int n_views,
+                                                                int max_t32, const float* partial, float w_ssim,
+                                                                float* loss, float* total) {
+  __shared__ double s_a[256], s_b[256];
+  for (int v = 0; v < n_views; ++v) reduce_view(views[v], v, max_t32, partial, w_ssim, loss, s_a, s_b);
+  if (threadIdx.x == 0 && total) {
+    double acc = 0.0;
+    for (int v = 0; v < n_views; ++v) acc += (double)loss[v];
+    *total = (float)acc;
   }
 }
 
@@ -335,8 +360,13 @@ glam_status launch_loss(const glam_views& v, const float* image, const float* ta
   float* partial = static_cast<float*>(ws);
   hipLaunchKernelGGL(loss_kernel, dim3((unsigned)mt, (unsigned)v.n, 3), dim3(kThreads), 0, s, v.dev, mt, image, target,
                      w_ssim, dimage, partial);
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, mt, partial, w_ssim, loss);
-  if (total) hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
+  if (v.n <= kOneBlockViews) {
+    hipLaunchKernelGGL(loss_reduce_total_kernel, dim3(1), dim3(256), 0, s, v.dev, v.n, mt, partial, w_ssim, loss,
+                       total);
+  } else {
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, mt, partial, w_ssim, loss);
+    if (total) hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
+  }
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

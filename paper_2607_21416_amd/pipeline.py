@@ -91,7 +91,7 @@ class Pipeline:
                  tile: int = TILE, tuning: dict | None = None, footprint: str = "opacity",
                  deterministic: bool = False, intermediates: bool = False):
         """tile: binning tile edge (8, 16 or 32); tuning: the compositing schedule
-        (long_log2, fwd_blocks_per_cu, bwd_blocks_per_cu; missing or 0 = default);
+        (long_log2, fwd/bwd_blocks_per_cu, fwd/bwd_group_waves; missing or 0 = default);
         footprint: "opacity" (the exact alpha >= 1/255 box) or "3sigma" (the lineage's
         tile-granular 3-sigma square); deterministic: reproducible gradients (no
         floating-point atomics in the compositing adjoint); intermediates: the backward

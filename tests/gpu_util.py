@@ -56,8 +56,8 @@ def check_pixels(img, T, n_contrib, ref, label, n_eval=None, mask_bits=AMB_STAGE
     return frac
 
 
-def run(scene, steps=1, tile=16, tuning=None):
-    pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning)
+def run(scene, steps=1, tile=16, tuning=None, **kw):
+    pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning, **kw)
     pipe.count_evaluations()
     pipe.fit_capacity()
     pipe.status.zero_()

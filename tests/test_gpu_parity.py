@@ -44,6 +44,16 @@ def anchor_small():
     return synth.anchor_scene(1012, [1500, 800], 2, W=200, H=120, fx=140.0, ssim_weight=0.2, bias_std=0.2)
 
 
+def anchor_feat8():
+    # the feature width the paper prints (F = 8), two partitions
+    return synth.anchor_scene(1016, [900, 500], 2, W=160, H=100, fx=110.0, F=8, ssim_weight=0.2, bias_std=0.2)
+
+
+def anchor_feat64():
+    # a wide feature vector (F = 64): layer 1 runs over 17 K-steps
+    return synth.anchor_scene(1017, [700, 400], 1, W=150, H=90, fx=100.0, F=64, ssim_weight=0.2, bias_std=0.2)
+
+
 def partition_without_anchors():
     # a partition whose only view has no anchors next to two populated ones
     return synth.anchor_scene(1013, [600, 0, 300], 1, W=96, H=64, fx=70.0, ssim_weight=0.2)
@@ -61,7 +71,7 @@ def partition_without_views():
 # full-size workloads: config 2 (20k anchors, one 1226x370 view) and config 3 (50k
 # anchors, four views, the benchmark's workload)
 SCENES = {"C1": lambda: synth.config("C1"), "plain_ragged": plain_ragged, "plain_dense": plain_dense,
-          "anchor_small": anchor_small,
+          "anchor_small": anchor_small, "anchor_feat8": anchor_feat8, "anchor_feat64": anchor_feat64,
           "empty_partition": partition_without_anchors, "viewless_partition": partition_without_views,
           "C2": lambda: synth.config("C2"),
           "C3": lambda: synth.config("C3")}

@@ -25,9 +25,12 @@ SCHEDULES = {
     "wide16": {"long_log2": 7, "fwd_group_waves": 16, "bwd_group_waves": 16},
     "wide8": {"long_log2": 8, "fwd_group_waves": 8, "fwd_blocks_per_cu": 1, "bwd_group_waves": 8,
               "bwd_blocks_per_cu": 2},
+    # forward and backward at different widths
+    "mixed": {"long_log2": 7, "fwd_group_waves": 16, "bwd_group_waves": 4},
 }
 CASES = ([(t, n, "narrow") for t in (8, 32) for n in SCENES] + [(16, n, "wide16") for n in SCENES]
-         + [(t, "plain_dense", "wide8") for t in (8, 32)])
+         + [(t, "plain_dense", "wide8") for t in (8, 32)]
+         + [(16, n, "mixed") for n in ("plain_dense", "anchor_small")])
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda p: f"tile{p[0]}-{p[1]}-{p[2]}")
