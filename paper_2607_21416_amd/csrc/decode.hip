@@ -442,38 +442,65 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   const size_t GK = (size_t)an.A * K;
   const int n_chunks = (A + 15) / 16;
   // each wave walks its chunks independently: no workgroup barrier until the end
-  for (int chunk = b_local * kBwdWaves + w; chunk < n_chunks; chunk += nb * kBwdWaves) {
+  // view-independent inputs of a chunk (features, anchor positions and, per Gaussian of
+  // this lane, the log-scale and offsets), loaded into registers one chunk ahead so
+  // that their latency hides behind the current chunk's work
+  struct ChunkIn {
+    float fv[16 * F / 64];
+    float apos[3];
+    float ls[3];
+    float off[3][3];
+  };
+  auto load_chunk = [&](int chunk, ChunkIn& in) {
     const int a0 = chunk * 16;
-    // view-independent inputs, loaded once per chunk: features into Z, anchor
-    // positions, and (per Gaussian of this lane) e^{s_a} and the offsets
-    {
-      float fv[16 * F / 64];
 #pragma unroll
-      for (int k = 0; k < 16 * F / 64; ++k) {
-        const int idx = l + 64 * k, ai = idx / F, a = a0 + ai;
-        fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
-      }
-#pragma unroll
-      for (int k = 0; k < 16 * F / 64; ++k) {
-        const int idx = l + 64 * k;
-        s_z[(idx / F) * C::ZS + idx % F] = fv[k];
-      }
-      if (C::FP > F)  // zero padding features
-        for (int i = l; i < 16 * (C::FP - F); i += 64) s_z[(i / (C::FP - F)) * C::ZS + F + i % (C::FP - F)] = 0.f;
+    for (int k = 0; k < 16 * F / 64; ++k) {
+      const int idx = l + 64 * k, ai = idx / F, a = a0 + ai;
+      in.fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
     }
-    float apos[3] = {0.f, 0.f, 0.f};
-    if (l < 16 && a0 + l < A)
-      for (int i = 0; i < 3; ++i) apos[i] = an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l];
-    float es[3] = {0.f, 0.f, 0.f}, off[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      in.apos[i] = l < 16 && a0 + l < A ? an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l] : 0.f;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int gi = l + 64 * q, ai = gi / K, a = a0 + ai;
-      if (ML != 1 && gi < 16 * K && a < A) {
-        const int ga = lead.anchor_begin + a;
-        es[q] = expf(an.log_scale[ga]);
-        if (ML == 0)
-          for (int i = 0; i < 3; ++i) off[q][i] = an.offs[i * GK + (size_t)ga * K + gi % K];
-      }
+      const bool ok = ML != 1 && gi < 16 * K && a < A;
+      const int ga = lead.anchor_begin + (ok ? a : 0);
+      in.ls[q] = ok ? an.log_scale[ga] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) in.off[q][i] = ok && ML == 0 ? an.offs[i * GK + (size_t)ga * K + gi % K] : 0.f;
+    }
+  };
+  // (wide features: no prefetch, the registers would spill)
+  constexpr bool kPrefetch = F <= 32;
+  const int chunk_step = nb * kBwdWaves;
+  ChunkIn nxt;
+  if (kPrefetch && b_local * kBwdWaves + w < n_chunks) load_chunk(b_local * kBwdWaves + w, nxt);
+  for (int chunk = b_local * kBwdWaves + w; chunk < n_chunks; chunk += chunk_step) {
+    const int a0 = chunk * 16;
+    ChunkIn cur;
+    if (kPrefetch) {
+      cur = nxt;
+      if (chunk + chunk_step < n_chunks) load_chunk(chunk + chunk_step, nxt);
+    } else {
+      load_chunk(chunk, cur);
+    }
+    // features into Z
+#pragma unroll
+    for (int k = 0; k < 16 * F / 64; ++k) {
+      const int idx = l + 64 * k;
+      s_z[(idx / F) * C::ZS + idx % F] = cur.fv[k];
+    }
+    if (C::FP > F)  // zero padding features
+      for (int i = l; i < 16 * (C::FP - F); i += 64) s_z[(i / (C::FP - F)) * C::ZS + F + i % (C::FP - F)] = 0.f;
+    float apos[3] = {cur.apos[0], cur.apos[1], cur.apos[2]};
+    float es[3], off[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int gi = l + 64 * q, a = a0 + gi / K;
+      es[q] = ML != 1 && gi < 16 * K && a < A ? expf(cur.ls[q]) : 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) off[q][i] = cur.off[q][i];
     }
     wave_sync();
     // the features' share of layer 1 (lane group g takes feature columns [g KF, g KF + KF))

@@ -554,7 +554,10 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
 // own lane and issues all their atomics with one instruction: the per-hit DPP folding
 // and its wait states are replaced by one LDS store per register.
 constexpr int kFlush = 4;         // hits staged per flush (9 kFlush lanes flush)
-constexpr int kStageWords = 192;  // x0, x1 and x2 (64 lanes each; only x2's first row is read)
+// x0, x1 and x2 (64 lanes each; only x2's first row is read), padded by four words so
+// that the flush's 16-byte reads of the kFlush slots spread over all 64 banks (three
+// passes per read instead of twelve)
+constexpr int kStageWords = 196;
 struct GradStage {
   float v[kFlush][kStageWords];
   uint32_t gid[kFlush];
