@@ -160,6 +160,27 @@ def test_project(case):
 
 def test_bin_sort_bit_exact(case):
     name, scene, pipe, h = case
+    check_bins(scene, pipe, h)
+
+
+def test_bin_sort_long_ranges():
+    # 40k wide Gaussians over 48x40 pixels: six of the nine 16x16 tiles hold 8,400-14,000
+    # pairs, each range spanning several of the sort's 2048-key blocks, the other three
+    # 5,000-6,500.  Scaling a scene about the camera leaves its image alone and changes the
+    # depth keys' width: 24 bits at depths 0.2-0.75, 27 bits at 20-100.
+    for seed, k in ((1018, 0.075), (1019, 10.0)):
+        s = synth.plain_scene(seed, 40000, 48, 40)
+        s["mean"] = (s["mean"] * k).astype(np.float32)
+        s["log_scale"] = (s["log_scale"] + np.log(k) + 0.8).astype(np.float32)
+        pipe = run(s)
+        h = host(pipe)
+        lens = check_bins(s, pipe, h)
+        print(f"seed {seed}: {len(lens)} tiles, ranges {sorted(lens.tolist())}, depth bits {h['dbits']}", flush=True)
+        assert (lens > 8192).sum() >= 2 and ((lens > 1023) & (lens <= 8192)).any()
+
+
+def check_bins(scene, pipe, h):
+    """The GPU's binning against the oracle's, bit for bit; returns the range lengths."""
     sls = view_slices(pipe)
     G = h["ntiles"].shape[0]
     prect = np.zeros((4, G), np.int32)
@@ -185,6 +206,7 @@ def test_bin_sort_bit_exact(case):
     order = pipe.order.cpu().numpy().astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(len(lens)))
     assert (lens[order[:n_long]] >= 1024).all() and (lens[order[n_long:]] < 1024).all()
+    return lens
 
 
 def test_render_fwd_stagewise(case):
