@@ -96,14 +96,6 @@ def split_views(scene):
     return out
 
 
-def one_view(scene, v):
-    """The single-view workload of view v of an anchor scene (the headline iteration):
-    the whole scene's anchors and MLP sets, one camera and its target."""
-    sub = dict(scene)
-    sub.update(cams=[scene["cams"][v]], targets=[scene["targets"][v]])
-    return sub
-
-
 def timed(torch, fn, iters, stream):
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -157,12 +149,12 @@ def make_step(torch, pipe, use_graph):
     return make_graph(torch, pipe.step, use_graph)
 
 
-def profiled_traffic(kernel, launch):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    the compositing source has changed since the counters were taken or they were taken
-    at another launch configuration (tile edge and schedule)."""
+def profiled_traffic(kernel, launch, name):
+    """HBM bytes per launch of `kernel` from the committed counter summary profiles/<name>,
+    or None when the compositing source has changed since the counters were taken or they
+    were taken at another launch configuration (tile edge and schedule)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_config3.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         rec = json.load(open(path))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
@@ -411,7 +403,7 @@ def run_workload(torch, scene, choice, args, dev, label):
                 evals_bwd=evals_bwd, evals_per_view=per_view, graph=graph, step=step)
 
 
-def dominant_roofline(w, choice, ceil):
+def dominant_roofline(w, choice, ceil, traffic_file):
     """The roofline object of the workload's dominant kernel (the slower compositing
     kernel), in the scope table's work units, with the FLOP convention and the measured
     ceiling beside it."""
@@ -427,7 +419,8 @@ def dominant_roofline(w, choice, ceil):
     measured_peak = ceil["fma_TFLOPs"] / 2 if ceil else None
     return {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_LANE_OPS, 2),
             "unit": "Tlane-op/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-            "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)}),
+            "traffic": profiled_traffic(dom, {"tile": choice["tile"], "schedule": tuning.schedule(choice)},
+                                        traffic_file),
             "work": f"{evals} Gaussian-pixel evaluations x {slots} FP32 VALU lane-op slots per launch "
                     f"(exp and reciprocal at a quarter of the VALU rate); peak = 256 CU x 4 SIMD x 16 lanes "
                     f"x 2.4 GHz",
@@ -449,6 +442,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched-vs-plain comparison")
     ap.add_argument("--headline-only", action="store_true",
                     help="the headline workload alone (no ceilings, four-view step, next rows, config 4, CPU)")
+    ap.add_argument("--four-view-only", action="store_true",
+                    help="config 3's four-view step alone (for profiling; prints its object, not the bench line)")
     ap.add_argument("--stage-iters", type=int, default=10)
     ap.add_argument("--config5", action="store_true",
                     help="also run config 5 (2 km path, 64 partitions x 8 views, mixed resolutions) once")
@@ -487,7 +482,22 @@ def main():
 
     log("bench: generating config 3 (50k anchors, 4 views 1226x370)")
     scene = synth.config("C3")
-    scene1 = one_view(scene, 0)
+    if args.four_view_only:
+        choice = choose(scene)
+        w4 = run_workload(torch, scene, choice, args, dev, "config 3, four views")
+        m = {"workload": "config 3: the four keyframe views in one batched step", "ms_per_step": round(w4["ms"], 4),
+             "tile": choice["tile"], "schedule": tuning.schedule(choice),
+             "stages_ms": {k: round(v, 4) for k, v in w4["st"].items()},
+             "roofline": dominant_roofline(w4, choice, None, "traffic_config3.json")}
+        if args.copy_mib > 0:
+            src = torch.ones(args.copy_mib * 262144, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"m1_prime": m}), flush=True)
+        return
+    scene1 = synth.one_view(scene, 0)
     choice1 = choose(scene1)
     sc1 = tuning.schedule(choice1)
     log("bench: headline (one view): tile %d, long tiles >= 2^%d, grids %dx%d / %dx%d (waves x workgroups per CU, "
@@ -497,7 +507,7 @@ def main():
     w1 = run_workload(torch, scene1, choice1, args, dev, "config 3, view 0")
     ms = w1["ms"]
     value = 1000.0 / ms
-    roofline = dominant_roofline(w1, choice1, ceil)
+    roofline = dominant_roofline(w1, choice1, ceil, "traffic_view0_config3.json")
     step_roofline = whole_step_roofline(w1["pipe"], ms, w1["need"], w1["evals_fwd"], w1["evals_bwd"], w1["st"])
     log(f"bench: M1 {value:.1f} iterations/s; dominant kernel {roofline['kernel']} at {roofline['frac']:.3f} of "
         f"its roofline; whole step {step_roofline['frac']:.3f}")
@@ -550,7 +560,7 @@ def main():
                        "view_iterations_per_s": round(n_views * 1000.0 / w4["ms"], 2),
                        "tile": choice["tile"], "schedule": tuning.schedule(choice), "tuning": choice["source"],
                        "stages_ms": {k: round(v, 4) for k, v in w4["st"].items()},
-                       "roofline": dominant_roofline(w4, choice, ceil),
+                       "roofline": dominant_roofline(w4, choice, ceil, "traffic_config3.json"),
                        "kernel_rooflines": kernel_rooflines(pipe, w4["st"], w4["need"], w4["evals_fwd"],
                                                             w4["evals_bwd"], ceil),
                        "step_roofline": whole_step_roofline(pipe, w4["ms"], w4["need"], w4["evals_fwd"],

@@ -24,7 +24,13 @@ namespace glam {
 namespace {
 
 constexpr int kScanThreads = 256, kScanItems = 4, kScanBlock = kScanThreads * kScanItems;
-constexpr int kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
+// Radix sort blocks of kSortThreads x items keys: 1024 keys (4 per thread) for up to
+// 2^20 pairs of capacity, where 2048-key blocks would leave most CUs with one block or
+// none and each block's ranking chain sets the pass time; 2048 keys above, where the
+// blocks fill the chip either way and fewer of them mean less counting and scanning.
+constexpr int kSortThreads = 256;
+constexpr long long kSmallSortCapacity = 1ll << 20;
+int sort_items(long long capacity) { return capacity <= kSmallSortCapacity ? 4 : 8; }
 constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
 constexpr int kMaxSortBlocks = 4096;
 constexpr uint32_t kDepthBase = 0x3E4CCCCDu;  // bit pattern of 0.2f: every visible depth is above it
@@ -44,7 +50,7 @@ constexpr int kLptBuckets = 32;
 
 struct Layout {
   size_t partial_sum, partial_max, plan, keys_alt, vals_alt, hist, digit_total, lpt, total;
-  int n_scan_blocks, n_sort_blocks;
+  int n_scan_blocks, n_sort_blocks, sort_items;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -53,7 +59,9 @@ Layout layout(long long n_gauss, long long capacity) {
   Layout L;
   L.n_scan_blocks = (int)((n_gauss + kScanBlock - 1) / kScanBlock);
   if (L.n_scan_blocks < 1) L.n_scan_blocks = 1;
-  long long tiles = (capacity + kSortTile - 1) / kSortTile;
+  L.sort_items = sort_items(capacity);
+  const long long sort_tile = (long long)kSortThreads * L.sort_items;
+  long long tiles = (capacity + sort_tile - 1) / sort_tile;
   L.n_sort_blocks = (int)(tiles < 1 ? 1 : (tiles > kMaxSortBlocks ? kMaxSortBlocks : tiles));
   size_t o = 0;
   L.partial_sum = o; o = align256(o + 4ull * L.n_scan_blocks);
@@ -124,8 +132,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t
 // Also clears the tile ranges and the longest-first counters for this call.
 __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const uint32_t* pmax, int nb,
                                                          long long capacity, long long n_tiles, int n_sort_blocks,
-                                                         Plan* plan, int32_t* status, uint32_t* ranges,
-                                                         uint32_t* lpt) {
+                                                         int sort_tile, Plan* plan, int32_t* status,
+                                                         uint32_t* ranges, uint32_t* lpt) {
   __shared__ unsigned long long s_part[1024];
   __shared__ uint32_t s_max[1024];
   const int t = threadIdx.x;
@@ -170,7 +178,7 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
     pl.dbits = (P > 0 && maxbits > kDepthBase) ? (uint32_t)dbit_length(maxbits - kDepthBase) : 1u;
     pl.tbits = n_tiles > 1 ? (uint32_t)(64 - __clzll((unsigned long long)(n_tiles - 1))) : 0u;
     pl.npasses = Pc > 0 ? (pl.dbits + pl.tbits + kRadixBits - 1) / kRadixBits : 0u;
-    pl.n_sort_tiles = (uint32_t)((Pc + kSortTile - 1) / kSortTile);
+    pl.n_sort_tiles = (uint32_t)((Pc + sort_tile - 1) / sort_tile);
     pl.tiles_per_block = (pl.n_sort_tiles + n_sort_blocks - 1) / n_sort_blocks;
     pl.active_blocks = pl.tiles_per_block ? (pl.n_sort_tiles + pl.tiles_per_block - 1) / pl.tiles_per_block : 0u;
     status[4] = (int32_t)pl.dbits;
@@ -298,6 +306,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return peers;
 }
 
+template <int kSortItems>
 __global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan* plan, int pass, int n_blocks,
                                                                      const uint64_t* keys_out,
                                                                      const uint64_t* keys_alt, uint32_t* hist) {
@@ -307,6 +316,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan*
   s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t* src = ((pass & 1) == 0) == ((pl.npasses & 1u) == 0) ? keys_out : keys_alt;
+  constexpr int kSortTile = kSortThreads * kSortItems;
   const int shift = pass * kRadixBits;
   const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
   const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
@@ -351,6 +361,7 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(const Plan* plan, int p
   if (threadIdx.x == 255) digit_total[blockIdx.x] = incl;
 }
 
+template <int kSortItems>
 __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Plan* plan, int pass, int n_blocks,
                                                                        const uint32_t* hist,
                                                                        const uint32_t* digit_total,
@@ -358,6 +369,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
                                                                        uint64_t* keys_alt, uint32_t* vals_alt) {
   const Plan pl = *plan;
   if ((uint32_t)pass >= pl.npasses || blockIdx.x >= pl.active_blocks) return;
+  constexpr int kSortTile = kSortThreads * kSortItems;
   // the per-(item round, wave, digit) counts, and once ranked the tile's keys and values
   // in digit order
   __shared__ __align__(16) uint32_t s_lds[kSortItems * (kSortThreads / 64) * kRadix];
@@ -557,8 +569,8 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                      n, psum, pmax);
   uint32_t* lpt = reinterpret_cast<uint32_t*>(w + L.lpt);
   hipLaunchKernelGGL(scan_plan_kernel, dim3(1), dim3(1024), 0, s, psum, pmax, L.n_scan_blocks,
-                     (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, plan, bins.status,
-                     bins.ranges, lpt);
+                     (long long)bins.capacity, (long long)v.n_tiles, L.n_sort_blocks, kSortThreads * L.sort_items,
+                     plan, bins.status, bins.ranges, lpt);
   hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
                      n, v.dev, v.n, tile_log2(v.tile_w), psum, plan, bins.keys, bins.vals, keys_alt, vals_alt,
                      bins.pair_begin);
@@ -566,11 +578,19 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
   const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
   const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;
   for (int p = 0; p < max_passes; ++p) {
-    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                       L.n_sort_blocks, bins.keys, keys_alt, hist);
+    if (L.sort_items == 4)
+      hipLaunchKernelGGL(radix_upsweep_kernel<4>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                         L.n_sort_blocks, bins.keys, keys_alt, hist);
+    else
+      hipLaunchKernelGGL(radix_upsweep_kernel<8>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                         L.n_sort_blocks, bins.keys, keys_alt, hist);
     hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, plan, p, L.n_sort_blocks, hist, dtot);
-    hipLaunchKernelGGL(radix_downsweep_kernel, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                       L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
+    if (L.sort_items == 4)
+      hipLaunchKernelGGL(radix_downsweep_kernel<4>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                         L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
+    else
+      hipLaunchKernelGGL(radix_downsweep_kernel<8>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
+                         L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
   }
   if (bins.capacity > 0)
     hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,

@@ -203,6 +203,14 @@ def config(name: str) -> dict:
     raise KeyError(name)
 
 
+def one_view(scene: dict, v: int) -> dict:
+    """The single-view workload of view v of an anchor scene (one mapping iteration on one
+    keyframe): the whole scene's anchors and MLP sets, that view's camera and target."""
+    sub = dict(scene)
+    sub.update(cams=[scene["cams"][v]], targets=[scene["targets"][v]])
+    return sub
+
+
 def long_path_scene(seed: int = 1005, n_parts: int = 64, views_per_part: int = 8,
                     F: int = 32, K: int = 10, hidden: int = 32, with_targets: bool = True) -> dict:
     """2 km polyline of five 400 m straight segments with alternating 90-degree turns.

@@ -1,7 +1,9 @@
-"""The benchmark's own workload in the benchmark's own launch configuration: config 3
-(50k anchors x 10 offsets = 500k Gaussians, four 1226x370 views, L1 + 0.2 (1 - SSIM)) at
-the tuner's stored choice for it (32x32 tiles, long tiles >= 2^10, 5/4 workgroups per
-CU), the whole step replayed from a HIP graph as the benchmark times it.
+"""The benchmark's own workloads in the benchmark's own launch configurations: config 3
+(50k anchors x 10 offsets = 500k Gaussians, 1226x370, L1 + 0.2 (1 - SSIM)) as one
+mapping iteration on view 0 alone (the headline) and as the four views in one step, each
+at the tuner's stored choice for it (tile edge, long-tile threshold, workgroup widths and
+counts, printed by the test), the whole step replayed from a HIP graph as the benchmark
+times it.
 
 Against the oracle, at full size and on every output: the tile assignment, sort order,
 ranges and longest-first order bit for bit at that tile edge; every pixel, T and
@@ -25,13 +27,16 @@ from test_gpu_parity import g2d_gradients
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def bench_case():
-    scene = synth.config("C3")
+WORKLOADS = {"view0": lambda: synth.one_view(synth.config("C3"), 0), "four_views": lambda: synth.config("C3")}
+
+
+@pytest.fixture(scope="module", params=list(WORKLOADS))
+def bench_case(request):
+    scene = WORKLOADS[request.param]()
     choice = tuning.autotune(scene, device="cuda")  # the stored choice: nothing is measured
     assert choice["source"] == "stored"
     tile = choice["tile"]
-    print(f"config 3 at tile {tile}, schedule {tuning.schedule(choice)}", flush=True)
+    print(f"config 3 ({request.param}) at tile {tile}, schedule {tuning.schedule(choice)}", flush=True)
     pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning.schedule(choice))
     pipe.fit_capacity()
     pipe.status.zero_()
@@ -73,7 +78,7 @@ def test_sort_bit_exact(bench_case):
     assert np.array_equal(nt, h["ntiles"])
     gb = [sl["g0"] for sl in sls] + [sls[-1]["g1"]]
     ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), gb, scene["cams"], (tile, tile))
-    assert h["P"] == ref["P"] > 10 ** 6
+    assert h["P"] == ref["P"] > 5 * 10 ** 5 * len(sls)
     assert np.array_equal(h["vals"], ref["vals"])
     assert np.array_equal((h["keys"] >> np.uint64(h["dbits"])).astype(np.int64), ref["tiles"].astype(np.int64))
     assert np.array_equal(h["ranges"], ref["ranges"])

@@ -19,6 +19,7 @@ import torch
 
 import oracle
 import synth
+from paper_2607_21416_amd.pipeline import Pipeline
 from gpu_util import (AMB_STAGE, AMB_VALUE, DECODE_GAMMA, GAMMA_E2E, U32, check_anchor_grads, check_dgauss,
                       check_e2e_pixels, check_pixels, decode_magnitude, e2e_grad_magnitude, gpu_splats, grad_close,
                       host, projection_bounds, run, stage_render, unpack_box, view_image, view_pixels, view_slices)
@@ -165,17 +166,27 @@ def test_bin_sort_bit_exact(case):
 
 def test_bin_sort_long_ranges():
     # 40k wide Gaussians over 48x40 pixels: six of the nine 16x16 tiles hold 8,400-14,000
-    # pairs, each range spanning several of the sort's 2048-key blocks, the other three
+    # pairs, each range spanning several of the sort's blocks, the other three
     # 5,000-6,500.  Scaling a scene about the camera leaves its image alone and changes the
-    # depth keys' width: 24 bits at depths 0.2-0.75, 27 bits at 20-100.
-    for seed, k in ((1018, 0.075), (1019, 10.0)):
+    # depth keys' width: 24 bits at depths 0.2-0.75, 27 bits at 20-100.  The sort takes
+    # 1024-key blocks up to 2^20 pairs of capacity and 2048-key blocks above: the last
+    # case sorts the same pairs in a buffer of 2^21.
+    for seed, k, capacity in ((1018, 0.075, None), (1019, 10.0, None), (1019, 10.0, 1 << 21)):
         s = synth.plain_scene(seed, 40000, 48, 40)
         s["mean"] = (s["mean"] * k).astype(np.float32)
         s["log_scale"] = (s["log_scale"] + np.log(k) + 0.8).astype(np.float32)
-        pipe = run(s)
+        if capacity is None:
+            pipe = run(s)
+        else:
+            pipe = Pipeline(s, device="cuda", capacity=capacity)
+            pipe.step()
+            torch.cuda.synchronize()
+            pipe.check_status()
+            assert pipe.capacity == capacity
         h = host(pipe)
         lens = check_bins(s, pipe, h)
-        print(f"seed {seed}: {len(lens)} tiles, ranges {sorted(lens.tolist())}, depth bits {h['dbits']}", flush=True)
+        print(f"seed {seed}, capacity {pipe.capacity}: {len(lens)} tiles, ranges {sorted(lens.tolist())}, "
+              f"depth bits {h['dbits']}", flush=True)
         assert (lens > 8192).sum() >= 2 and ((lens > 1023) & (lens <= 8192)).any()
 
 
@@ -339,7 +350,6 @@ def test_empty_and_overflow():
     assert np.all(h["dg"]["mean"] == 0)
     # pair capacity overflow is reported, not written past
     s = synth.config("C1")
-    from paper_2607_21416_amd.pipeline import Pipeline
     pipe = Pipeline(s, device="cuda", capacity=64)
     guard = pipe.keys.new_zeros(0)
     pipe.forward()
