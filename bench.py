@@ -492,7 +492,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ceil = None
-    if not args.headline_only:
+    if not (args.headline_only or args.four_view_only):
         log("bench: ceilings of this GPU (microbenchmarks, outside any timed region)")
         ceil = measure_ceilings()
         log("bench: ceilings " + ", ".join(f"{k} {v}" for k, v in ceil.items() if k != "published"))
