@@ -750,6 +750,28 @@ def main():
     })
     del pipe, w4
 
+    # a per-pixel loss: config 2 (20k anchors x 10 Gaussians, one 1226x370 view, L1), its
+    # step with the forward, the loss and the compositing adjoint in one pass against the
+    # same step through the three separate calls
+    log("bench: config 2 (L1 loss): fused forward + loss + adjoint against the separate calls")
+    s2 = synth.config("C2")
+    fused_ms = {}
+    for fuse in (True, False):
+        p2 = Pipeline(s2, device=dev, tuning=tuning.schedule(tuning.DEFAULT), fuse_l1=fuse)
+        p2.fit_capacity()
+        p2.status.zero_()
+        for _ in range(2):
+            p2.step()
+        f2step, f2g = make_step(torch, p2, True)
+        fused_ms[fuse] = timed(torch, f2step, max(5, args.steps), stream)
+        p2.check_status()
+        del f2g, p2
+    out["fused_l1"] = {"workload": "config 2: 20k anchors x 10 = 200k Gaussians, one 1226x370 view, L1 loss",
+                       "fused_ms": round(fused_ms[True], 4), "separate_ms": round(fused_ms[False], 4),
+                       "speedup": round(fused_ms[False] / fused_ms[True], 3),
+                       "iterations_per_s_fused": round(1000.0 / fused_ms[True], 1)}
+    log(f"bench: config 2 step {fused_ms[True]:.3f} ms fused, {fused_ms[False]:.3f} ms separate")
+
     evals4 = None
     if not args.no_batched:
         log("bench: config 4 (16 partitions x 4 views), batched vs plain")

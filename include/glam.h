@@ -369,6 +369,25 @@ glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins
                                const int32_t* n_contrib, const float* dimage, float* g2d,
                                hipStream_t stream);
 
+/* For a per-pixel loss (Eq. 3 with w_ssim = 0: L_v = mean |C - target| over the view's
+   pixels and channels), the forward of Eq. 1, that loss and the adjoint of Eq. 1 in one
+   pass over the tiles (Sec. III-A): each quadrant item is composited, its pixels take
+   dL/dC = sign(C - target) / (3 W H) from their own values, and the item is walked back
+   at once while its records are still cached, instead of glam_render_fwd, glam_loss and
+   glam_composite_bwd (an SSIM term needs the whole image before any dL/dC).  Writes
+   what those three write: image, T_final, n_contrib, dimage ([3][H][W] per view at
+   3 * pix_begin, device), loss[n_views] (device), total[0] = sum of loss[] in view order
+   if total is not NULL, and g2d [n_gauss][9] (zeroed first; FP32 atomics, as
+   glam_composite_bwd).  target: [3][H][W] per view.  The grid is bins.tuning's backward
+   schedule.  workspace: glam_render_fused_l1_workspace_bytes (one partial sum per 8x8
+   quadrant item). */
+size_t glam_render_fused_l1_workspace_bytes(const glam_views* views);
+glam_status glam_render_fused_l1(const glam_projected* proj, const glam_bins* bins,
+                                 const glam_views* views, const float* bg, const float* target,
+                                 float* image, float* T_final, int32_t* n_contrib, float* dimage,
+                                 float* loss, float* total, float* g2d, void* workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
+
 /* Adjoint of the projection of Sec. III-A (see glam_project): g2d -> dgauss (anchor
    mode: per view-Gaussian; plain mode:
    summed over views into the plain parameter gradients).  Overwrites dgauss. */

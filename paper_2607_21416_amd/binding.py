@@ -24,6 +24,7 @@ GLAM_QUEUE_WORDS = 1088
 
 EXPORTS = [
     "glam_status_string", "glam_mlp_param_count", "glam_views_build", "glam_bin_sort_workspace_bytes",
+    "glam_render_fused_l1_workspace_bytes", "glam_render_fused_l1",
     "glam_decode", "glam_project", "glam_bin_sort", "glam_render_fwd", "glam_loss_workspace_bytes", "glam_loss",
     "glam_composite_bwd", "glam_project_bwd", "glam_decode_bwd_workspace_bytes", "glam_decode_bwd",
     "glam_render_bwd", "glam_adam_step", "glam_sample_keyframes", "glam_deform_anchors",
@@ -132,6 +133,8 @@ def load():
         "glam_loss_workspace_bytes": (SZ, [P]),
         "glam_loss": (I32, [P, P, P, F32, P, P, P, P, SZ, P]),
         "glam_composite_bwd": (I32, [P, P, P, P, P, P, P, P, P]),
+        "glam_render_fused_l1_workspace_bytes": (SZ, [P]),
+        "glam_render_fused_l1": (I32, [P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "glam_project_bwd": (I32, [P, P, P, U32, P, P, P]),
         "glam_decode_bwd_workspace_bytes": (SZ, [P, P, I32]),
         "glam_decode_bwd": (I32, [P, P, I32, P, U32, P, P, P, P, P, P, SZ, P]),
@@ -244,6 +247,18 @@ def glam_composite_bwd(proj, bins, views, bg, T_final, n_contrib, dimage, g2d, s
     return _check("glam_composite_bwd",
                   load().glam_composite_bwd(ref(proj), ref(bins), ref(views), ref(bg), ref(T_final), ref(n_contrib),
                                             ref(dimage), ref(g2d), _stream(stream)))
+
+
+def glam_render_fused_l1_workspace_bytes(views):
+    return load().glam_render_fused_l1_workspace_bytes(ref(views))
+
+
+def glam_render_fused_l1(proj, bins, views, bg, target, image, T_final, n_contrib, dimage, loss, total, g2d, ws,
+                         ws_bytes, stream):
+    return _check("glam_render_fused_l1",
+                  load().glam_render_fused_l1(ref(proj), ref(bins), ref(views), ref(bg), ref(target), ref(image),
+                                              ref(T_final), ref(n_contrib), ref(dimage), ref(loss), ref(total),
+                                              ref(g2d), ref(ws), ws_bytes, _stream(stream)))
 
 
 def glam_project_bwd(gauss, proj, views, flags, g2d, dgauss, stream):

@@ -247,6 +247,25 @@ glam_status glam_composite_bwd(const glam_projected* proj, const glam_bins* bins
   return glam::launch_composite_bwd(*proj, *bins, *views, bg, T_final, n_contrib, dimage, g2d, nullptr, stream);
 }
 
+size_t glam_render_fused_l1_workspace_bytes(const glam_views* views) {
+  if (!views_host_ok(views)) return 0;
+  const size_t a = glam::fused_l1_workspace(*views), b = glam::loss_workspace(*views);
+  return a > b ? a : b;
+}
+
+glam_status glam_render_fused_l1(const glam_projected* proj, const glam_bins* bins, const glam_views* views,
+                                 const float* bg, const float* target, float* image, float* T_final,
+                                 int32_t* n_contrib, float* dimage, float* loss, float* total, float* g2d,
+                                 void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!proj_ok(proj) || !bins_ok(bins) || !views_ok(views) || !ok_ptr(target) || !ok_ptr(image) ||
+      !ok_ptr(T_final) || !ok_ptr(n_contrib) || !ok_ptr(dimage) || !ok_ptr(loss) || !ok_ptr(g2d) ||
+      !ok_ptr(workspace) || (bg && !aligned16(bg)) || (total && !aligned16(total)))
+    return GLAM_ERR_INVALID_ARG;
+  if (workspace_bytes < glam_render_fused_l1_workspace_bytes(views)) return GLAM_ERR_WORKSPACE;
+  return glam::launch_fused_l1(*proj, *bins, *views, bg, target, image, T_final, n_contrib, dimage, loss, total, g2d,
+                               workspace, stream);
+}
+
 glam_status glam_project_bwd(const glam_gaussians* gauss, const glam_projected* proj, const glam_views* views,
                              uint32_t flags, const float* g2d, glam_gaussians* dgauss, hipStream_t stream) {
   if (!gauss_ok(gauss, true) || !proj_ok(proj) || !views_ok(views) || !ok_ptr(g2d) || !gauss_ok(dgauss, true) ||

@@ -52,6 +52,14 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
                                  const float* bg, const float* T_final, const int32_t* n_contrib,
                                  const float* dimage, float* g2d, float* det_part, hipStream_t s);
 
+// The forward, the L1 term of the loss and the compositing adjoint in one pass (a
+// per-pixel loss); its workspace holds one partial sum per quadrant item (and, with no
+// Gaussians, the loss kernel's partial sums).
+size_t fused_l1_workspace(const glam_views& v);
+glam_status launch_fused_l1(const glam_projected& proj, const glam_bins& bins, const glam_views& v, const float* bg,
+                            const float* target, float* image, float* T_final, int32_t* n_contrib, float* dimage,
+                            float* loss, float* total, float* g2d, void* ws, hipStream_t s);
+
 size_t loss_workspace(const glam_views& v);
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
                         float* dimage, float* loss, float* total, void* ws, hipStream_t s);

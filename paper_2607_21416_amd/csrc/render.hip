@@ -412,8 +412,9 @@ __device__ __forceinline__ void fwd_write(const Item& it, const FwdState& st, co
 // A chunk is one gathered batch: its hits stay in L for the exact pass, and the next
 // round's records are fetched while the current round is composited.
 static_assert(kChunk == 64, "a long-tile chunk is one gathered batch");
+// Returns the pixel's final state (the same in every wave).
 template <bool kStop, int kW>
-__device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
+__device__ FwdState fwd_long(const float* splat, const uint32_t* vals, uint32_t s, uint32_t e, uint32_t n_gauss,
                          const Item& it, WaveLds& L, FwdRound<kW>& R, int w, int lane, const float* bgc,
                          float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval) {
   const float px = it.x + 0.5f, py = it.y + 0.5f;
@@ -485,6 +486,7 @@ __device__ void fwd_long(const float* splat, const uint32_t* vals, uint32_t s, u
     if (__ballot(!st.done) == 0) break;  // the same decision in every wave
   }
   if (w == 0) fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
+  return st;
 }
 
 // kCount: also record per pixel the entry that stopped the walk (n_eval).
@@ -892,6 +894,149 @@ composite_bwd_kernel(
   leave_queue(q, gridDim.x * kW, lane);
 }
 
+// ---------------------------------------------------------------------------------
+// forward, L1 loss and adjoint in one pass (a per-pixel loss)
+// ---------------------------------------------------------------------------------
+
+__device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+
+// The L1 term of Eq. 3 at this lane's pixel, from its composited state: |C - target|
+// summed over the channels (returned), dL/dC = sign(C - target) / (3 W H) into dimage
+// (when given) and the adjoint's starting state (T_final, background, dL/dC, last
+// composited entry), as the loss kernel and the backward's set-up would give them.
+__device__ __forceinline__ float l1_start(const Item& it, const FwdState& st, const float* bgc, const float* target,
+                                          float* dimage, BwdState& b) {
+  b = BwdState{st.T, bgc[0], bgc[1], bgc[2], 0.f, 0.f, 0.f, st.last};
+  if (!it.inside) return 0.f;
+  const long long HW = (long long)it.W * it.H;
+  const long long p = (long long)it.y * it.W + it.x;
+  const float* tg = target + 3 * it.pix_begin;
+  const float inv_n = 1.f / (float)(3 * HW);
+  const float d0 = fmaf(st.T, bgc[0], st.C0) - tg[p];
+  const float d1 = fmaf(st.T, bgc[1], st.C1) - tg[HW + p];
+  const float d2 = fmaf(st.T, bgc[2], st.C2) - tg[2 * HW + p];
+  b.g0 = l1_sign(d0) * inv_n;
+  b.g1 = l1_sign(d1) * inv_n;
+  b.g2 = l1_sign(d2) * inv_n;
+  if (dimage) {
+    float* di = dimage + 3 * it.pix_begin;
+    di[p] = b.g0;
+    di[HW + p] = b.g1;
+    di[2 * HW + p] = b.g2;
+  }
+  return fabsf(d0) + fabsf(d1) + fabsf(d2);
+}
+
+// Exchange buffers of a long item: the forward's, then (after a barrier) the backward's.
+template <int kW>
+union FusedRound {
+  FwdRound<kW> f;
+  BwdRound<kW> b;
+};
+
+// Per quadrant item: the forward of Eq. 1 (as render_fwd_kernel), the pixels' L1 terms
+// and dL/dC, then at once the reverse walk of the adjoint (as composite_bwd_kernel) over
+// the records the forward has just gathered.  l1_part[(tile << ql) | quadrant] takes the
+// item's sum of |C - target|.
+template <int kW>
+__global__ void __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(kW == 4 ? kBwdWavesPerEU
+                                                                                      : kWideWavesPerEU)))
+fused_l1_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ vals,
+                const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
+                uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, int tl, const float* bg,
+                const float* target, float* image, float* T_final, int32_t* n_contrib, float* dimage, float* g2d,
+                float* l1_part, uint32_t capacity, uint32_t n_gauss) {
+  __shared__ WaveLds lds[kW];
+  __shared__ FusedRound<kW> round;
+  __shared__ GradStage stage[kW];
+  __shared__ uint32_t s_item;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  WaveLds& L = lds[w];
+  GradStage& G = stage[w];
+  const int off = stage_offset(lane);
+  int nst = 0;
+  const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
+  const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
+  const int ql = 2 * (tl - 3);
+  const DetCtx dc{nullptr, 0, 0, tl, ql, 0};  // floating-point atomics: no partial slots
+  __builtin_amdgcn_s_setprio(2);
+  for (uint32_t li = next_long_item(queue, &s_item); li < (n_long << ql); li = next_long_item(queue, &s_item)) {
+    const int tile = (int)min(order[li >> ql], (uint32_t)n_tiles - 1);
+    const int quad = (int)(li & ((1u << ql) - 1u));
+    const Item it = make_item(views, n_views, tile, quad, lane, tl);
+    const uint32_t e = min(ranges[2 * tile + 1], capacity);
+    const uint32_t s = min(ranges[2 * tile], e);
+    const FwdState fs =
+        fwd_long<false, kW>(splat, vals, s, e, n_gauss, it, L, round.f, w, lane, bgc, image, T_final, n_contrib,
+                            nullptr);
+    BwdState bs;
+    const float l1 = wave_sum(l1_start(it, fs, bgc, target, w == 0 ? dimage : nullptr, bs));
+    if (w == 0 && lane == 0) l1_part[((size_t)tile << ql) | (size_t)quad] = l1;
+    __syncthreads();  // every wave has read the forward's exchange: the backward's may overwrite it
+    bwd_long<false, kW>(splat, vals, s, n_gauss, it, L, round.b, w, lane, G, nst, off, bs, g2d, dc);
+  }
+  __builtin_amdgcn_s_setprio(0);
+  const uint32_t n_items = ((uint32_t)n_tiles - n_long) << ql;
+  for (uint32_t item = next_item(queue, lane, ql); item < n_items; item = next_item(queue, lane, ql)) {
+    const int tile = (int)min(order[n_long + (item >> ql)], (uint32_t)n_tiles - 1);
+    const int quad = (int)(item & ((1u << ql) - 1u));
+    const Item it = make_item(views, n_views, tile, quad, lane, tl);
+    const uint32_t e = min(ranges[2 * tile + 1], capacity);
+    const uint32_t s = min(ranges[2 * tile], e);
+    FwdState st{1.f, 0.f, 0.f, 0.f, 0, (int)(e - s), !it.inside};
+    fwd_exact<false>(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
+    fwd_write(it, st, bgc, image, T_final, n_contrib, nullptr);
+    BwdState bs;
+    const float l1 = wave_sum(l1_start(it, st, bgc, target, dimage, bs));
+    if (lane == 0) l1_part[((size_t)tile << ql) | (size_t)quad] = l1;
+    const int top = it.live ? wave_max(bs.last) : 0;
+    bwd_walk<false>(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, bs, g2d, dc);
+  }
+  stage_flush<false>(G, nst, off, lane, g2d);
+  leave_queue(queue, gridDim.x * kW, lane);
+}
+
+// View v's L1 loss from its items' sums, in double precision and a fixed order (thread
+// k adds k, k + 256, ...; then a tree); one workgroup per view, or one for all views
+// (which then also adds up the total) when they are few.
+__device__ void l1_reduce_view(const glam_view_info& vw, int v, int ql, const float* l1_part, float* loss,
+                               double* s_a) {
+  const long long i0 = vw.tile_begin << ql;
+  const long long n = (long long)(vw.tiles_x * vw.tiles_y) << ql;
+  double a = 0.0;
+  for (long long k = threadIdx.x; k < n; k += 256) a += l1_part[i0 + k];
+  s_a[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s_a[threadIdx.x] += s_a[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[v] = (float)(s_a[0] / (3.0 * (double)vw.cam.width * (double)vw.cam.height));
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) l1_reduce_kernel(const glam_view_info* views, int n_views, int ql,
+                                                        const float* l1_part, float* loss, float* total, int one) {
+  __shared__ double s_a[256];
+  if (one) {
+    for (int v = 0; v < n_views; ++v) l1_reduce_view(views[v], v, ql, l1_part, loss, s_a);
+    if (threadIdx.x == 0 && total) {
+      double acc = 0.0;
+      for (int v = 0; v < n_views; ++v) acc += (double)loss[v];
+      *total = (float)acc;
+    }
+  } else {
+    l1_reduce_view(views[blockIdx.x], blockIdx.x, ql, l1_part, loss, s_a);
+  }
+}
+
+__global__ void l1_total_kernel(const float* loss, int n, float* total) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int v = 0; v < n; ++v) acc += (double)loss[v];
+  *total = (float)acc;
+}
+
 // The reproducible backward's segmented reduction: view-Gaussian g's nine sums are its
 // partials [pair_begin[g] << ql, (pair_begin[g] + ntiles[g]) << ql) added in that order
 // (tiles row-major, then quadrants).
@@ -1041,6 +1186,51 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
   if (det && v.n_gauss > 0)
     hipLaunchKernelGGL(det_reduce_kernel, dim3((unsigned)((v.n_gauss + 255) / 256)), dim3(256), 0, s, det_part,
                        bins.pair_begin, proj.ntiles, (long long)v.n_gauss, ql, (uint32_t)bins.capacity, g2d);
+  return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
+}
+
+size_t fused_l1_workspace(const glam_views& v) {
+  const int ql = 2 * (tile_log2(v.tile_w) - 3);
+  return (size_t)((long long)v.n_tiles << ql) * sizeof(float);
+}
+
+glam_status launch_fused_l1(const glam_projected& proj, const glam_bins& bins, const glam_views& v, const float* bg,
+                            const float* target, float* image, float* T_final, int32_t* n_contrib, float* dimage,
+                            float* loss, float* total, float* g2d, void* ws, hipStream_t s) {
+  const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
+  if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
+  float* l1_part = static_cast<float*>(ws);
+  const long long n = 9 * v.n_gauss;
+  if (n > 0)
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
+                       g2d, n);
+  if (v.n_gauss == 0) {
+    // nothing to composite or differentiate: the background image and its L1 term
+    glam_status st = launch_background(v, bg, image, T_final, n_contrib, nullptr, s);
+    if (st != GLAM_OK) return st;
+    return launch_loss(v, image, target, 0.f, dimage, loss, total, ws, s);
+  }
+  const int gw = bins.tuning.bwd_group_waves > 0 ? bins.tuning.bwd_group_waves : 4;
+  const long long items = v.n_tiles << ql;
+  auto launch = [&](auto kernel, int kw, int dflt) {
+    const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : dflt;
+    hipLaunchKernelGGL(kernel, dim3(persistent_blocks(items, kw, bpc)), dim3(64 * kw), 0, s, proj.splat, bins.vals,
+                       bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, target,
+                       image, T_final, n_contrib, dimage, g2d, l1_part, (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
+  };
+  if (gw == 16)
+    launch(fused_l1_kernel<16>, 16, default_blocks<16, false>());
+  else if (gw == 8)
+    launch(fused_l1_kernel<8>, 8, default_blocks<8, false>());
+  else
+    launch(fused_l1_kernel<4>, 4, default_blocks<4, false>());
+  constexpr int kOneBlockViews = 64;
+  if (v.n <= kOneBlockViews) {
+    hipLaunchKernelGGL(l1_reduce_kernel, dim3(1), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 1);
+  } else {
+    hipLaunchKernelGGL(l1_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 0);
+    if (total) hipLaunchKernelGGL(l1_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
+  }
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 

@@ -89,13 +89,15 @@ class Pipeline:
 
     def __init__(self, scene: dict, device="cuda", capacity: int | None = None, bg=(0.0, 0.0, 0.0),
                  tile: int = TILE, tuning: dict | None = None, footprint: str = "opacity",
-                 deterministic: bool = False, intermediates: bool = False):
+                 deterministic: bool = False, intermediates: bool = False, fuse_l1: bool = True):
         """tile: binning tile edge (8, 16 or 32); tuning: the compositing schedule
         (long_log2, fwd/bwd_blocks_per_cu, fwd/bwd_group_waves; missing or 0 = default);
         footprint: "opacity" (the exact alpha >= 1/255 box) or "3sigma" (the lineage's
         tile-granular 3-sigma square); deterministic: reproducible gradients (no
         floating-point atomics in the compositing adjoint); intermediates: the backward
-        also writes the 2-D gradients d(u, v, A, B, C, opacity, rgb) to self.d2d."""
+        also writes the 2-D gradients d(u, v, A, B, C, opacity, rgb) to self.d2d;
+        fuse_l1: with a per-pixel L1 loss (no SSIM term), step() composites, takes the loss
+        and walks the compositing adjoint in one pass (glam_render_fused_l1)."""
         self.device = torch.device(device)
         dev = self.device
         self.scene = scene
@@ -141,6 +143,10 @@ class Pipeline:
         self.bg = torch.zeros(4, device=dev)
         self.bg[:3] = torch.tensor(bg, dtype=torch.float32)
         self.ws_loss = torch.empty(B.glam_loss_workspace_bytes(self.vt.views), device=dev, dtype=torch.uint8)
+        self.fuse_l1 = bool(fuse_l1) and self.ssim_weight == 0.0 and not self.deterministic and not self.intermediates
+        if self.fuse_l1:
+            self.ws_fused = torch.empty(max(256, B.glam_render_fused_l1_workspace_bytes(self.vt.views)), device=dev,
+                                        dtype=torch.uint8)
         self.status = torch.zeros(8, device=dev, dtype=torch.int32)
         self._alloc_gauss_buffers(capacity)
 
@@ -381,9 +387,23 @@ class Pipeline:
         self.compute_loss(s)
         self.generation += 1
 
+    def fused_l1(self, s=None):
+        """Forward compositing, the L1 loss and the compositing adjoint in one pass."""
+        B.glam_render_fused_l1(self.proj, self.bins, self.vt.views, self.bg, self.target, self.image, self.T_final,
+                               self.n_contrib, self.dimage, self.loss, self.loss_total, self.g2d, self.ws_fused,
+                               self.ws_fused.numel(), s or self.stream())
+
     def step(self, s=None):
-        self.forward(s)
-        self.backward(s)
+        if not self.fuse_l1 or self.n_eval is not None:
+            self.forward(s)
+            self.backward(s)
+            return
+        self.decode_project(s)
+        self.bin_sort(s)
+        self.fused_l1(s)
+        self.generation += 1
+        self.project_bwd(s)
+        self.decode_bwd(s)
 
     # ------------------------------------------------------------------------------
     def pair_count(self) -> int:
