@@ -216,6 +216,15 @@ typedef struct {
    bwd_group_waves   the same for the backward compositing grid
    bwd_blocks_per_cu the same for the backward grid (groups of 4: default and maximum
                      6; of 8: 2; of 16: 1)
+   non_persistent    1: glam_render_fwd and glam_composite_bwd / glam_render_bwd
+                     launch no persistent grid and use no work queue: one workgroup of
+                     four waves per four (tile, quadrant) items in tile order, each wave
+                     walking its quadrant's whole range (long tiles too), as the
+                     rasterisers of the 3DGS lineage launch one block per tile; the plain
+                     form the batched step is measured against.  The widths, workgroup
+                     counts and long-tile threshold then do not apply to those calls (the
+                     threshold still orders the bins).  0: the persistent queue (default).
+                     glam_render_fused_l1 always runs the persistent grid
    reserved          must be 0 */
 typedef struct {
   int32_t long_log2;
@@ -223,7 +232,8 @@ typedef struct {
   int32_t bwd_blocks_per_cu;
   int32_t fwd_group_waves;
   int32_t bwd_group_waves;
-  int32_t reserved[3];
+  int32_t non_persistent;
+  int32_t reserved[2];
 } glam_tuning;
 
 /* Sorted (tile, Gaussian) pairs, per-tile ranges and the compositing work order. */

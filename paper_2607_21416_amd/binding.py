@@ -76,10 +76,12 @@ class Projected(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("long_log2", C.c_int32), ("fwd_blocks_per_cu", C.c_int32), ("bwd_blocks_per_cu", C.c_int32),
-                ("fwd_group_waves", C.c_int32), ("bwd_group_waves", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("fwd_group_waves", C.c_int32), ("bwd_group_waves", C.c_int32), ("non_persistent", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
-SCHEDULE_KEYS = ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu", "fwd_group_waves", "bwd_group_waves")
+SCHEDULE_KEYS = ("long_log2", "fwd_blocks_per_cu", "bwd_blocks_per_cu", "fwd_group_waves", "bwd_group_waves",
+                 "non_persistent")
 
 
 def make_tuning(schedule: dict | None) -> Tuning:

@@ -25,8 +25,8 @@ inline bool group_ok(int waves, int blocks, int max4) {
 inline bool tuning_ok(const glam_tuning& t) {
   return (t.long_log2 == 0 || (t.long_log2 >= 6 && t.long_log2 <= 24)) &&
          group_ok(t.fwd_group_waves, t.fwd_blocks_per_cu, kMaxFwdBlocksPerCU) &&
-         group_ok(t.bwd_group_waves, t.bwd_blocks_per_cu, kMaxBwdBlocksPerCU) && t.reserved[0] == 0 &&
-         t.reserved[1] == 0 && t.reserved[2] == 0;
+         group_ok(t.bwd_group_waves, t.bwd_blocks_per_cu, kMaxBwdBlocksPerCU) &&
+         (t.non_persistent == 0 || t.non_persistent == 1) && t.reserved[0] == 0 && t.reserved[1] == 0;
 }
 
 // Compute units of the current device (256 if the runtime cannot say).

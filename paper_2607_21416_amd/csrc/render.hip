@@ -497,7 +497,7 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
                   const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, const int32_t* status,
                   uint32_t* queue, const glam_view_info* views, int n_views, int n_tiles, int tl,
                   const float* bg, float* image, float* T_final, int32_t* n_contrib, int32_t* n_eval,
-                  uint32_t capacity, uint32_t n_gauss) {
+                  uint32_t capacity, uint32_t n_gauss, int direct) {
   __shared__ WaveLds lds[kW];
   __shared__ FwdRound<kW> round;
   __shared__ uint32_t s_item;
@@ -506,6 +506,19 @@ render_fwd_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ 
   const float bgc[3] = {bg ? bg[0] : 0.f, bg ? bg[1] : 0.f, bg ? bg[2] : 0.f};
   const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
   const int ql = 2 * (tl - 3);  // log2 of the quadrants per tile
+  if (direct) {  // no queue: wave w of workgroup b takes item kW b + w in tile order, whole range
+    const uint32_t item = blockIdx.x * kW + w;
+    if (item < ((uint32_t)n_tiles << ql)) {
+      const int tile = (int)(item >> ql);
+      const Item it = make_item(views, n_views, tile, (int)(item & ((1u << ql) - 1u)), lane, tl);
+      const uint32_t e = min(ranges[2 * tile + 1], capacity);
+      const uint32_t s = min(ranges[2 * tile], e);
+      FwdState st{1.f, 0.f, 0.f, 0.f, 0, (int)(e - s), !it.inside};
+      fwd_exact<kCount>(splat, vals, s, s, e, n_gauss, it, L, lane, it.x + 0.5f, it.y + 0.5f, st);
+      fwd_write(it, st, bgc, image, T_final, n_contrib, n_eval);
+    }
+    return;
+  }
   // long tiles first, one quadrant per workgroup
   __builtin_amdgcn_s_setprio(2);
   for (uint32_t li = next_long_item(queue, &s_item); li < (n_long << ql); li = next_long_item(queue, &s_item)) {
@@ -852,7 +865,7 @@ composite_bwd_kernel(
     const float* __restrict__ splat, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ order, const int32_t* status, uint32_t* queue, const glam_view_info* views,
     int n_views, int n_tiles, int tl, const float* bg, const float* T_final, const int32_t* n_contrib,
-    const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss, const uint32_t* pair_begin) {
+    const float* dimage, float* g2d, uint32_t capacity, uint32_t n_gauss, const uint32_t* pair_begin, int direct) {
   __shared__ WaveLds lds[kW];
   __shared__ BwdRound<kW> round;
   __shared__ GradStage stage[kW];
@@ -866,6 +879,22 @@ composite_bwd_kernel(
   const uint32_t n_long = min((uint32_t)status[7], (uint32_t)n_tiles);
   uint32_t* q = queue + kQueueWords;
   const int ql = 2 * (tl - 3);  // log2 of the quadrants per tile
+  if (direct) {  // no queue: wave w of workgroup b takes item kW b + w in tile order, whole range
+    const uint32_t item = blockIdx.x * kW + w;
+    if (item < ((uint32_t)n_tiles << ql)) {
+      const int tile = (int)(item >> ql);
+      const int quad = (int)(item & ((1u << ql) - 1u));
+      const Item it = make_item(views, n_views, tile, quad, lane, tl);
+      const uint32_t e = min(ranges[2 * tile + 1], capacity);
+      const uint32_t s = min(ranges[2 * tile], e);
+      BwdState st = bwd_begin(it, e - s, bgc, T_final, n_contrib, dimage);
+      const int top = it.live ? wave_max(st.last) : 0;
+      const DetCtx dc{pair_begin, it.qx0 >> tl, it.qy0 >> tl, tl, ql, quad};
+      bwd_walk<kDet>(splat, vals, s, 0, top, n_gauss, it, L, lane, G, nst, off, st, g2d, dc);
+    }
+    stage_flush<kDet>(G, nst, off, lane, g2d);
+    return;
+  }
   __builtin_amdgcn_s_setprio(2);
   for (uint32_t li = next_long_item(q, &s_item); li < (n_long << ql); li = next_long_item(q, &s_item)) {
     const int tile = (int)min(order[li >> ql], (uint32_t)n_tiles - 1);
@@ -1127,13 +1156,15 @@ glam_status launch_render_fwd(const glam_projected& proj, const glam_bins& bins,
   }
   const int tl = tile_log2(v.tile_w), ql = 2 * (tl - 3);
   if (((unsigned long long)v.n_tiles << ql) >= (1ull << 32)) return GLAM_ERR_UNSUPPORTED;
-  const int gw = bins.tuning.fwd_group_waves > 0 ? bins.tuning.fwd_group_waves : 4;
+  const bool direct = bins.tuning.non_persistent != 0;
+  const int gw = direct ? 4 : (bins.tuning.fwd_group_waves > 0 ? bins.tuning.fwd_group_waves : 4);
   const long long items = v.n_tiles << ql;
   auto launch = [&](auto kernel, int kw, int dflt) {
     const int bpc = bins.tuning.fwd_blocks_per_cu > 0 ? bins.tuning.fwd_blocks_per_cu : dflt;
-    hipLaunchKernelGGL(kernel, dim3(persistent_blocks(items, kw, bpc)), dim3(64 * kw), 0, s, proj.splat, bins.vals,
-                       bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, image,
-                       T_final, n_contrib, n_eval, (uint32_t)bins.capacity, (uint32_t)v.n_gauss);
+    const unsigned grid = direct ? (unsigned)((items + kw - 1) / kw) : persistent_blocks(items, kw, bpc);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * kw), 0, s, proj.splat, bins.vals, bins.ranges, bins.order,
+                       bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, image, T_final, n_contrib, n_eval,
+                       (uint32_t)bins.capacity, (uint32_t)v.n_gauss, direct ? 1 : 0);
   };
   if (gw == 16)
     launch(n_eval ? render_fwd_kernel<true, 16> : render_fwd_kernel<false, 16>, 16, default_blocks<16, true>());
@@ -1167,13 +1198,15 @@ glam_status launch_composite_bwd(const glam_projected& proj, const glam_bins& bi
   if (n > 0)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)min((n / 4 + 255) / 256 + 1, 8LL * cu_count())), dim3(256), 0, s,
                        acc, n);
-  const int gw = bins.tuning.bwd_group_waves > 0 ? bins.tuning.bwd_group_waves : 4;
+  const bool direct = bins.tuning.non_persistent != 0;
+  const int gw = direct ? 4 : (bins.tuning.bwd_group_waves > 0 ? bins.tuning.bwd_group_waves : 4);
   const long long items = v.n_tiles << ql;
   auto launch = [&](auto kernel, int kw, int dflt) {
     const int bpc = bins.tuning.bwd_blocks_per_cu > 0 ? bins.tuning.bwd_blocks_per_cu : dflt;
-    hipLaunchKernelGGL(kernel, dim3(persistent_blocks(items, kw, bpc)), dim3(64 * kw), 0, s, proj.splat, bins.vals,
-                       bins.ranges, bins.order, bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, T_final,
-                       n_contrib, dimage, acc, (uint32_t)bins.capacity, (uint32_t)v.n_gauss, bins.pair_begin);
+    const unsigned grid = direct ? (unsigned)((items + kw - 1) / kw) : persistent_blocks(items, kw, bpc);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * kw), 0, s, proj.splat, bins.vals, bins.ranges, bins.order,
+                       bins.status, bins.queue, v.dev, v.n, (int)v.n_tiles, tl, bg, T_final, n_contrib, dimage, acc,
+                       (uint32_t)bins.capacity, (uint32_t)v.n_gauss, bins.pair_begin, direct ? 1 : 0);
   };
   if (v.n_tiles > 0 && v.n_gauss > 0) {
     if (gw == 16)

@@ -68,7 +68,7 @@ def test_schedule_out_of_range_is_rejected():
     bad_sched = [dict(long_log2=5), dict(long_log2=25), dict(fwd_blocks_per_cu=6), dict(bwd_blocks_per_cu=7),
                  dict(fwd_blocks_per_cu=-1), dict(fwd_group_waves=12), dict(bwd_group_waves=2),
                  dict(fwd_group_waves=16, fwd_blocks_per_cu=2), dict(bwd_group_waves=8, bwd_blocks_per_cu=3),
-                 dict(fwd_group_waves=-4)]
+                 dict(fwd_group_waves=-4), dict(non_persistent=2), dict(non_persistent=-1)]
     reserved = B.make_tuning(None)
     reserved.reserved[1] = 1
     for bad in [B.make_tuning(d) for d in bad_sched] + [reserved]:

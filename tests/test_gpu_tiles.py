@@ -1,10 +1,10 @@
 """The binning tile edge and the compositing schedule change the work decomposition,
 never the result: with 8x8 and 32x32 tiles (one and sixteen 8x8 compositing quadrants
 per tile) and non-default schedules (a low long-tile threshold, smaller persistent
-grids, long tiles shared by workgroups of 8 and 16 waves), the tile assignment, sort
-order and ranges match the oracle's at that tile edge bit for bit, the long tiles are
-counted and listed first, and the pixels and the 2-D gradients match the oracle
-stage-wise (same bars as the 16x16 parity tests)."""
+grids, long tiles shared by workgroups of 8 and 16 waves, no persistent grid at all),
+the tile assignment, sort order and ranges match the oracle's at that tile edge bit for
+bit, the long tiles are counted and listed first, and the pixels and the 2-D gradients
+match the oracle stage-wise (same bars as the 16x16 parity tests)."""
 import numpy as np
 import pytest
 import torch
@@ -27,10 +27,13 @@ SCHEDULES = {
               "bwd_blocks_per_cu": 2},
     # forward and backward at different widths
     "mixed": {"long_log2": 7, "fwd_group_waves": 16, "bwd_group_waves": 4},
+    # no persistent grid: one wave per (tile, quadrant) item in tile order, whole ranges
+    "direct": {"long_log2": 7, "non_persistent": 1},
 }
 CASES = ([(t, n, "narrow") for t in (8, 32) for n in SCENES] + [(16, n, "wide16") for n in SCENES]
          + [(t, "plain_dense", "wide8") for t in (8, 32)]
-         + [(16, n, "mixed") for n in ("plain_dense", "anchor_small")])
+         + [(16, n, "mixed") for n in ("plain_dense", "anchor_small")]
+         + [(t, n, "direct") for t in (8, 16, 32) for n in ("plain_dense", "anchor_small")])
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda p: f"tile{p[0]}-{p[1]}-{p[2]}")

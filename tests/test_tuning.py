@@ -34,7 +34,7 @@ def test_every_grid_candidate_is_a_valid_schedule():
     for gw, b in tuning.BWD_GRIDS:
         assert gw * b <= (24 if gw == 4 else 16)
     t = B.make_tuning(tuning.schedule(tuning.DEFAULT))
-    assert (t.fwd_group_waves, t.bwd_group_waves, list(t.reserved)) == (4, 4, [0, 0, 0])
+    assert (t.fwd_group_waves, t.bwd_group_waves, t.non_persistent, list(t.reserved)) == (4, 4, 0, [0, 0])
 
 
 def test_stored_choices_are_valid_and_used():
