@@ -125,8 +125,10 @@ __device__ __forceinline__ void load_weights(const float* pm, float* s, int t, i
   }
 }
 
+// The camera centre -R^T t (compensated: camera translations of kilometres keep every
+// digit of the anchors' directions and distances from it).
 __device__ __forceinline__ void camera_centre(const glam_camera& c, float xc[3]) {
-  for (int i = 0; i < 3; ++i) xc[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
+  for (int i = 0; i < 3; ++i) xc[i] = -dot3_add(c.R[i], c.R[3 + i], c.R[6 + i], c.t[0], c.t[1], c.t[2], 0.f);
 }
 
 // Layer 2 of MLP ml: Y^T tiles from the H^T registers (permuted K), stored to y.

@@ -60,6 +60,11 @@ glam_status launch_fused_l1(const glam_projected& proj, const glam_bins& bins, c
                             const float* target, float* image, float* T_final, int32_t* n_contrib, float* dimage,
                             float* loss, float* total, float* g2d, void* ws, hipStream_t s);
 
+// The views' L1 losses from per-(tile, quadrant) sums of |C - target| (the fused pass's):
+// l1_part[(tile << ql) | quadrant].
+glam_status launch_l1_reduce(const glam_views& v, int ql, const float* l1_part, float* loss, float* total,
+                             hipStream_t s);
+
 size_t loss_workspace(const glam_views& v);
 glam_status launch_loss(const glam_views& v, const float* image, const float* target, float w_ssim,
                         float* dimage, float* loss, float* total, void* ws, hipStream_t s);

@@ -16,7 +16,8 @@
 // subtract the leaving one).  Per-(tile, channel) sums of |x - y| and SSIM go to a
 // small workspace; a last kernel reduces each view's sums in double precision (one
 // workgroup for all views when they are few, which also adds up the step's total).
-// Nothing but the image, the target and dL/dC touches HBM.
+// Nothing but the image, the target and dL/dC touches HBM.  The per-view L1 losses of the
+// fused forward + loss + adjoint pass are reduced here too, from its per-item sums.
 #include <mutex>
 
 #include "common.hpp"
@@ -270,39 +271,50 @@ __global__ void __launch_bounds__(kThreads) loss_kernel(const glam_view_info* vi
   }
 }
 
-// View v's loss from its per-(tile, channel) sums, in double precision and a fixed
-// order (thread k adds k, k + 256, ...; then a tree).  Every thread of the workgroup
-// calls it.
+// Sums of a and b over a workgroup of 256 threads, in double precision and a fixed
+// order: each wave's lanes by a butterfly, then the four waves in order.  Every thread
+// calls it and gets both sums.  s: 8 doubles of LDS, free again when it returns.
+__device__ __forceinline__ void block_sum256(double& a, double& b, double* s) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s[threadIdx.x >> 6] = a;
+    s[4 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  a = ((s[0] + s[1]) + s[2]) + s[3];
+  b = ((s[4] + s[5]) + s[6]) + s[7];
+  __syncthreads();
+}
+
+// View v's loss from its per-(tile, channel) sums, by the workgroup (thread t adds the
+// sums t, t + 256, ...).  Every thread calls it.
 __device__ void reduce_view(const glam_view_info& vw, int v, int max_t32, const float* partial, float w_ssim,
-                            float* loss, double* s_a, double* s_b) {
+                            float* loss, double* s) {
   const int n = 3 * ((vw.cam.width + kT - 1) / kT) * ((vw.cam.height + kT - 1) / kT);
   const float* pv = partial + 2 * 3 * (long long)v * max_t32;
   double a = 0.0, b = 0.0;
+#pragma unroll 4
   for (int k = threadIdx.x; k < n; k += 256) {
     a += pv[2 * k];
     b += pv[2 * k + 1];
   }
-  s_a[threadIdx.x] = a;
-  s_b[threadIdx.x] = b;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) { s_a[threadIdx.x] += s_a[threadIdx.x + off]; s_b[threadIdx.x] += s_b[threadIdx.x + off]; }
-    __syncthreads();
-  }
+  block_sum256(a, b, s);
   if (threadIdx.x == 0) {
     const double cnt = 3.0 * (double)vw.cam.width * (double)vw.cam.height;
-    double L = s_a[0] / cnt;
-    if (w_ssim != 0.f) L += (double)w_ssim * (1.0 - s_b[0] / cnt);
+    double L = a / cnt;
+    if (w_ssim != 0.f) L += (double)w_ssim * (1.0 - b / cnt);
     loss[v] = (float)L;
   }
-  __syncthreads();  // s_a and s_b are reused
 }
 
 // One workgroup per view.
 __global__ void __launch_bounds__(256) loss_reduce_kernel(const glam_view_info* views, int max_t32,
                                                           const float* partial, float w_ssim, float* loss) {
-  __shared__ double s_a[256], s_b[256];
-  reduce_view(views[blockIdx.x], blockIdx.x, max_t32, partial, w_ssim, loss, s_a, s_b);
+  __shared__ double s[8];
+  reduce_view(views[blockIdx.x], blockIdx.x, max_t32, partial, w_ssim, loss, s);
 }
 
 // A few views: one workgroup reduces them in view order and then adds their losses
@@ -311,8 +323,8 @@ constexpr int kOneBlockViews = 64;
 __global__ void __launch_bounds__(256) loss_reduce_total_kernel(const glam_view_info* views, int n_views,
                                                                 int max_t32, const float* partial, float w_ssim,
                                                                 float* loss, float* total) {
-  __shared__ double s_a[256], s_b[256];
-  for (int v = 0; v < n_views; ++v) reduce_view(views[v], v, max_t32, partial, w_ssim, loss, s_a, s_b);
+  __shared__ double s[8];
+  for (int v = 0; v < n_views; ++v) reduce_view(views[v], v, max_t32, partial, w_ssim, loss, s);
   if (threadIdx.x == 0 && total) {
     double acc = 0.0;
     for (int v = 0; v < n_views; ++v) acc += (double)loss[v];
@@ -326,6 +338,35 @@ __global__ void loss_total_kernel(const float* loss, int n, float* total) {
   double acc = 0.0;
   for (int v = 0; v < n; ++v) acc += (double)loss[v];
   *total = (float)acc;
+}
+
+// View v's L1 loss from the fused pass's per-item sums, by the workgroup (thread t adds
+// the sums t, t + 256, ...); one workgroup per view, or one for all views (which then
+// also adds up the total) when they are few.  Every thread calls it.
+__device__ void l1_reduce_view(const glam_view_info& vw, int v, int ql, const float* l1_part, float* loss, double* s) {
+  const long long i0 = vw.tile_begin << ql;
+  const long long n = (long long)(vw.tiles_x * vw.tiles_y) << ql;
+  double a = 0.0;
+#pragma unroll 4
+  for (long long k = threadIdx.x; k < n; k += 256) a += l1_part[i0 + k];
+  double unused = 0.0;
+  block_sum256(a, unused, s);
+  if (threadIdx.x == 0) loss[v] = (float)(a / (3.0 * (double)vw.cam.width * (double)vw.cam.height));
+}
+
+__global__ void __launch_bounds__(256) l1_reduce_kernel(const glam_view_info* views, int n_views, int ql,
+                                                        const float* l1_part, float* loss, float* total, int one) {
+  __shared__ double s[8];
+  if (one) {
+    for (int v = 0; v < n_views; ++v) l1_reduce_view(views[v], v, ql, l1_part, loss, s);
+    if (threadIdx.x == 0 && total) {
+      double acc = 0.0;
+      for (int v = 0; v < n_views; ++v) acc += (double)loss[v];
+      *total = (float)acc;
+    }
+  } else {
+    l1_reduce_view(views[blockIdx.x], blockIdx.x, ql, l1_part, loss, s);
+  }
 }
 
 int max_tiles32(const glam_views& v) {
@@ -343,6 +384,17 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 size_t loss_workspace(const glam_views& v) { return align256(8ull * 3 * (size_t)max_tiles32(v) * (size_t)v.n); }
+
+glam_status launch_l1_reduce(const glam_views& v, int ql, const float* l1_part, float* loss, float* total,
+                             hipStream_t s) {
+  if (v.n <= kOneBlockViews) {
+    hipLaunchKernelGGL(l1_reduce_kernel, dim3(1), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 1);
+  } else {
+    hipLaunchKernelGGL(l1_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 0);
+    if (total) hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
+  }
+  return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
+}
 
 glam_status launch_loss_noalloc(const glam_views& v, const float* image, const float* target, float w_ssim,
                                 float* dimage, float* loss, float* total, hipStream_t s) {

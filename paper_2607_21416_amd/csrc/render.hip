@@ -1025,47 +1025,6 @@ fused_l1_kernel(const float* __restrict__ splat, const uint32_t* __restrict__ va
   leave_queue(queue, gridDim.x * kW, lane);
 }
 
-// View v's L1 loss from its items' sums, in double precision and a fixed order (thread
-// k adds k, k + 256, ...; then a tree); one workgroup per view, or one for all views
-// (which then also adds up the total) when they are few.
-__device__ void l1_reduce_view(const glam_view_info& vw, int v, int ql, const float* l1_part, float* loss,
-                               double* s_a) {
-  const long long i0 = vw.tile_begin << ql;
-  const long long n = (long long)(vw.tiles_x * vw.tiles_y) << ql;
-  double a = 0.0;
-  for (long long k = threadIdx.x; k < n; k += 256) a += l1_part[i0 + k];
-  s_a[threadIdx.x] = a;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s_a[threadIdx.x] += s_a[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) loss[v] = (float)(s_a[0] / (3.0 * (double)vw.cam.width * (double)vw.cam.height));
-  __syncthreads();
-}
-
-__global__ void __launch_bounds__(256) l1_reduce_kernel(const glam_view_info* views, int n_views, int ql,
-                                                        const float* l1_part, float* loss, float* total, int one) {
-  __shared__ double s_a[256];
-  if (one) {
-    for (int v = 0; v < n_views; ++v) l1_reduce_view(views[v], v, ql, l1_part, loss, s_a);
-    if (threadIdx.x == 0 && total) {
-      double acc = 0.0;
-      for (int v = 0; v < n_views; ++v) acc += (double)loss[v];
-      *total = (float)acc;
-    }
-  } else {
-    l1_reduce_view(views[blockIdx.x], blockIdx.x, ql, l1_part, loss, s_a);
-  }
-}
-
-__global__ void l1_total_kernel(const float* loss, int n, float* total) {
-  if (threadIdx.x != 0) return;
-  double acc = 0.0;
-  for (int v = 0; v < n; ++v) acc += (double)loss[v];
-  *total = (float)acc;
-}
-
 // The reproducible backward's segmented reduction: view-Gaussian g's nine sums are its
 // partials [pair_begin[g] << ql, (pair_begin[g] + ntiles[g]) << ql) added in that order
 // (tiles row-major, then quadrants).
@@ -1257,14 +1216,8 @@ glam_status launch_fused_l1(const glam_projected& proj, const glam_bins& bins, c
     launch(fused_l1_kernel<8>, 8, default_blocks<8, false>());
   else
     launch(fused_l1_kernel<4>, 4, default_blocks<4, false>());
-  constexpr int kOneBlockViews = 64;
-  if (v.n <= kOneBlockViews) {
-    hipLaunchKernelGGL(l1_reduce_kernel, dim3(1), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 1);
-  } else {
-    hipLaunchKernelGGL(l1_reduce_kernel, dim3(v.n), dim3(256), 0, s, v.dev, v.n, ql, l1_part, loss, total, 0);
-    if (total) hipLaunchKernelGGL(l1_total_kernel, dim3(1), dim3(64), 0, s, loss, v.n, total);
-  }
-  return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
+  if (hipGetLastError() != hipSuccess) return GLAM_ERR_HIP;
+  return launch_l1_reduce(v, ql, l1_part, loss, total, s);
 }
 
 }  // namespace glam
