@@ -168,14 +168,16 @@ __device__ __forceinline__ void wave_sync() {
 
 // Work split of the decode and its adjoint over partitions: partition slot k (a run of
 // consecutive views of one partition) owns workgroups [first[k], first[k+1]) of a 1-D
-// grid, shared in proportion to the partitions' anchor counts; leader[k] is the first
-// of the slot's views.
+// grid, shared in proportion to the partitions' anchor counts; its views are
+// [leader[k], leader[k+1]).  The adjoint's workgroups of a slot differentiate one MLP
+// each: the first (split[k] & 0xffff) the opacity MLP, the next (split[k] >> 16) the
+// colour MLP, the rest the covariance MLP.
 constexpr int kMaxBwdParts = 256;
 struct BwdGrid {
   int n_parts;
   int first[kMaxBwdParts + 1];
-  int leader[kMaxBwdParts];
-  int n_views_of[kMaxBwdParts];
+  int leader[kMaxBwdParts + 1];
+  int split[kMaxBwdParts];
 };
 
 // A workgroup stages its partition's weights once; each wave then takes 16-anchor
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
   int m = 0;
   while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
   const int b_local = (int)blockIdx.x - grid.first[m], nb = grid.first[m + 1] - grid.first[m];
-  const int v0 = grid.leader[m], v1 = v0 + grid.n_views_of[m];
+  const int v0 = grid.leader[m], v1 = grid.leader[m + 1];
   const glam_view_info lead = views[v0];
   const int A = lead.anchor_count;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
@@ -317,11 +319,12 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
 // adjoint
 // ---------------------------------------------------------------------------------
 
-// The adjoint is split by MLP: a workgroup differentiates one of the three MLPs (for
-// the covariance MLP, the largest, two workgroups share the work), so a wave holds
-// only that MLP's weight-gradient accumulators in registers and stages only its
-// weights in LDS.  Everything the three MLPs share (the input rows Z and the ReLU
-// pattern of their own hidden layer) is cheap to rebuild.
+// The adjoint is split by MLP: a workgroup differentiates one of the three MLPs, so a
+// wave holds only that MLP's weight-gradient accumulators in registers and stages only
+// its weights in LDS.  Everything the three MLPs share (the input rows Z and the ReLU
+// pattern of their own hidden layer) is cheap to rebuild.  The workgroups of each MLP
+// are counted so that the three finish together (the covariance MLP's chunks cost about
+// twice the others').
 constexpr int kBwdWaves = 4;
 constexpr int kBwdBlocksPerCU = 2;  // workgroups resident per CU (registers: two waves per SIMD)
 
@@ -378,17 +381,12 @@ __device__ __forceinline__ f4 mfma4(const float4& a, const float4& b, f4 acc) {
 template <int F, int K, int ML>
 __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__ mlp,
                                const glam_view_info* views, int sigmoid_op, const glam_gaussians& dg,
-                               const BwdGrid& grid, int half, float* doffs, float* dfeat_part, float* dls_part,
-                               float* partial, float* smem) {
+                               const BwdGrid& grid, int m, int b_local, int nb, float* doffs, float* dfeat_part,
+                               float* dls_part, float* partial, float* smem) {
   using C = MCfg<F, K, ML>;
   constexpr MlpOff O = mlp_offsets(F, K);
   constexpr int OUT = C::OUT;
-  int m = 0;
-  while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
-  const int nb0 = grid.first[m + 1] - grid.first[m];
-  const int b_local = ML == 2 ? 2 * ((int)blockIdx.x - grid.first[m]) + half : (int)blockIdx.x - grid.first[m];
-  const int nb = ML == 2 ? 2 * nb0 : nb0;
-  const int v0 = grid.leader[m], v1 = v0 + grid.n_views_of[m];
+  const int v0 = grid.leader[m], v1 = grid.leader[m + 1];
   const glam_view_info lead = views[v0];
   const int A = lead.anchor_count;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lg = l >> 4;
@@ -799,8 +797,8 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
     }
     __syncthreads();
   }
-  // partial rows: plane 0 holds every MLP's share, plane 1 the second covariance half
-  float* dst = partial + ((size_t)(ML == 2 ? half : 0) * gridDim.x + blockIdx.x) * O.total + O.w1[ML];
+  // one partial row per workgroup, of which it fills its MLP's parameters
+  float* dst = partial + (size_t)blockIdx.x * O.total + O.w1[ML];
   for (int i = t; i < C::PM; i += 64 * kBwdWaves) dst[i] = red[i];
 }
 
@@ -813,34 +811,35 @@ decode_bwd_kernel(glam_anchors an, const float* __restrict__ mlp,
                                                                     float* partial) {
   extern __shared__ float smem[];
   const size_t AF = (size_t)an.A * F;
-  switch (blockIdx.y) {
-    case 0:
-      decode_bwd_mlp<F, K, 0>(an, mlp, views, sigmoid_op, dg, grid, 0, doffs, dfeat_part, dls_part, partial, smem);
-      break;
-    case 1:
-      decode_bwd_mlp<F, K, 1>(an, mlp, views, sigmoid_op, dg, grid, 0, doffs, dfeat_part + AF, dls_part, partial,
-                              smem);
-      break;
-    default:
-      decode_bwd_mlp<F, K, 2>(an, mlp, views, sigmoid_op, dg, grid, (int)blockIdx.y - 2, doffs, dfeat_part + 2 * AF,
-                              dls_part + an.A, partial, smem);
-      break;
-  }
+  int m = 0;
+  while (m + 1 < grid.n_parts && grid.first[m + 1] <= (int)blockIdx.x) ++m;
+  const int b = (int)blockIdx.x - grid.first[m], nb = grid.first[m + 1] - grid.first[m];
+  const int n0 = grid.split[m] & 0xffff, n1 = grid.split[m] >> 16;
+  if (b < n0)
+    decode_bwd_mlp<F, K, 0>(an, mlp, views, sigmoid_op, dg, grid, m, b, n0, doffs, dfeat_part, dls_part, partial,
+                            smem);
+  else if (b < n0 + n1)
+    decode_bwd_mlp<F, K, 1>(an, mlp, views, sigmoid_op, dg, grid, m, b - n0, n1, doffs, dfeat_part + AF, dls_part,
+                            partial, smem);
+  else
+    decode_bwd_mlp<F, K, 2>(an, mlp, views, sigmoid_op, dg, grid, m, b - n0 - n1, nb - n0 - n1, doffs,
+                            dfeat_part + 2 * AF, dls_part + an.A, partial, smem);
 }
 
-// dmlp[m] = sum of partition m's workgroup partials (plane 1 only holds covariance
-// parameters).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
-__device__ void mlp_grad_reduce(const float* partial, const BwdGrid& grid, int P, int cov0, int n_units,
-                                float* dmlp, int bx, int slot) {
+// dmlp[m] = sum of the partials of partition m's workgroups that differentiate the MLP
+// owning each parameter (its colour MLP's parameters start at col0, its covariance
+// MLP's at cov0).  Block: 16 parameters x 16 partial groups, contiguous 64-byte reads.
+__device__ void mlp_grad_reduce(const float* partial, const BwdGrid& grid, int P, int col0, int cov0, float* dmlp,
+                                int bx, int slot) {
   __shared__ float s[16][17];
   const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
   const int i = bx * 16 + c;  // slot: index into grid (partitions with views)
   float acc = 0.f;
   if (i < P) {
-    for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16) acc += partial[(size_t)b * P + i];
-    if (i >= cov0)
-      for (int b = grid.first[slot] + r; b < grid.first[slot + 1]; b += 16)
-        acc += partial[((size_t)n_units + b) * P + i];
+    const int n0 = grid.split[slot] & 0xffff, n1 = grid.split[slot] >> 16;
+    const int lo = grid.first[slot] + (i < col0 ? 0 : (i < cov0 ? n0 : n0 + n1));
+    const int hi = i < col0 ? grid.first[slot] + n0 : (i < cov0 ? grid.first[slot] + n0 + n1 : grid.first[slot + 1]);
+    for (int b = lo + r; b < hi; b += 16) acc += partial[(size_t)b * P + i];
   }
   s[r][c] = acc;
   __syncthreads();
@@ -885,13 +884,13 @@ __device__ void anchor_grad_combine(const float* dfeat_part, const float* dls_pa
 // weight-gradient partials (16 parameters x one partition each), the rest combine the
 // anchor gradients.
 template <int F, int K>
-__global__ void __launch_bounds__(256) decode_bwd_finish_kernel(const float* partial, BwdGrid grid, int P, int cov0,
-                                                                int n_units, float* dmlp, int red_x, int n_red,
+__global__ void __launch_bounds__(256) decode_bwd_finish_kernel(const float* partial, BwdGrid grid, int P, int col0,
+                                                                int cov0, float* dmlp, int red_x, int n_red,
                                                                 const float* dfeat_part, const float* dls_part, int A,
                                                                 Covered cov, float* dfeat, float* doffs, float* dls) {
   const int b = (int)blockIdx.x;
   if (b < n_red)
-    mlp_grad_reduce(partial, grid, P, cov0, n_units, dmlp, b % red_x, b / red_x);
+    mlp_grad_reduce(partial, grid, P, col0, cov0, dmlp, b % red_x, b / red_x);
   else
     anchor_grad_combine<F, K>(dfeat_part, dls_part, A, cov, dfeat, doffs, dls, (long long)(b - n_red));
 }
@@ -922,34 +921,73 @@ int max_anchors(const glam_views& v) {
   return mx;
 }
 
-// Units (one workgroup for each of the opacity and colour MLPs, two for the covariance
-// MLP) in total: enough for kBwdBlocksPerCU resident workgroups on every CU, shared by
-// the partitions in proportion to their anchor counts (at least one each, never more
-// than their 16-anchor chunks / waves).
-int total_bwd_units() { return cu_count() * kBwdBlocksPerCU / 4; }
+// Workgroups of the adjoint in total: kBwdBlocksPerCU resident on every CU.
+int total_bwd_blocks() { return cu_count() * kBwdBlocksPerCU; }
 
-bool bwd_grid(const glam_views& v, BwdGrid& g, int budget) {
+// Relative cost of one 16-anchor chunk in the adjoint of each MLP (measured per wave at
+// K = 10: the opacity MLP also carries the gradients of the offsets and of the
+// Gaussians' means, the covariance MLP has seven outputs per Gaussian).
+constexpr double kMlpChunkCost[3] = {1.1, 1.0, 1.9};
+
+// Workgroups needed for MLP j so that no wave's chunks cost more than T.
+long long mlp_blocks_for(long long n_chunks, double T, int j) {
+  const long long per = (long long)(T / kMlpChunkCost[j] + 1e-9);  // chunks one wave may take
+  if (per < 1) return 1ll << 40;
+  const long long waves = (n_chunks + per - 1) / per;
+  return (waves + kBwdWaves - 1) / kBwdWaves;
+}
+
+// The split of a slot's budget of workgroups over the three MLPs that minimises the
+// cost of the longest wave (chunks are dealt to a MLP's waves round-robin, so its
+// waves take ceil(chunks / waves) at most): the least makespan T whose workgroup
+// counts fit the budget, by bisection (the counts only grow as T shrinks).
+void split_mlps(long long n_chunks, int budget, int c[3]) {
+  c[0] = c[1] = c[2] = 1;
+  if (n_chunks <= 0 || budget <= 3) return;
+  auto fits = [&](double T) {
+    long long s = 0;
+    for (int j = 0; j < 3; ++j) s += mlp_blocks_for(n_chunks, T, j);
+    return s <= budget;
+  };
+  double lo = 0.0, hi = kMlpChunkCost[2] * (double)n_chunks;  // one wave each always fits
+  for (int it = 0; it < 64; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (fits(mid) ? hi : lo) = mid;
+  }
+  for (int j = 0; j < 3; ++j) c[j] = (int)mlp_blocks_for(n_chunks, hi, j);
+}
+
+// The slots (runs of consecutive views of one partition) and their workgroups.  The
+// forward gives each slot its share of `budget` (never more workgroups than 4-wave
+// groups of 16-anchor chunks); the adjoint (adjoint = true) splits each slot's share
+// over the three MLPs with split_mlps.
+bool bwd_grid(const glam_views& v, BwdGrid& g, int budget, bool adjoint) {
   g.n_parts = 0;
   long long total_anchors = 0;
   for (int i = 0; i < v.n; ++i) {
     const glam_view_info& vi = v.host[i];
-    if (i > 0 && v.host[i - 1].cam.partition == vi.cam.partition) {
-      ++g.n_views_of[g.n_parts - 1];
-      continue;
-    }
+    if (i > 0 && v.host[i - 1].cam.partition == vi.cam.partition) continue;
     if (g.n_parts == kMaxBwdParts) return false;
     g.leader[g.n_parts] = i;
-    g.n_views_of[g.n_parts] = 1;
     ++g.n_parts;
     total_anchors += vi.anchor_count;
   }
+  g.leader[g.n_parts] = v.n;
   int b = 0;
   for (int k = 0; k < g.n_parts; ++k) {
     const int A = v.host[g.leader[k]].anchor_count;
-    const int cap = (A + 16 * kBwdWaves - 1) / (16 * kBwdWaves);
     int nb = total_anchors > 0 ? (int)((double)budget * A / (double)total_anchors + 0.5) : 1;
-    nb = nb < 1 ? 1 : (nb > cap ? (cap < 1 ? 1 : cap) : nb);
     g.first[k] = b;
+    if (adjoint) {
+      int c[3];
+      split_mlps((A + 15) / 16, nb < 3 ? 3 : nb, c);
+      g.split[k] = c[0] | (c[1] << 16);
+      nb = c[0] + c[1] + c[2];
+    } else {
+      const int cap = (A + 16 * kBwdWaves - 1) / (16 * kBwdWaves);
+      nb = nb < 1 ? 1 : (nb > cap ? (cap < 1 ? 1 : cap) : nb);
+      g.split[k] = 0;
+    }
     b += nb;
   }
   g.first[g.n_parts] = b;
@@ -961,7 +999,7 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
                        const glam_gaussians& out, const glam_projected* proj, hipStream_t s) {
   if (max_anchors(v) == 0 || v.n == 0) return GLAM_OK;
   BwdGrid g;
-  if (!bwd_grid(v, g, 2 * cu_count())) return GLAM_ERR_UNSUPPORTED;  // two workgroups per CU
+  if (!bwd_grid(v, g, 2 * cu_count(), false)) return GLAM_ERR_UNSUPPORTED;  // two workgroups per CU
   const size_t sm = fwd_smem<F, K>();
   if (!set_smem_limit((const void*)decode_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
   const glam_projected none{};
@@ -970,18 +1008,18 @@ glam_status run_decode(const glam_anchors& a, const float* mlp, const glam_views
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
-// Workspace of the adjoint: weight-gradient partials (two planes of units x P),
+// Workspace of the adjoint: weight-gradient partials (one row of P per workgroup),
 // per-MLP anchor feature gradients [3][A][F] and log-scale parts [2][A].
 struct BwdWs {
   size_t partial, dfeat, dls, total;
 };
 
-BwdWs bwd_ws(int F, int K, int A, int units) {
+BwdWs bwd_ws(int F, int K, int A, int blocks) {
   const MlpOff o = mlp_offsets(F, K);
   BwdWs w;
-  const size_t u = units > 0 ? (size_t)units : 1;
+  const size_t u = blocks > 0 ? (size_t)blocks : 1;
   w.partial = 0;
-  w.dfeat = (2 * u * (size_t)o.total * 4 + 255) & ~size_t(255);
+  w.dfeat = (u * (size_t)o.total * 4 + 255) & ~size_t(255);
   w.dls = w.dfeat + ((3 * (size_t)A * F * 4 + 255) & ~size_t(255));
   w.total = w.dls + ((2 * (size_t)A * 4 + 255) & ~size_t(255));
   return w;
@@ -993,9 +1031,9 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
                            hipStream_t s) {
   constexpr int P = mlp_offsets(F, K).total;
   BwdGrid g;
-  if (!bwd_grid(v, g, total_bwd_units())) return GLAM_ERR_UNSUPPORTED;
-  const int units = g.first[g.n_parts];
-  const BwdWs W = bwd_ws(F, K, a.A, units);
+  if (!bwd_grid(v, g, total_bwd_blocks(), true)) return GLAM_ERR_UNSUPPORTED;
+  const int blocks = g.first[g.n_parts];
+  const BwdWs W = bwd_ws(F, K, a.A, blocks);
   char* w = static_cast<char*>(ws);
   float* partial = reinterpret_cast<float*>(w + W.partial);
   float* dfp = reinterpret_cast<float*>(w + W.dfeat);
@@ -1006,16 +1044,16 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
     const long long nm = (long long)n_parts * P;
     hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, dmlp, nm);
   }
-  if (units > 0) {
+  if (blocks > 0) {
     const size_t sm = sizeof(float) * bwd_smem_words<F, K>();
     if (!set_smem_limit((const void*)decode_bwd_kernel<F, K>, sm, s)) return GLAM_ERR_HIP;
-    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(units, 4), dim3(64 * kBwdWaves), sm, s, a, mlp, v.dev,
+    hipLaunchKernelGGL((decode_bwd_kernel<F, K>), dim3(blocks), dim3(64 * kBwdWaves), sm, s, a, mlp, v.dev,
                        sig ? 1 : 0, dg, g, doffs, dfp, dlp, partial);
   }
   // the reduction writes dmlp[partition of slot k]: pass partitions in place of leaders
   BwdGrid r = g;
   for (int k = 0; k < g.n_parts; ++k) r.leader[k] = v.host[g.leader[k]].cam.partition;
-  const int red_x = (P + 15) / 16, n_red = units > 0 ? red_x * g.n_parts : 0;
+  const int red_x = (P + 15) / 16, n_red = blocks > 0 ? red_x * g.n_parts : 0;
   Covered cov;
   cov.n = 0;
   for (int k = 0; k < g.n_parts; ++k) {
@@ -1034,7 +1072,8 @@ glam_status run_decode_bwd(const glam_anchors& a, const float* mlp, int n_parts,
   const long long n_comb = a.A > 0 ? (AF + 255) / 256 : 0;
   if (n_red + n_comb > 0)
     hipLaunchKernelGGL((decode_bwd_finish_kernel<F, K>), dim3((unsigned)(n_red + n_comb)), dim3(256), 0, s, partial, r,
-                       P, mlp_offsets(F, K).w1[2], units, dmlp, red_x, n_red, dfp, dlp, a.A, cov, dfeat, doffs, dls);
+                       P, mlp_offsets(F, K).w1[1], mlp_offsets(F, K).w1[2], dmlp, red_x, n_red, dfp, dlp, a.A, cov,
+                       dfeat, doffs, dls);
   return hipGetLastError() == hipSuccess ? GLAM_OK : GLAM_ERR_HIP;
 }
 
@@ -1053,7 +1092,7 @@ glam_status launch_decode(const glam_anchors& a, const float* mlp, const glam_vi
 size_t decode_bwd_workspace(const glam_anchors& a, const glam_views& v, int n_parts) {
   (void)n_parts;
   BwdGrid g;
-  if (!bwd_grid(v, g, total_bwd_units())) return 0;
+  if (!bwd_grid(v, g, total_bwd_blocks(), true)) return 0;
   return bwd_ws(a.F, a.K, a.A, g.first[g.n_parts]).total;
 }
 
