@@ -101,27 +101,63 @@ struct Cfg {
   static_assert(NIN % 4 == 0, "F + 4 must be a multiple of 4");
 };
 
-// Copies one packed MLP set into the padded LDS layout.
+// LDS word of packed weight i (the padded layout of lds_offsets), from compile-time
+// constants only: no table is indexed at run time.
 template <int F, int K>
-__device__ __forceinline__ void load_weights(const float* pm, float* s, int t, int nthreads) {
-  using C = Cfg<F, K>;
+__host__ __device__ constexpr int lds_word(int i) {
+  constexpr int nin = F + 4, w1s = F + 5, w2s = kHid + 1;
   constexpr MlpOff O = mlp_offsets(F, K);
   constexpr LdsOff L = lds_offsets(F, K);
-  for (int i = t; i < C::P; i += nthreads) {
+  const bool m0 = i < O.w1[1], m1 = !m0 && i < O.w1[2];
+  const int base = m0 ? O.w1[0] : (m1 ? O.w1[1] : O.w1[2]);
+  const int lbase = m0 ? L.w1[0] : (m1 ? L.w1[1] : L.w1[2]);
+  const int out = m0 ? K : (m1 ? 3 * K : 7 * K);
+  const int j = i - base;
+  if (j < kHid * nin) return lbase + (j / nin) * w1s + j % nin;  // W1 row j / nin
+  const int j1 = j - kHid * nin;
+  if (j1 < kHid) return lbase + kHid * w1s + j1;  // b1
+  const int j2 = j1 - kHid;
+  if (j2 < out * kHid) return lbase + kHid * w1s + kHid + (j2 / kHid) * w2s + j2 % kHid;  // W2 row j2 / kHid
+  return lbase + kHid * w1s + kHid + out * w2s + (j2 - out * kHid);  // b2
+}
+
+// lds_word against the offset tables, for every packed weight (checked when compiling).
+template <int F, int K>
+constexpr bool lds_word_matches() {
+  constexpr MlpOff O = mlp_offsets(F, K);
+  constexpr LdsOff L = lds_offsets(F, K);
+  for (int i = 0; i < O.total; ++i) {
     const int l = i < O.w1[1] ? 0 : (i < O.w1[2] ? 1 : 2);
     const int j = i - O.w1[l];
     int dst;
-    if (j < kHid * C::NIN) {
-      dst = L.w1[l] + (j / C::NIN) * C::W1S + j % C::NIN;
-    } else if (j < kHid * C::NIN + kHid) {
-      dst = L.b1[l] + (j - kHid * C::NIN);
-    } else if (j < O.b2[l] - O.w1[l]) {
-      const int jj = j - kHid * C::NIN - kHid;
-      dst = L.w2[l] + (jj / kHid) * C::W2S + jj % kHid;
-    } else {
-      dst = L.b2[l] + (j - (O.b2[l] - O.w1[l]));
-    }
-    s[dst] = pm[i];
+    if (j < kHid * (F + 4)) dst = L.w1[l] + (j / (F + 4)) * (F + 5) + j % (F + 4);
+    else if (j < kHid * (F + 4) + kHid) dst = L.b1[l] + (j - kHid * (F + 4));
+    else if (j < O.b2[l] - O.w1[l]) dst = L.w2[l] + ((j - kHid * (F + 4) - kHid) / kHid) * (kHid + 1) +
+                                            (j - kHid * (F + 4) - kHid) % kHid;
+    else dst = L.b2[l] + (j - (O.b2[l] - O.w1[l]));
+    if (dst != lds_word<F, K>(i)) return false;
+  }
+  return true;
+}
+
+// Copies one packed MLP set into the padded LDS layout, by a workgroup of 256 threads:
+// every thread's loads are issued before its first store, so the copy costs about one
+// memory latency instead of one per word.
+template <int F, int K>
+__device__ __forceinline__ void load_weights(const float* pm, float* s, int t) {
+  using C = Cfg<F, K>;
+  static_assert(lds_word_matches<F, K>(), "LDS layout of the weights");
+  constexpr int kN = (C::P + 255) / 256;
+  float v[kN];
+#pragma unroll
+  for (int n = 0; n < kN; ++n) {
+    const int i = t + 256 * n;
+    v[n] = i < C::P ? pm[i] : 0.f;
+  }
+#pragma unroll
+  for (int n = 0; n < kN; ++n) {
+    const int i = t + 256 * n;
+    if (i < C::P) s[lds_word<F, K>(i)] = v[n];
   }
 }
 
@@ -202,7 +238,7 @@ __global__ void __launch_bounds__(256) decode_kernel(glam_anchors an, const floa
   float* s_p = smem;
   float* s_z = s_p + C::PA + w * 16 * C::ZS;
   float* s_y = smem + C::PA + 4 * 16 * C::ZS + w * 16 * C::YS;
-  load_weights<F, K>(mlp + (size_t)lead.cam.partition * C::P, s_p, t, 256);
+  load_weights<F, K>(mlp + (size_t)lead.cam.partition * C::P, s_p, t);
   __syncthreads();
   const long long n = out.n;
   const size_t GK = (size_t)an.A * K;
@@ -395,10 +431,59 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   float* s_yt = s_z + 16 * C::ZS;
   float* s_ht = s_yt + C::OUTP * C::YTS;
   float* s_ds = s_ht + kHid * C::HTS;
+  const long long n = dg.n;
+  const size_t GK = (size_t)an.A * K;
+  const int n_chunks = (A + 15) / 16;
+  // view-independent inputs of a chunk (features, anchor positions and, per Gaussian of
+  // this lane, the log-scale and offsets), loaded into registers one chunk ahead so
+  // that their latency hides behind the current chunk's work
+  struct ChunkIn {
+    float fv[16 * F / 64];
+    float apos[3];
+    float ls[3];
+    float off[3][3];
+  };
+  auto load_chunk = [&](int chunk, ChunkIn& in) {
+    const int a0 = chunk * 16;
+#pragma unroll
+    for (int k = 0; k < 16 * F / 64; ++k) {
+      const int idx = l + 64 * k, ai = idx / F, a = a0 + ai;
+      in.fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      in.apos[i] = l < 16 && a0 + l < A ? an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int gi = l + 64 * q, ai = gi / K, a = a0 + ai;
+      const bool ok = ML != 1 && gi < 16 * K && a < A;
+      const int ga = lead.anchor_begin + (ok ? a : 0);
+      in.ls[q] = ok ? an.log_scale[ga] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) in.off[q][i] = ok && ML == 0 ? an.offs[i * GK + (size_t)ga * K + gi % K] : 0.f;
+    }
+  };
+  // (wide features: no prefetch, the registers would spill); the first chunk's loads
+  // are issued before the weights are staged, so that the two latencies overlap
+  constexpr bool kPrefetch = F <= 32;
+  const int chunk_step = nb * kBwdWaves;
+  ChunkIn nxt;
+  if (kPrefetch && b_local * kBwdWaves + w < n_chunks) load_chunk(b_local * kBwdWaves + w, nxt);
   {  // this MLP's weights: W1, b1, W2 (rows padded to 36), b2, and the transposes W2^T, W1^T
     const float* pm = mlp + (size_t)lead.cam.partition * O.total + O.w1[ML];
-    for (int i = t; i < C::PM; i += 64 * kBwdWaves) {
-      const float v = pm[i];
+    // every load in flight before the first store (one memory latency, not one per word)
+    constexpr int kN = (C::PM + 64 * kBwdWaves - 1) / (64 * kBwdWaves);
+    float vw[kN];
+#pragma unroll
+    for (int n = 0; n < kN; ++n) {
+      const int i = t + 64 * kBwdWaves * n;
+      vw[n] = i < C::PM ? pm[i] : 0.f;
+    }
+#pragma unroll
+    for (int n = 0; n < kN; ++n) {
+      const int i = t + 64 * kBwdWaves * n;
+      if (i >= C::PM) break;
+      const float v = vw[n];
       if (i < kHid * C::NINP) {
         const int h = i / C::NINP, c = i % C::NINP;
         s_p[C::LW1 + h * C::W1S + C::col_in(c)] = v;
@@ -438,44 +523,7 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
   for (int i = 0; i < 2 * C::NC1; ++i) dW1[i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < (OUT + 63) / 64; ++i) db2[i] = 0.f;
-  const long long n = dg.n;
-  const size_t GK = (size_t)an.A * K;
-  const int n_chunks = (A + 15) / 16;
   // each wave walks its chunks independently: no workgroup barrier until the end
-  // view-independent inputs of a chunk (features, anchor positions and, per Gaussian of
-  // this lane, the log-scale and offsets), loaded into registers one chunk ahead so
-  // that their latency hides behind the current chunk's work
-  struct ChunkIn {
-    float fv[16 * F / 64];
-    float apos[3];
-    float ls[3];
-    float off[3][3];
-  };
-  auto load_chunk = [&](int chunk, ChunkIn& in) {
-    const int a0 = chunk * 16;
-#pragma unroll
-    for (int k = 0; k < 16 * F / 64; ++k) {
-      const int idx = l + 64 * k, ai = idx / F, a = a0 + ai;
-      in.fv[k] = a < A ? an.feat[(size_t)(lead.anchor_begin + a) * F + idx % F] : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      in.apos[i] = l < 16 && a0 + l < A ? an.pos[(size_t)i * an.A + lead.anchor_begin + a0 + l] : 0.f;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int gi = l + 64 * q, ai = gi / K, a = a0 + ai;
-      const bool ok = ML != 1 && gi < 16 * K && a < A;
-      const int ga = lead.anchor_begin + (ok ? a : 0);
-      in.ls[q] = ok ? an.log_scale[ga] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) in.off[q][i] = ok && ML == 0 ? an.offs[i * GK + (size_t)ga * K + gi % K] : 0.f;
-    }
-  };
-  // (wide features: no prefetch, the registers would spill)
-  constexpr bool kPrefetch = F <= 32;
-  const int chunk_step = nb * kBwdWaves;
-  ChunkIn nxt;
-  if (kPrefetch && b_local * kBwdWaves + w < n_chunks) load_chunk(b_local * kBwdWaves + w, nxt);
   for (int chunk = b_local * kBwdWaves + w; chunk < n_chunks; chunk += chunk_step) {
     const int a0 = chunk * 16;
     ChunkIn cur;
