@@ -6,9 +6,12 @@
 //                      the number of 8-bit radix passes
 //  3. duplicate        per view-Gaussian: its pairs, key = tile << dbits | depth key,
 //                      value = view-Gaussian index, in index order (row-major tiles)
-//  4. radix passes     LSD, reduce-then-scan (no inter-block waiting): upsweep digit
-//                      histogram per block, per-digit scan across blocks, downsweep
-//                      scatter with a stable in-block rank from wave ballots
+//  4. radix passes     LSD, reduce-then-scan (no inter-block waiting), two launches
+//                      per pass: upsweep digit histogram per block, also added into
+//                      per-group totals (groups of 32 blocks); downsweep: each block's
+//                      digit offsets from the group totals and the counts of the
+//                      blocks before it in its group, then the scatter with a stable
+//                      in-block rank from wave ballots
 //  5. ranges           [start, end) of every tile (cleared by the plan kernel)
 //  6. order            the compositing work order, longest ranges first (one workgroup
 //                      when the tiles are few)
@@ -33,6 +36,8 @@ constexpr long long kSmallSortCapacity = 1ll << 20;
 int sort_items(long long capacity) { return capacity <= kSmallSortCapacity ? 4 : 8; }
 constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
 constexpr int kMaxSortBlocks = 4096;
+constexpr int kMaxPasses = 8;            // tile bits (at most 33) + depth bits (at most 31)
+constexpr int kGroup = 32;               // radix blocks per group total
 constexpr uint32_t kDepthBase = 0x3E4CCCCDu;  // bit pattern of 0.2f: every visible depth is above it
 
 struct Plan {
@@ -49,8 +54,8 @@ struct Plan {
 constexpr int kLptBuckets = 32;
 
 struct Layout {
-  size_t partial_sum, partial_max, plan, keys_alt, vals_alt, hist, digit_total, lpt, total;
-  int n_scan_blocks, n_sort_blocks, sort_items;
+  size_t partial_sum, partial_max, plan, keys_alt, vals_alt, count, gsum, lpt, total;
+  int n_scan_blocks, n_sort_blocks, sort_items, n_groups;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -63,14 +68,15 @@ Layout layout(long long n_gauss, long long capacity) {
   const long long sort_tile = (long long)kSortThreads * L.sort_items;
   long long tiles = (capacity + sort_tile - 1) / sort_tile;
   L.n_sort_blocks = (int)(tiles < 1 ? 1 : (tiles > kMaxSortBlocks ? kMaxSortBlocks : tiles));
+  L.n_groups = (L.n_sort_blocks + kGroup - 1) / kGroup;
   size_t o = 0;
   L.partial_sum = o; o = align256(o + 4ull * L.n_scan_blocks);
   L.partial_max = o; o = align256(o + 4ull * L.n_scan_blocks);
   L.plan = o; o = align256(o + sizeof(Plan));
   L.keys_alt = o; o = align256(o + 8ull * (size_t)capacity);
   L.vals_alt = o; o = align256(o + 4ull * (size_t)capacity);
-  L.hist = o; o = align256(o + 4ull * kRadix * L.n_sort_blocks);
-  L.digit_total = o; o = align256(o + 4ull * kRadix);
+  L.count = o; o = align256(o + 4ull * kRadix * L.n_sort_blocks);
+  L.gsum = o; o = align256(o + 4ull * kRadix * L.n_groups * kMaxPasses);
   L.lpt = o; o = align256(o + 4ull * 2 * kLptBuckets);
   L.total = o;
   return L;
@@ -192,13 +198,16 @@ __global__ void __launch_bounds__(1024) scan_plan_kernel(uint32_t* psum, const u
 // view-Gaussians: it stages their tile boxes in LDS with the exclusive prefix of their
 // pair counts (the first-level scan redone in LDS), then each thread emits pairs
 // k = t, t + 256, ... of the workgroup's range, finding its Gaussian by binary search
-// in the prefix, so every pair costs the same and the stores are coalesced.
+// in the prefix, so every pair costs the same and the stores are coalesced.  Also
+// clears the radix passes' group totals (gsum, gsum_words words).
 __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* ntiles, const float* splat,
                                                                  long long n, const glam_view_info* views,
                                                                  int n_views, int tl, const uint32_t* psum,
                                                                  const Plan* plan, uint64_t* keys_out,
                                                                  uint32_t* vals_out, uint64_t* keys_alt,
-                                                                 uint32_t* vals_alt, uint32_t* pair_begin) {
+                                                                 uint32_t* vals_alt, uint32_t* pair_begin,
+                                                                 uint32_t* gsum, int gsum_words) {
+  for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < gsum_words; i += gridDim.x * kScanThreads) gsum[i] = 0u;
   __shared__ uint32_t s_pre[kScanBlock];   // count, then exclusive prefix within the workgroup
   __shared__ uint32_t s_tile[kScanBlock];  // global tile of the box's top-left corner
   __shared__ uint32_t s_dim[kScanBlock];   // box width in tiles | view tiles_x << 16
@@ -306,10 +315,13 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return peers;
 }
 
+// Digit counts of this block's keys: count[block][digit], and added into the group
+// totals gsum[pass][block / kGroup][digit].
 template <int kSortItems>
-__global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan* plan, int pass, int n_blocks,
+__global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan* plan, int pass, int n_groups,
                                                                      const uint64_t* keys_out,
-                                                                     const uint64_t* keys_alt, uint32_t* hist) {
+                                                                     const uint64_t* keys_alt, uint32_t* count,
+                                                                     uint32_t* gsum) {
   const Plan pl = *plan;
   if ((uint32_t)pass >= pl.npasses || blockIdx.x >= pl.active_blocks) return;
   __shared__ uint32_t s_cnt[kRadix];
@@ -336,35 +348,14 @@ __global__ void __launch_bounds__(kSortThreads) radix_upsweep_kernel(const Plan*
     }
   }
   __syncthreads();
-  hist[threadIdx.x * n_blocks + blockIdx.x] = s_cnt[threadIdx.x];
-}
-
-// One block per digit: exclusive scan of that digit's counts across blocks.
-__global__ void __launch_bounds__(256) radix_scan_kernel(const Plan* plan, int pass, int n_blocks, uint32_t* hist,
-                                                         uint32_t* digit_total) {
-  const Plan pl = *plan;
-  if ((uint32_t)pass >= pl.npasses) return;
-  __shared__ uint32_t s[256];
-  uint32_t* row = hist + blockIdx.x * n_blocks;
-  const int nb = (int)min((uint32_t)n_blocks, pl.active_blocks);
-  const int per = (nb + 255) / 256;
-  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
-  uint32_t local = 0;
-  for (int i = lo; i < hi; ++i) local += row[i];
-  const uint32_t incl = block_scan256(local, s);
-  uint32_t run = incl - local;
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t v = row[i];
-    row[i] = run;
-    run += v;
-  }
-  if (threadIdx.x == 255) digit_total[blockIdx.x] = incl;
+  const uint32_t c = s_cnt[threadIdx.x];
+  count[(size_t)blockIdx.x * kRadix + threadIdx.x] = c;
+  if (c) atomicAdd(&gsum[((size_t)pass * n_groups + blockIdx.x / kGroup) * kRadix + threadIdx.x], c);
 }
 
 template <int kSortItems>
-__global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Plan* plan, int pass, int n_blocks,
-                                                                       const uint32_t* hist,
-                                                                       const uint32_t* digit_total,
+__global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Plan* plan, int pass, int n_groups,
+                                                                       const uint32_t* count, const uint32_t* gsum,
                                                                        uint64_t* keys_out, uint32_t* vals_out,
                                                                        uint64_t* keys_alt, uint32_t* vals_alt) {
   const Plan pl = *plan;
@@ -387,9 +378,37 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep_kernel(const Pla
   uint32_t* vdst = src_is_out ? vals_alt : vals_out;
   const int shift = pass * kRadixBits;
   const int t = threadIdx.x, w = t >> 6;
-  // global base of each digit = exclusive scan of the digit totals
-  const uint32_t tot = digit_total[t];
-  s_run[t] = block_scan256(tot, s_scan) - tot + hist[t * n_blocks + blockIdx.x];
+  // where digit t of this block goes: the keys of smaller digits (exclusive scan of the
+  // digit totals), then digit t's keys in the groups before this block's and in the
+  // blocks before it in its group; every load in flight before the first sum
+  const int grp = (int)blockIdx.x / kGroup, b0 = grp * kGroup;
+  const int ng = (int)((pl.active_blocks + kGroup - 1) / kGroup);
+  const uint32_t* gs = gsum + (size_t)pass * n_groups * kRadix + t;
+  uint32_t tot = 0, before = 0;
+  {
+    uint32_t vg[kGroup], vb[kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      vg[k] = k < ng ? gs[(size_t)k * kRadix] : 0u;
+      vb[k] = b0 + k < (int)blockIdx.x ? count[(size_t)(b0 + k) * kRadix + t] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      tot += vg[k];
+      before += (k < grp ? vg[k] : 0u) + vb[k];
+    }
+  }
+  for (int g0 = kGroup; g0 < ng; g0 += kGroup) {  // more than kGroup groups
+    uint32_t vg[kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) vg[k] = g0 + k < ng ? gs[(size_t)(g0 + k) * kRadix] : 0u;
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      tot += vg[k];
+      before += g0 + k < grp ? vg[k] : 0u;
+    }
+  }
+  s_run[t] = block_scan256(tot, s_scan) - tot + before;
   __syncthreads();
   const uint32_t t0 = blockIdx.x * pl.tiles_per_block;
   const uint32_t t1 = min(pl.n_sort_tiles, t0 + pl.tiles_per_block);
@@ -562,9 +581,13 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
   Plan* plan = reinterpret_cast<Plan*>(w + L.plan);
   uint64_t* keys_alt = reinterpret_cast<uint64_t*>(w + L.keys_alt);
   uint32_t* vals_alt = reinterpret_cast<uint32_t*>(w + L.vals_alt);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
-  uint32_t* dtot = reinterpret_cast<uint32_t*>(w + L.digit_total);
+  uint32_t* count = reinterpret_cast<uint32_t*>(w + L.count);
+  uint32_t* gsum = reinterpret_cast<uint32_t*>(w + L.gsum);
   const long long n = v.n_gauss;
+  // host bound on the passes: tile bits are known, depth keys take at most 31 bits
+  const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
+  const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;
+  if (max_passes > kMaxPasses) return GLAM_ERR_UNSUPPORTED;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.depth,
                      n, psum, pmax);
   uint32_t* lpt = reinterpret_cast<uint32_t*>(w + L.lpt);
@@ -573,24 +596,20 @@ glam_status launch_bin_sort(const glam_projected& proj, const glam_views& v, con
                      plan, bins.status, bins.ranges, lpt);
   hipLaunchKernelGGL(duplicate_kernel, dim3(L.n_scan_blocks), dim3(kScanThreads), 0, s, proj.ntiles, proj.splat,
                      n, v.dev, v.n, tile_log2(v.tile_w), psum, plan, bins.keys, bins.vals, keys_alt, vals_alt,
-                     bins.pair_begin);
-  // host bound on the passes: tile bits are known, depth keys take at most 31 bits
-  const int tbits = v.n_tiles > 1 ? bit_length((uint64_t)(v.n_tiles - 1)) : 0;
-  const int max_passes = (tbits + 31 + kRadixBits - 1) / kRadixBits;
+                     bins.pair_begin, gsum, max_passes * L.n_groups * kRadix);
   for (int p = 0; p < max_passes; ++p) {
     if (L.sort_items == 4)
       hipLaunchKernelGGL(radix_upsweep_kernel<4>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                         L.n_sort_blocks, bins.keys, keys_alt, hist);
+                         L.n_groups, bins.keys, keys_alt, count, gsum);
     else
       hipLaunchKernelGGL(radix_upsweep_kernel<8>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                         L.n_sort_blocks, bins.keys, keys_alt, hist);
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, plan, p, L.n_sort_blocks, hist, dtot);
+                         L.n_groups, bins.keys, keys_alt, count, gsum);
     if (L.sort_items == 4)
       hipLaunchKernelGGL(radix_downsweep_kernel<4>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                         L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
+                         L.n_groups, count, gsum, bins.keys, bins.vals, keys_alt, vals_alt);
     else
       hipLaunchKernelGGL(radix_downsweep_kernel<8>, dim3(L.n_sort_blocks), dim3(kSortThreads), 0, s, plan, p,
-                         L.n_sort_blocks, hist, dtot, bins.keys, bins.vals, keys_alt, vals_alt);
+                         L.n_groups, count, gsum, bins.keys, bins.vals, keys_alt, vals_alt);
   }
   if (bins.capacity > 0)
     hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)((bins.capacity + 255) / 256)), dim3(256), 0, s, plan,
