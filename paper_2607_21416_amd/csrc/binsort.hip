@@ -217,18 +217,16 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
   const Plan pl = *plan;
   const int t = threadIdx.x;
   const long long base = (long long)blockIdx.x * kScanBlock;
+  const uint32_t gbase = psum[blockIdx.x];  // this block's first pair (the plan kernel's prefix)
   if (t == 0) s_view0 = find_view(views, n_views, base, [](const glam_view_info& v) { return v.g_begin; });
+  // tile counts and boxes side by side (a box is only used where its count is positive)
   int32_t cnt[kScanItems];
   float4 rec[kScanItems];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const long long g = base + i * kScanThreads + t;
     cnt[i] = g < n ? ntiles[g] : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    const long long g = base + i * kScanThreads + t;
-    rec[i] = cnt[i] > 0 ? reinterpret_cast<const float4*>(splat + g * kSplatWords)[2] : make_float4(0.f, 0.f, 0.f, 0.f);
+    rec[i] = g < n ? reinterpret_cast<const float4*>(splat + g * kSplatWords)[2] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
   const int v0 = s_view0;
@@ -268,16 +266,14 @@ __global__ void __launch_bounds__(kScanThreads) duplicate_kernel(const int32_t* 
   for (int i = 0; i < kScanItems; ++i) s_pre[t * kScanItems + i] = before + local[i];
   __syncthreads();
   if (pair_begin) {  // each view-Gaussian's first pair, in the same order as the emission below
-    const uint32_t gb = psum[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
       const long long g = base + i * kScanThreads + t;
-      if (g < n) pair_begin[g] = gb + s_pre[i * kScanThreads + t];
+      if (g < n) pair_begin[g] = gbase + s_pre[i * kScanThreads + t];
     }
   }
   uint64_t* kout = (pl.npasses & 1u) ? keys_alt : keys_out;
   uint32_t* vout = (pl.npasses & 1u) ? vals_alt : vals_out;
-  const uint32_t gbase = psum[blockIdx.x];
   for (uint32_t k = t; k < total; k += kScanThreads) {
     // last entry whose prefix is <= k (zero-count entries share the next one's prefix)
     int lo = 0, hi = kScanBlock - 1;

@@ -99,26 +99,35 @@ __global__ void __launch_bounds__(kThreads) loss_kernel(const glam_view_info* vi
     // 1. inputs of the 52x52 region
     float* sx = sA;
     float* sy = sA + kI * kIS;
-    // all loads in flight before the first LDS store
+    // all loads in flight before the first LDS store; element k = t + kThreads n is
+    // (row, column) (k / kI, k % kI), stepped from n to n + 1 without a division, and
+    // every lane loads (pixel 0 where the element is outside the image, then zero)
     constexpr int kLoads = (kI * kI + kThreads - 1) / kThreads;
+    constexpr int kStepR = kThreads / kI, kStepJ = kThreads % kI;
     float vx[kLoads], vy[kLoads];
+    int rr[kLoads], cc[kLoads];
+    {
+      int r = t / kI, j = t % kI;
 #pragma unroll
-    for (int n = 0; n < kLoads; ++n) {
-      const int k = t + kThreads * n;
-      const int r = k / kI, j = k % kI;
-      const int gx = x0 - 2 * kR + j, gy = y0 - 2 * kR + r;
-      const bool in = k < kI * kI && gx >= 0 && gx < W && gy >= 0 && gy < H;
-      const long long o = in ? (long long)gy * W + gx : 0;
-      vx[n] = in ? xp[o] : 0.f;
-      vy[n] = in ? yp[o] : 0.f;
+      for (int n = 0; n < kLoads; ++n) {
+        rr[n] = r;
+        cc[n] = j;
+        const int gx = x0 - 2 * kR + j, gy = y0 - 2 * kR + r;
+        const bool in = r < kI && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+        const unsigned o = in ? (unsigned)(gy * W + gx) : 0u;  // < W H < 2^30 (edges below 2^15)
+        const float a = xp[o], b = yp[o];
+        vx[n] = in ? a : 0.f;
+        vy[n] = in ? b : 0.f;
+        j += kStepJ;
+        r += kStepR;
+        if (j >= kI) { j -= kI; ++r; }
+      }
     }
 #pragma unroll
     for (int n = 0; n < kLoads; ++n) {
-      const int k = t + kThreads * n;
-      if (k < kI * kI) {
-        const int r = k / kI, j = k % kI;
-        sx[r * kIS + j] = vx[n];
-        sy[r * kIS + j] = vy[n];
+      if (rr[n] < kI) {
+        sx[rr[n] * kIS + cc[n]] = vx[n];
+        sy[rr[n] * kIS + cc[n]] = vy[n];
       }
     }
     __syncthreads();
