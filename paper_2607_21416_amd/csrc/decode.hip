@@ -808,46 +808,47 @@ __device__ void decode_bwd_mlp(const glam_anchors& an, const float* __restrict__
       }
     wave_sync();
   }
-  // workgroup reduction of this MLP's weight gradients into the packed layout
+  // workgroup reduction of this MLP's weight gradients into the packed layout: each wave
+  // stores its share (one value per parameter) in a slice of LDS of its own, then every
+  // parameter is summed over the slices from zero in wave order, so the sums are
+  // reproducible
+  static_assert(kBwdWaves * C::PM <= C::SMEM, "reduction slices fit the workgroup's LDS");
   __syncthreads();
-  float* red = s_p;  // packed offsets relative to this MLP's first parameter
-  for (int i = t; i < C::PM; i += 64 * kBwdWaves) red[i] = 0.f;
-  __syncthreads();
+  float* red = smem + w * C::PM;  // packed offsets relative to this MLP's first parameter
   constexpr int RW2 = kHid * C::NINP + kHid, RB2 = RW2 + OUT * kHid, RB1 = kHid * C::NINP;
-  // the waves add their shares one after another (every address takes one add per wave),
-  // so the sums are formed in wave order and the gradients are reproducible
-  for (int ww = 0; ww < kBwdWaves; ++ww) {
-    if (w == ww) {
 #pragma unroll
-      for (int ot = 0; ot < C::OT; ++ot)
+  for (int ot = 0; ot < C::OT; ++ot)
 #pragma unroll
-        for (int ht = 0; ht < 2; ++ht)
+    for (int ht = 0; ht < 2; ++ht)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int o = ot * 16 + 4 * lg + r;
-            if (o < OUT) red[RW2 + o * kHid + ht * 16 + li] += dW2[ot * 2 + ht][r];
-          }
-#pragma unroll
-      for (int i = 0; i < (OUT + 63) / 64; ++i) {
-        const int o = l + 64 * i;
-        if (o < OUT) red[RB2 + o] += db2[i];
+      for (int r = 0; r < 4; ++r) {
+        const int o = ot * 16 + 4 * lg + r;
+        if (o < OUT) red[RW2 + o * kHid + ht * 16 + li] = dW2[ot * 2 + ht][r];
       }
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int ct = 0; ct < C::NC1; ++ct)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int h = mt * 16 + 4 * lg + r, col = C::col_packed(ct * 16 + li);
-            if (col >= 0 && col < C::NINP) red[h * C::NINP + col] += dW1[mt * C::NC1 + ct][r];
-          }
-      if (l < kHid) red[RB1 + l] += db1;
-    }
-    __syncthreads();
+  for (int i = 0; i < (OUT + 63) / 64; ++i) {
+    const int o = l + 64 * i;
+    if (o < OUT) red[RB2 + o] = db2[i];
   }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < C::NC1; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h = mt * 16 + 4 * lg + r, col = C::col_packed(ct * 16 + li);
+        if (col >= 0 && col < C::NINP) red[h * C::NINP + col] = dW1[mt * C::NC1 + ct][r];
+      }
+  if (l < kHid) red[RB1 + l] = db1;
+  __syncthreads();
   // one partial row per workgroup, of which it fills its MLP's parameters
   float* dst = partial + (size_t)blockIdx.x * O.total + O.w1[ML];
-  for (int i = t; i < C::PM; i += 64 * kBwdWaves) dst[i] = red[i];
+  for (int i = t; i < C::PM; i += 64 * kBwdWaves) {
+    float acc = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < kBwdWaves; ++ww) acc += smem[ww * C::PM + i];
+    dst[i] = acc;
+  }
 }
 
 template <int F, int K>
