@@ -888,7 +888,16 @@ __device__ void mlp_grad_reduce(const float* partial, const BwdGrid& grid, int P
     const int n0 = grid.split[slot] & 0xffff, n1 = grid.split[slot] >> 16;
     const int lo = grid.first[slot] + (i < col0 ? 0 : (i < cov0 ? n0 : n0 + n1));
     const int hi = i < col0 ? grid.first[slot] + n0 : (i < cov0 ? grid.first[slot] + n0 + n1 : grid.first[slot + 1]);
-    for (int b = lo + r; b < hi; b += 16) acc += partial[(size_t)b * P + i];
+    // rows lo + r, lo + r + 16, ... in order, eight loads in flight at a time
+    constexpr int kBatch = 8;
+    for (int b = lo + r; b < hi; b += 16 * kBatch) {
+      float v[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) v[k] = b + 16 * k < hi ? partial[(size_t)(b + 16 * k) * P + i] : 0.f;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k)
+        if (b + 16 * k < hi) acc += v[k];
+    }
   }
   s[r][c] = acc;
   __syncthreads();
