@@ -1,8 +1,9 @@
 """Config 5, the largest single-GPU workload: the 2 km path, 64 partitions (log-uniform
 30k-300k Gaussians, own MLP sets) x 8 views at three resolutions (1226x370, 1280x384,
 1280x960) in one batch: 512 views, 62M view-Gaussians, 371 Mpx, about 90M pairs, in the
-launch configuration the benchmark runs it (16x16 tiles, default schedule; the benchmark
-replays the same launches from a graph).
+launch configuration the benchmark runs it (the tuner's stored choice for this workload:
+tile edge and compositing schedule, printed by the fixture; the benchmark replays the
+same launches from a graph).
 
 The outputs are too many for the oracle to recompute whole, so it checks a sample of
 views, one by one, from partitions along the whole path and at every resolution: the
@@ -19,6 +20,7 @@ import oracle
 import synth
 from gpu_util import (AMB_STAGE, check_anchor_grads, check_dgauss, check_pixels, gpu_splats, grad_close, stage_render,
                       view_image, view_pixels, view_slices)
+from paper_2607_21416_amd import tuning
 from paper_2607_21416_amd.pipeline import Pipeline
 from test_gpu_parity import g2d_gradients
 
@@ -63,7 +65,11 @@ def view_host(pipe, sl):
 def c5():
     print("config 5: generating", flush=True)
     scene = synth.config("C5")
-    pipe = Pipeline(scene, device="cuda")
+    choice = tuning.autotune(scene, device="cuda")  # the stored choice: nothing is measured
+    assert choice["source"] == "stored"
+    tile = choice["tile"]
+    print(f"config 5 at tile {tile}, schedule {tuning.schedule(choice)}", flush=True)
+    pipe = Pipeline(scene, device="cuda", tile=tile, tuning=tuning.schedule(choice))
     pipe.fit_capacity()
     pipe.status.zero_()
     print(f"config 5: {pipe.vt.n} views, {pipe.vt.n_gauss} view-Gaussians, capacity {pipe.capacity}", flush=True)
@@ -73,36 +79,36 @@ def c5():
     sls = view_slices(pipe)
     assert len(sls) == 512 and {(sls[v]["W"], sls[v]["H"]) for v in SAMPLE} >= {(1226, 370), (1280, 384), (1280, 960)}
     assert len({scene["cams"][v]["partition"] for v in SAMPLE}) == len(SAMPLE)
-    return scene, pipe, sls, {v: view_host(pipe, sls[v]) for v in SAMPLE}
+    return scene, pipe, sls, {v: view_host(pipe, sls[v]) for v in SAMPLE}, (tile, tile)
 
 
 def test_sampled_views_binning_and_forward(c5):
-    scene, pipe, sls, hv = c5
+    scene, pipe, sls, hv, tile = c5
     for v in SAMPLE:
         h, sl = hv[v]
         cam = scene["cams"][v]
         n = sl["g1"]
-        prect, nt = oracle.rect_f32(h["uv"][0], h["uv"][1], h["ext"][0], h["ext"][1], sl["W"], sl["H"])
+        prect, nt = oracle.rect_f32(h["uv"][0], h["uv"][1], h["ext"][0], h["ext"][1], sl["W"], sl["H"], tile)
         assert np.array_equal(nt, h["ntiles"]), f"view {v}"
-        ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), [0, n], [cam])
+        ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), [0, n], [cam], tile)
         assert h["P"] == ref["P"] > 0, f"view {v}"
         assert np.array_equal(h["vals"], ref["vals"]), f"view {v}"
         assert np.array_equal(h["tile_ids"], ref["tiles"].astype(np.int64)), f"view {v}"
         assert np.array_equal(h["ranges"], ref["ranges"]), f"view {v}"
         pr, gs = gpu_splats(h, sl)
-        r = stage_render(pr, gs, h["vals"], h["ranges"], cam)
+        r = stage_render(pr, gs, h["vals"], h["ranges"], cam, tile=tile)
         check_pixels(view_image(h, sl), view_pixels(h, sl, "T_final"), view_pixels(h, sl, "n_contrib"), r,
                      f"config 5 view {v}")
 
 
 def test_sampled_views_backward(c5):
-    scene, pipe, sls, hv = c5
+    scene, pipe, sls, hv, tile = c5
     dims = {}
     flat = torch.zeros(3 * int(pipe.vt.n_pix), dtype=torch.float32, device="cuda")
     for v in SAMPLE:
         h, sl = hv[v]
         pr, gs = gpu_splats(h, sl)
-        r = stage_render(pr, gs, h["vals"], h["ranges"], scene["cams"][v])
+        r = stage_render(pr, gs, h["vals"], h["ranges"], scene["cams"][v], tile=tile)
         _, _, _, d = oracle.loss(view_image(h, sl).astype(np.float64), scene["targets"][v], scene["ssim_weight"])
         d[:, (r["amb"] & (AMB_STAGE | oracle.AMB_CLAMP)) != 0] = 0.0
         dims[v] = d
@@ -121,7 +127,7 @@ def test_sampled_views_backward(c5):
         dg = {k: _slice_g(t, g0, g1, int(pipe.vt.n_gauss)).cpu().numpy() for k, t in pipe.dg.items()}
         dgs[v] = dg
         pr, gs = gpu_splats(h, sl)
-        g2d = oracle.render_bwd(pr, gs, h["vals"], h["ranges"], scene["cams"][v], dims[v])
+        g2d = oracle.render_bwd(pr, gs, h["vals"], h["ranges"], scene["cams"][v], dims[v], tile=tile)
         got = g2d_gradients(g2d_gpu, h["conic"])
         for k, nm in enumerate(("u", "v", "A", "B", "C", "opacity", "r", "g", "b")):
             grad_close(got[k], g2d[k], name=f"config 5 view {v} d{nm}")
