@@ -79,7 +79,10 @@ def test_sort_bit_exact(bench_case):
     assert np.array_equal(nt, h["ntiles"])
     gb = [sl["g0"] for sl in sls] + [sls[-1]["g1"]]
     ref = oracle.bin_sort(prect, nt, h["depth"].astype(np.float64), gb, scene["cams"], (tile, tile))
-    assert h["P"] == ref["P"] > 5 * 10 ** 5 * len(sls)
+    # every visible view-Gaussian has a pair, and the views are the full-size ones (about
+    # 0.14M of each view's 0.5M Gaussians visible; 0.59M pairs per view at 16x16 tiles,
+    # 0.31M at 32x32)
+    assert h["P"] == ref["P"] >= int((nt > 0).sum()) > 10 ** 5 * len(sls)
     assert np.array_equal(h["vals"], ref["vals"])
     assert np.array_equal((h["keys"] >> np.uint64(h["dbits"])).astype(np.int64), ref["tiles"].astype(np.int64))
     assert np.array_equal(h["ranges"], ref["ranges"])
