@@ -45,9 +45,10 @@ def test_stored_choices_are_valid_and_used():
         s = tuning.schedule(c)
         assert (s["fwd_group_waves"], s["fwd_blocks_per_cu"]) in tuning.FWD_GRIDS
         assert (s["bwd_group_waves"], s["bwd_blocks_per_cu"]) in tuning.BWD_GRIDS
-    # the benchmark workloads have a stored choice, returned without measuring (no GPU here)
-    for name in ("C3", "C4"):
-        scene = synth.config(name)
+    # the benchmark workloads have a stored choice, returned without measuring (no GPU here):
+    # config 3's view 0 alone (the headline), config 3's four views, configs 4 and 5
+    scenes = [synth.one_view(synth.config("C3"), 0)] + [synth.config(name) for name in ("C3", "C4", "C5")]
+    for scene in scenes:
         assert tuning.workload_key(scene) in stored
         got = tuning.autotune(scene, device="cpu")
         assert got["source"] in ("stored", "cache") and got["tile"] == stored[tuning.workload_key(scene)]["tile"]
